@@ -1,0 +1,108 @@
+"""Planted mistakes in the oracle must fail at least one pin.
+
+Each case monkeypatches one plausible error into the oracle (transposed
+operand, dropped term, wrong sign, wrong index) and re-runs a pin from
+test_oracle_pins; the pin must now fail.  Runs on the CPU only.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fcgle_oracle as O
+import tests.test_oracle_pins as pins
+
+
+def _fails(fn, *args):
+    try:
+        fn(*args)
+    except AssertionError:
+        return True
+    return False
+
+
+def test_transposed_eigenvectors_are_caught(monkeypatch):
+    orig = O.apply_f
+
+    def bad(kind, theta, V, Qs, lams, params):
+        Vhat = O.tucker(V, Qs)  # Q instead of Q^T
+        return O.tucker(O.f_grid(kind, theta, lams, params) * Vhat, [Q.T for Q in Qs])
+
+    monkeypatch.setattr(O, "apply_f", bad)
+    assert _fails(pins.test_apply_f_matches_brute_force, (7, 9), "exp")
+    monkeypatch.setattr(O, "apply_f", orig)
+
+
+def test_dropped_gamma_term_is_caught(monkeypatch):
+    def bad(t, U, params, source=None):
+        _, _, gamma, kappa, zeta = params
+        out = -(kappa + 1j * zeta) * (np.abs(U) ** 2) * U
+        if source is not None:
+            out = out + source(t, U.shape)
+        return out
+
+    monkeypatch.setattr(O, "g_nonlin", bad)
+    assert _fails(pins.test_manufactured_solution_solves_the_semidiscrete_ode)
+
+
+def test_wrong_sign_of_D_is_caught(monkeypatch):
+    def bad(alpha, n, h, fd_order=2):
+        g = O.fd2_weights(alpha, n)
+        import scipy.linalg as sla
+        return (h ** -alpha) * sla.toeplitz(g)
+
+    monkeypatch.setattr(O, "diff_matrix", bad)
+    assert _fails(pins.test_D_symmetric_toeplitz_negative_definite, 1.5)
+
+
+def test_recurrence_index_slip_is_caught(monkeypatch):
+    def bad(alpha, n):
+        g = np.empty(n)
+        g[0] = math.gamma(alpha + 1) / math.gamma(alpha / 2 + 1) ** 2
+        for k in range(1, n):
+            g[k] = (1.0 - (alpha + 1) / (alpha / 2 + k + 1)) * g[k - 1]
+        return g
+
+    monkeypatch.setattr(O, "fd2_weights", bad)
+    assert _fails(pins.test_fd2_recurrence_matches_gamma_definition, 1.5)
+
+
+def test_phi_series_off_by_one_is_caught(monkeypatch):
+    def bad(l, z):
+        z = np.asarray(z, dtype=np.complex128)
+        if l == 0:
+            return np.exp(z)
+        acc = np.zeros_like(z)
+        for k in range(39, -1, -1):
+            acc = acc * z + 1.0 / math.factorial(k + l - 1)
+        return acc
+
+    monkeypatch.setattr(O, "phi", bad)
+    assert _fails(pins.test_phi_matches_high_precision_definition, 1)
+
+
+def test_lbdf2_wrong_extrapolation_is_caught(monkeypatch):
+    def bad(P, U, Uprev, t, tau):
+        rhs = (4.0 / 3.0) * U - (1.0 / 3.0) * Uprev + (2.0 * tau / 3.0) * P.g(t + tau, U)
+        return P.f("inv", 2.0 * tau / 3.0, rhs)
+
+    monkeypatch.setattr(O, "step_lbdf2", bad)
+    assert _fails(pins.test_observed_temporal_order_on_manufactured_solution, "lbdf2", 2)
+
+
+def test_adjoint_missing_conjugate_is_caught(monkeypatch):
+    orig = O.expeuler_vjp
+
+    def bad(P, U, Ubar_next, t, tau):
+        ubar, pbar = orig(P, U, Ubar_next, t, tau)
+        nu, eta, gamma, kappa, zeta = P.params
+        c = kappa + 1j * zeta
+        z = tau * (nu + 1j * eta) * O.ell_grid(P.lams)
+        a_hat = O.tucker(Ubar_next, [Q.T for Q in P.Qs])
+        w = tau * O.tucker(np.conj(O.phi(1, z)) * a_hat, P.Qs)
+        # replace -c u^2 conj(w) by -c u^2 w
+        ubar = ubar + c * U * U * np.conj(w) - c * U * U * w
+        return ubar, pbar
+
+    monkeypatch.setattr(O, "expeuler_vjp", bad)
+    assert _fails(pins.test_exp_euler_adjoint_matches_central_differences)

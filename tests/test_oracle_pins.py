@@ -1,0 +1,267 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: the Gamma
+definition of the FD weights, alpha -> 2 closed forms (classical 3- and 5-point
+stencils, Dirichlet-Laplacian eigenpairs), a high-precision evaluation of the
+phi-functions from their definition, brute force on the assembled Kronecker
+sum (expm / solve / augmented expm), the Kronecker-product exponential, the
+2-D Sylvester form of the inverse, invariants, observed temporal orders on a
+manufactured solution, and central finite differences for the adjoint.
+"""
+import math
+
+import mpmath
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from oracle import fcgle_oracle as O
+from workloads import grid_axes, random_complex, sech_product
+
+PARAMS = (1.0, 0.5, 1.0, 1.0, 0.5)
+
+
+# --- Section 2: FD weights and D ------------------------------------------------------
+
+@pytest.mark.parametrize("alpha", [1.1, 1.3, 1.5, 1.7, 1.9, 1.99])
+def test_fd2_recurrence_matches_gamma_definition(alpha):
+    n = 30
+    g_rec = O.fd2_weights(alpha, n)
+    g_def = O.fd2_weights_gamma(alpha, n)
+    assert np.max(np.abs(g_rec - g_def)) <= 1e-13 * np.max(np.abs(g_def))
+
+
+def test_fd2_alpha2_is_three_point_laplacian():
+    g = O.fd2_weights(2.0, 12)
+    np.testing.assert_allclose(g, [2.0, -1.0] + [0.0] * 10, atol=1e-15)
+
+
+def test_fd4_alpha2_is_five_point_stencil():
+    g = O.fd4_weights(2.0, 12)
+    np.testing.assert_allclose(g, [2.5, -4.0 / 3.0, 1.0 / 12.0] + [0.0] * 9, atol=1e-15)
+
+
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
+def test_D_symmetric_toeplitz_negative_definite(alpha):
+    n, h = 40, 0.3
+    D = O.diff_matrix(alpha, n, h)
+    assert np.array_equal(D, D.T)
+    for k in range(1, n):
+        assert np.all(np.diag(D, k) == D[0, k])
+    assert np.all(np.linalg.eigvalsh(D) < 0)
+    # the weight sum is positive and g_k < 0 for k >= 1 (diagonal dominance)
+    g = O.fd2_weights(alpha, n)
+    assert g[0] > 0 and np.all(g[1:] < 0) and g[0] + 2 * np.sum(g[1:]) > 0
+
+
+def test_eig_alpha2_dirichlet_laplacian_closed_form():
+    n, h = 17, 0.2
+    lam, Q = O.eig(O.diff_matrix(2.0, n, h))
+    k = np.arange(1, n + 1)
+    lam_exact = -(4.0 / h ** 2) * np.sin(k * np.pi / (2 * (n + 1))) ** 2
+    np.testing.assert_allclose(np.sort(lam), np.sort(lam_exact), rtol=1e-13)
+    j = np.arange(1, n + 1)[:, None]
+    Qex = np.sqrt(2.0 / (n + 1)) * np.sin(j * k[None, :] * np.pi / (n + 1))
+    # match columns (eigenvalues distinct); sign is arbitrary
+    order = np.argsort(lam)
+    order_ex = np.argsort(lam_exact)
+    for a, b in zip(order, order_ex):
+        s = np.sign(Q[:, a] @ Qex[:, b])
+        np.testing.assert_allclose(s * Q[:, a], Qex[:, b], atol=1e-12)
+
+
+@pytest.mark.parametrize("alpha", [1.3, 1.7])
+def test_eig_reconstruction_and_orthogonality(alpha):
+    n, h = 64, 0.1
+    D = O.diff_matrix(alpha, n, h)
+    lam, Q = O.eig(D)
+    assert np.linalg.norm(Q @ np.diag(lam) @ Q.T - D) <= 1e-14 * n * np.linalg.norm(D)
+    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * n
+    assert np.all(lam < 0)
+
+
+# --- phi-functions ----------------------------------------------------------------------
+
+def _phi_mp(l, z):
+    """phi_l from its definition in 60-digit arithmetic (recurrence is exact enough there)."""
+    with mpmath.workdps(60):
+        zz = mpmath.mpc(z.real, z.imag)
+        if zz == 0:
+            return complex(1 / mpmath.factorial(l))
+        p = mpmath.exp(zz)
+        for j in range(1, l + 1):
+            p = (p - 1 / mpmath.factorial(j - 1)) / zz
+        return complex(p)
+
+
+@pytest.mark.parametrize("l", [1, 2, 3])
+def test_phi_matches_high_precision_definition(l):
+    rng = np.random.default_rng(3)
+    mags = np.concatenate([10.0 ** rng.uniform(-9, 1.2, 200), [0.999, 1.0, 1.001]])
+    args = rng.uniform(0, 2 * np.pi, mags.size)
+    z = mags * np.exp(1j * args)
+    got = O.phi(l, z)
+    ref = np.array([_phi_mp(l, zz) for zz in z])
+    assert np.max(np.abs(got - ref) / np.abs(ref)) < 2e-14
+
+
+def test_phi_at_zero():
+    for l in range(4):
+        assert O.phi(l, np.array([0.0]))[0] == pytest.approx(1.0 / math.factorial(l), rel=0, abs=0)
+
+
+# --- Section 3: matrix function actions ---------------------------------------------------
+
+def _problem(n, seed, params=PARAMS):
+    rng = np.random.default_rng(seed)
+    alpha = rng.uniform(1.1, 1.95, len(n))
+    h = rng.uniform(0.05, 0.5, len(n))
+    Ds, Qs, lams = O.setup(n, alpha, h)
+    return Ds, Qs, lams
+
+
+def test_kron_order_matches_mode_products():
+    Ds, Qs, lams = _problem((4, 5, 3), 0)
+    V = random_complex((4, 5, 3), 1)
+    K = O.kron_sum(Ds, PARAMS)
+    np.testing.assert_allclose((K @ V.ravel()).reshape(V.shape), O.apply_K(V, Ds, PARAMS), rtol=0, atol=1e-9)
+
+
+@pytest.mark.parametrize("n", [(7, 9), (5, 6, 4), (3, 4, 2, 3)])
+@pytest.mark.parametrize("kind", ["inv", "exp", "phi1", "phi2", "phi3"])
+def test_apply_f_matches_brute_force(n, kind):
+    Ds, Qs, lams = _problem(n, 10 + len(n))
+    V = random_complex(n, 2)
+    theta = 3e-3
+    got = O.apply_f(kind, theta, V, Qs, lams, PARAMS)
+    ref = O.brute_apply(kind, theta, V, Ds, PARAMS)
+    assert O.rel_l2(got, ref) <= 1e-12
+
+
+def test_apply_exp_matches_kronecker_product_of_1d_exponentials():
+    n = (16, 20, 12)
+    Ds, Qs, lams = _problem(n, 5)
+    V = random_complex(n, 6)
+    got = O.apply_f("exp", 1e-2, V, Qs, lams, PARAMS)
+    ref = O.exp_neudecker(1e-2, V, Ds, PARAMS)
+    assert O.rel_l2(got, ref) <= 1e-12
+
+
+def test_apply_inv_matches_sylvester_2d():
+    n = (24, 31)
+    Ds, Qs, lams = _problem(n, 7)
+    V = random_complex(n, 8)
+    theta = 2e-2
+    c = PARAMS[0] + 1j * PARAMS[1]
+    a = 0.5 * np.eye(n[0]) - theta * c * Ds[0]
+    b = (0.5 * np.eye(n[1]) - theta * c * Ds[1]).T
+    ref = sla.solve_sylvester(a, b, V)
+    got = O.apply_f("inv", theta, V, Qs, lams, PARAMS)
+    assert O.rel_l2(got, ref) <= 1e-11
+
+
+def test_phi1_identity_with_dense_operator():
+    n = (20, 14, 9)
+    Ds, Qs, lams = _problem(n, 9)
+    V = random_complex(n, 10)
+    theta = 5e-3
+    lhs = theta * O.apply_K(O.apply_f("phi1", theta, V, Qs, lams, PARAMS), Ds, PARAMS)
+    rhs = O.apply_f("exp", theta, V, Qs, lams, PARAMS) - V
+    assert O.rel_l2(lhs, rhs) <= 1e-11
+
+
+def test_exp_is_unitary_when_dispersive():
+    params = (0.0, 1.3, 0.0, 0.0, 0.7)
+    n = (12, 10, 8)
+    Ds, Qs, lams = _problem(n, 11, params)
+    V = random_complex(n, 12)
+    out = O.apply_f("exp", 0.3, V, Qs, lams, params)
+    assert abs(np.linalg.norm(out) / np.linalg.norm(V) - 1.0) <= 1e-13
+
+
+# --- schemes -------------------------------------------------------------------------------
+
+def _manufactured(n, domain, alpha, params=PARAMS):
+    axes = grid_axes(n, domain)
+    h = [(b - a) / (m + 1) for (a, b), m in zip(domain, n)]
+    U0 = sech_product(axes, [1.0] + [0.0] * (len(n) - 1))
+    P = O.Problem(n, alpha, h, params)
+    P.source = O.manufactured_source(U0, P.Ds, params)
+    return P, U0
+
+
+def test_manufactured_solution_solves_the_semidiscrete_ode():
+    P, U0 = _manufactured((9, 8, 7), ((-8.0, 8.0),) * 3, (1.3, 1.6, 1.8))
+    for t in (0.0, 0.37):
+        u = math.exp(-t) * U0
+        dudt = -math.exp(-t) * U0
+        rhs = O.apply_K(u, P.Ds, P.params) + P.g(t, u)
+        assert np.linalg.norm(dudt - rhs) <= 1e-12 * np.linalg.norm(dudt)
+
+
+@pytest.mark.parametrize("scheme,order", [("exp_euler", 1), ("lawson", 1), ("lie", 1), ("lbdf2", 2)])
+def test_observed_temporal_order_on_manufactured_solution(scheme, order):
+    P, U0 = _manufactured((10, 12, 8), ((-8.0, 8.0),) * 3, (1.3, 1.6, 1.8))
+    T = 0.5
+    errs = []
+    taus = [2e-2, 1e-2, 5e-3, 2.5e-3]
+    for tau in taus:
+        steps = int(round(T / tau))
+        U = O.run(P, scheme, U0, tau, steps)
+        errs.append(O.rel_l2(U, math.exp(-T) * U0))
+    slopes = np.diff(np.log(errs)) / np.diff(np.log(taus))
+    assert abs(slopes[-1] - order) <= 0.1, (errs, slopes)
+
+
+def test_first_order_norm_drift_vanishes_with_tau():
+    # nu = gamma = kappa = 0, s = 0: the flow conserves the L2 norm; exponential Euler is
+    # exact on the linear part, so the drift comes from the nonlinear term only and is O(tau).
+    params = (0.0, 1.0, 0.0, 0.0, 1.0)
+    n = (16, 12)
+    axes = grid_axes(n, ((-10.0, 10.0),) * 2)
+    U0 = sech_product(axes, (1.0, 1.0))
+    P = O.Problem(n, (1.5, 1.5), [20.0 / 17, 20.0 / 13], params)
+    drifts = []
+    for tau in (4e-2, 2e-2, 1e-2):
+        U = O.run(P, "exp_euler", U0, tau, int(round(0.4 / tau)))
+        drifts.append(abs(np.linalg.norm(U) / np.linalg.norm(U0) - 1.0))
+    slopes = np.diff(np.log(drifts)) / np.log(0.5)
+    assert np.all(np.abs(slopes - 1.0) < 0.15), (drifts, slopes)
+
+
+# --- adjoint -------------------------------------------------------------------------------
+
+def _loss(params, U0, n, alpha, h, target, tau, steps):
+    P = O.Problem(n, alpha, h, params)
+    U = O.run(P, "exp_euler", U0, tau, steps)
+    return float(np.sum(np.abs(U - target) ** 2))
+
+
+def test_exp_euler_adjoint_matches_central_differences():
+    n = (8, 7, 6)
+    alpha = (1.5, 1.4, 1.6)
+    h = (20.0 / 9, 20.0 / 8, 20.0 / 7)
+    axes = grid_axes(n, ((-10.0, 10.0),) * 3)
+    U0 = sech_product(axes, (1.0, 0.0, 0.0))
+    tau, steps = 1e-2, 6
+    pert = np.array(PARAMS) + np.array([0.1, -0.1, 0.1, -0.1, 0.1])
+    target = O.run(O.Problem(n, alpha, h, tuple(pert)), "exp_euler", U0, tau, steps)
+    P = O.Problem(n, alpha, h, PARAMS)
+    L, ubar0, pbar = O.expeuler_loss_and_grad(P, U0, target, tau, steps)
+    fd_h = 1e-4
+    # parameters
+    for i in range(5):
+        pp = np.array(PARAMS); pp[i] += fd_h
+        pm = np.array(PARAMS); pm[i] -= fd_h
+        fd = (_loss(tuple(pp), U0, n, alpha, h, target, tau, steps)
+              - _loss(tuple(pm), U0, n, alpha, h, target, tau, steps)) / (2 * fd_h)
+        assert abs(fd - pbar[i]) <= 1e-6 * max(abs(fd), 1e-3), (i, fd, pbar[i])
+    # initial state, along random complex unit directions
+    rng = np.random.default_rng(5)
+    for _ in range(4):
+        dlt = rng.standard_normal(n) + 1j * rng.standard_normal(n)
+        dlt /= np.linalg.norm(dlt)
+        fd = (_loss(PARAMS, U0 + fd_h * dlt, n, alpha, h, target, tau, steps)
+              - _loss(PARAMS, U0 - fd_h * dlt, n, alpha, h, target, tau, steps)) / (2 * fd_h)
+        an = float(np.real(np.vdot(ubar0, dlt)))
+        assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-3), (fd, an)
