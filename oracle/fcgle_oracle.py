@@ -12,7 +12,8 @@ Ginzburg--Landau equation"):
 
 * Section 2: FD2 weights g_k (Gamma form and its stable recurrence), the FD4
   extrapolated weights, the dense Toeplitz matrix D_n^alpha and its
-  diagonalisation D = Q Lambda Q^T (scipy eigh, i.e. LAPACK).
+  diagonalisation D = Q Lambda Q^T (LAPACK DSYEV through scipy, then one
+  extended-precision orthogonalisation sweep).
 * Section 3 (eq. fKu_diag): the Tucker form of f(theta K) v, computed with
   permute-based tensordot mode products.
 * Section 3 (eq. Neudeckerd): the exponential as a Kronecker product of 1-D
@@ -89,9 +90,21 @@ def diff_matrix(alpha: float, n: int, h: float, fd_order: int = 2) -> np.ndarray
 
 
 def eig(D: np.ndarray) -> Tuple[np.ndarray, np.ndarray]:
-    """D = Q diag(lam) Q^T with Q orthogonal (Section 2, eq. diag), by LAPACK through scipy."""
-    lam, Q = sla.eigh(D)
-    return lam, Q
+    """D = Q diag(lam) Q^T with Q orthogonal (Section 2, eq. diag).
+
+    LAPACK DSYEV (the routine the paper uses, Section 4) through scipy, followed by one
+    Newton-Schulz orthogonalisation sweep Q <- Q + Q (I - Q^T Q)/2 in extended precision and
+    Rayleigh-quotient eigenvalues lam_k = q_k^T D q_k.  Reading: Section 2 requires Q to be
+    orthogonal, and the stateless schemes apply Q f Q^T once per step, so any loss of
+    orthogonality left by the FP64 solver (a few 1e-15) would accumulate linearly with the
+    number of steps; after the sweep Q^T Q = I to rounding of the final FP64 entries.
+    """
+    lam, Q = sla.eigh(D, driver="ev")
+    X = Q.astype(np.longdouble)
+    Dl = D.astype(np.longdouble)
+    X = X + 0.5 * (X @ (np.eye(D.shape[0], dtype=np.longdouble) - X.T @ X))
+    lam = np.sum(X * (Dl @ X), axis=0)
+    return lam.astype(np.float64), X.astype(np.float64)
 
 
 def setup(n: Sequence[int], alpha: Sequence[float], h: Sequence[float], fd_order: int = 2):

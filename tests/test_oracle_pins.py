@@ -76,7 +76,8 @@ def test_eig_reconstruction_and_orthogonality(alpha):
     D = O.diff_matrix(alpha, n, h)
     lam, Q = O.eig(D)
     assert np.linalg.norm(Q @ np.diag(lam) @ Q.T - D) <= 1e-14 * n * np.linalg.norm(D)
-    assert np.linalg.norm(Q.T @ Q - np.eye(n)) <= 1e-14 * n
+    # orthogonal to the rounding of its FP64 entries (spectral norm), see oracle.eig
+    assert np.linalg.norm(Q.T @ Q - np.eye(n), 2) <= 1.5e-15
     assert np.all(lam < 0)
 
 
