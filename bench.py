@@ -1,0 +1,200 @@
+"""Benchmark: exponential-Euler steps per second for the 3-D space-fractional CGLE at 256^3.
+
+Workload: 256^3 inner points on (-12,12)^3, alpha = 1.7 per axis, (nu, eta, gamma, kappa,
+zeta) = (1, 0.5, 1, 1, 0.5), u0 = sum of 4 random-phase Gaussians (seed 21394),
+tau = 1e-3; one step = one forward and one backward Tucker operator (6 mode products) with
+the nonlinearity and the eigenspace update fused into them.
+
+The headline `value` is the FP32-MFMA path (complex64 state); the FP64, split-BF16 (3 and 6
+products) paths are timed the same way and reported under "variants", each with its relative
+L2 error at T = 200 steps against the FP64 oracle (stored samples of the oracle trajectory,
+tests/golden/3d_256_gauss4_expeuler.npz) when that file is present.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--precision fp32] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6, "bf16x6": 2516.6}
+HBM_PEAK_GBS = 8000.0
+GOLDEN = os.path.join(ROOT, "tests", "golden", "3d_256_gauss4_expeuler.npz")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
+    ap.add_argument("--variants", default="fp64,fp32,bf16x3,bf16x6")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--n", type=int, default=256)
+    return ap.parse_args()
+
+
+def time_precision(prec, w, U0, steps, warmup, autotune, golden):
+    import torch
+    from paper_2510_21394_amd import Plan
+    from paper_2510_21394_amd.fcgle import decode_signature
+
+    dt = torch.complex128 if prec == "fp64" else torch.complex64
+    plan = Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
+    if autotune:
+        plan.autotune(3)
+    u0 = torch.from_numpy(U0).to(dt).cuda()
+    u = u0.clone()
+    plan.run("exp_euler", u, 0.0, warmup)          # includes the one-time forward transform
+    torch.cuda.synchronize()
+    plan.timing_enable(6 * steps + 16)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run("exp_euler", u, warmup * w.tau, steps)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    rec = plan.timing_read()
+    plan.timing_enable(0)
+    # accuracy: a fresh trajectory of the stored length from u0
+    err = None
+    if golden is not None:
+        v = u0.clone()
+        plan.set_state(v)
+        plan.run("exp_euler", v, 0.0, int(golden["steps"]))
+        torch.cuda.synchronize()
+        got = v.reshape(-1)[torch.from_numpy(golden["idx"]).cuda()].cpu().numpy().astype(np.complex128)
+        ref = golden["val"]
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    # per-kernel aggregation (kernel instantiation = signature)
+    per = {}
+    for axis, fwd, sig, ms in rec:
+        d = per.setdefault(sig, {"ms": 0.0, "count": 0, "launches": set()})
+        d["ms"] += ms
+        d["count"] += 1
+        d["launches"].add((axis, fwd))
+    n = w.n[0]
+    N = int(np.prod(w.n))
+    flop_per_launch = 4.0 * n * N  # real Q (n x n) times complex fibres: 2 real flop per MAC x 2 parts
+    total_mp_ms = sum(d["ms"] for d in per.values())
+    dom_sig = max(per, key=lambda s: per[s]["ms"])
+    dom = per[dom_sig]
+    avg_ms = dom["ms"] / dom["count"]
+    achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    kernels = []
+    for sig, d in sorted(per.items(), key=lambda kv: -kv[1]["ms"]):
+        a = d["ms"] / d["count"]
+        kernels.append({"kernel": decode_signature(sig), "signature": sig, "launches_per_step": d["count"] / steps,
+                        "avg_us": round(a * 1e3, 2),
+                        "tflops": round(flop_per_launch / (a * 1e-3) / 1e12, 2),
+                        "axes_dirs": sorted(d["launches"])})
+    out = {
+        "precision": prec,
+        "steps_per_s": steps / elapsed,
+        "ms_per_step": 1e3 * elapsed / steps,
+        "mode_products_ms_per_step": total_mp_ms / steps,
+        "mode_product_tflops_avg": 6 * steps * flop_per_launch / (total_mp_ms * 1e-3) / 1e12,
+        "rel_l2_vs_fp64_oracle_at_T": err,
+        "tiles": plan.describe(),
+        "dominant": {"signature": dom_sig, "kernel": decode_signature(dom_sig), "avg_ms": avg_ms,
+                     "achieved_tflops": achieved, "count": dom["count"]},
+        "kernels": kernels,
+    }
+    plan.close()
+    del u, u0
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
+    """The FP64 oracle as it stands, timed on the host cores (bounded sample of the workload)."""
+    from oracle import fcgle_oracle as O
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    U = U0
+    t0 = time.perf_counter()
+    k = 0
+    while k < max_steps:
+        U = O.step_exp_euler(P, U, k * w.tau, w.tau)
+        k += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    threads = os.environ.get("OPENBLAS_NUM_THREADS") or os.environ.get("OMP_NUM_THREADS")
+    cores = len(os.sched_getaffinity(0))
+    return {"value": k / el, "unit": "steps/s", "cores": int(threads) if threads else cores, "kind": "oracle",
+            "sample": f"{k} exponential-Euler step(s) of the 256^3 workload from u0 in numpy/scipy FP64 "
+                      f"({el:.1f} s; affinity {cores} cores)"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+                          "n_gpus": a.gpus}))
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    import workloads as W
+    w = W.headline_3d(n=a.n)
+    U0 = W.u0_headline(w)
+    golden = None
+    if a.n == 256 and os.path.exists(GOLDEN):
+        golden = dict(np.load(GOLDEN))
+    variants = {}
+    order = [a.precision] + [p for p in a.variants.split(",") if p and p != a.precision]
+    for prec in order:
+        variants[prec] = time_precision(prec, w, U0, a.steps, a.warmup, not a.no_autotune, golden)
+        print(f"# {prec}: {variants[prec]['steps_per_s']:.1f} steps/s, "
+              f"{variants[prec]['ms_per_step']:.3f} ms/step, err {variants[prec]['rel_l2_vs_fp64_oracle_at_T']}",
+              file=sys.stderr, flush=True)
+    head = variants[a.precision]
+    dom = head["dominant"]
+    peak = PEAK_TFLOPS[a.precision]
+    line = {
+        "metric": "exp-Euler steps/sec 3-D 256^3 complex; FP32/BF16x3-MFMA vs FP64 at rel err",
+        "value": head["steps_per_s"],
+        "unit": "steps/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3->f32", "bf16x6": "bf16x6->f32"}[a.precision],
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": list(w.n), "domain": list(w.domain[0]), "alpha": list(w.alpha),
+                   "params": list(w.params), "tau": w.tau, "scheme": "exp_euler", "precision": a.precision,
+                   "rel_l2_steps": int(golden["steps"]) if golden is not None else None},
+        "rel_l2_vs_fp64_oracle_at_T": head["rel_l2_vs_fp64_oracle_at_T"],
+        "roofline": {
+            "bound": "mfma",
+            "kernel": dom["kernel"],
+            "achieved": dom["achieved_tflops"],
+            "peak": peak,
+            "unit": "TFLOP/s",
+            "frac": dom["achieved_tflops"] / peak,
+            "traffic": None,
+            "per_launch_flop": 4.0 * w.n[0] * float(np.prod(w.n)),
+            "avg_launch_ms": dom["avg_ms"],
+        },
+        "variants": {p: {k: v for k, v in d.items() if k != "kernels"} for p, d in variants.items()},
+        "kernels": head["kernels"],
+    }
+    if not a.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, U0)
+    print(json.dumps(line, default=lambda o: list(o) if isinstance(o, (set, tuple)) else str(o)))
+
+
+if __name__ == "__main__":
+    main()

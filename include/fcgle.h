@@ -1,0 +1,248 @@
+/*
+ * fcgle.h -- C ABI of the MI355X (gfx950) library for the matrix/tensor-oriented
+ * integrators of the d-dimensional space-fractional complex Ginzburg--Landau
+ * equation (Caliari & Cassini).
+ *
+ * The equation (Section 1, eq. FCGLE) is
+ *     u_t = (nu + i eta) sum_mu d^{alpha_mu}_{x_mu} u + gamma u - (kappa + i zeta)|u|^2 u + s,
+ * semidiscretised (Section 2) with centred fractional differences on n_mu inner
+ * points per axis into u' = K u + g(t, u), where K = (nu + i eta)(D_1 (+) ... (+) D_d)
+ * is a Kronecker sum (eq. Ksum) of dense symmetric Toeplitz matrices D_mu = Q_mu Lambda_mu Q_mu^T
+ * (eqs. Dnalpha, diag).  Every time step applies a matrix function f(theta K) through
+ * the Tucker form (Section 3, eq. fKu_diag):
+ *     f(theta K) v = vec( (F o (V x_1 Q_1^T ... x_d Q_d^T)) x_1 Q_1 ... x_d Q_d ),
+ * F_j = f(theta (nu + i eta) sum_mu lambda_{j_mu}).
+ *
+ * Conventions shared by all entry points
+ * --------------------------------------
+ *  - Tensors are C-ordered (n_1, ..., n_d), axis d fastest, complex interleaved
+ *    (re, im).  The element type is complex128 for FCGLE_FP64 plans and
+ *    complex64 for FCGLE_FP32 / FCGLE_BF16X3 / FCGLE_BF16X6 plans.
+ *  - Arguments named *_dev are device pointers on the plan's device, owned by
+ *    the caller, 16-byte aligned.  Arguments without the suffix are host memory.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work is ordered on it; no entry point synchronises except
+ *    fcgle_setup / fcgle_batch_setup (host-to-device uploads), the fcgle_host_*
+ *    helpers (host only) and the calls documented as synchronising.
+ *  - Return value: FCGLE_OK (0) or a negative fcgle_status.  A readable message
+ *    for the last failure on the calling thread is given by fcgle_last_error().
+ *    No C++ exception crosses this boundary.
+ *  - A plan is not thread-safe: calls on one plan must not overlap.
+ */
+#ifndef FCGLE_H
+#define FCGLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct fcgle_plan fcgle_plan;
+
+/* Model parameters of eq. FCGLE (Section 1): nu >= 0, kappa >= 0 (the paper takes
+ * both positive; 0 is accepted for conservation tests), eta, gamma, zeta real. */
+typedef struct {
+  double nu, eta, gamma, kappa, zeta;
+} fcgle_params;
+
+typedef enum {
+  FCGLE_OK = 0,
+  FCGLE_ERR_ARG = -1,         /* invalid argument (sizes, orders, NULL, tau mismatch ...) */
+  FCGLE_ERR_UNSUPPORTED = -2, /* valid request this build does not implement            */
+  FCGLE_ERR_NOMEM = -3,       /* device or host allocation failed                       */
+  FCGLE_ERR_HIP = -4,         /* a HIP runtime call failed                              */
+  FCGLE_ERR_NONFINITE = -5,   /* NaN/Inf found by fcgle_check_finite                    */
+  FCGLE_ERR_STATE = -6        /* call out of order (e.g. no source registered)          */
+} fcgle_status;
+
+/* Matrix functions f(z) (Section 3 and Section 4, eq. phi). */
+typedef enum {
+  FCGLE_INV = 0,  /* 1/(1 - z): linearly implicit steps          */
+  FCGLE_EXP = 1,  /* e^z = phi_0                                  */
+  FCGLE_PHI1 = 2, /* phi_1(z) = (e^z - 1)/z, phi_1(0) = 1         */
+  FCGLE_PHI2 = 3, /* phi_2(z) = (phi_1(z) - 1)/z, phi_2(0) = 1/2  */
+  FCGLE_PHI3 = 4  /* phi_3(z) = (phi_2(z) - 1/2)/z, phi_3(0) = 1/6 */
+} fcgle_kind;
+
+/* Time schemes for u' = K u + g(t, u). */
+typedef enum {
+  FCGLE_EXP_EULER = 0, /* u+ = e^{tau K} u + tau phi_1(tau K) g(t, u)                      */
+  FCGLE_LAWSON = 1,    /* u+ = e^{tau K} (u + tau g(t, u))                                  */
+  FCGLE_LIE = 2,       /* backward-forward Euler (Section 4): (I - tau K) u+ = u + tau g(t, u) */
+  FCGLE_LBDF2 = 3      /* linearised BDF2 with BFE start (Section 4, eq. lbdf2-v)          */
+} fcgle_scheme;
+
+/* Arithmetic of the mode-product contractions.  Setup (weights, eigenpairs,
+ * f-grids) is always FP64. */
+typedef enum {
+  FCGLE_FP64 = 0,   /* complex128 state, FP64 MFMA                                       */
+  FCGLE_FP32 = 1,   /* complex64 state, FP32 MFMA                                        */
+  FCGLE_BF16X3 = 2, /* complex64 state, Q and U split in 2 BF16 pieces, 3 products, FP32 acc */
+  FCGLE_BF16X6 = 3  /* complex64 state, 3 BF16 pieces, 6 products, FP32 acc               */
+} fcgle_precision;
+
+/* ---------------------------------------------------------------------------
+ * Plan lifetime
+ * ------------------------------------------------------------------------- */
+
+/* Build a plan on the current HIP device.
+ *   d          : number of space dimensions, 1 <= d <= 4
+ *   n[d]       : inner points per axis, 2 <= n_mu <= 4096 (Section 2 grid)
+ *   alpha[d]   : fractional orders, 1 < alpha_mu <= 2 (the paper requires < 2;
+ *                2 gives the classical 3-point Laplacian and is kept for tests)
+ *   h[d]       : grid spacings (b_mu - a_mu)/(n_mu + 1) > 0
+ *   params     : model parameters (see fcgle_params)
+ *   fd_order   : 2 (eq. FD2) or 4 (eq. FD4)
+ *   precision  : fcgle_precision
+ *   tau        : time step > 0; the f-grids are built for it
+ *   out        : receives the plan (NULL on failure)
+ * Forms the weights g_k by their recurrence (Section 2), the dense D_mu, their
+ * eigendecomposition in FP64 on the host (Section 4, the paper's CPU-side
+ * diagonalisation), and uploads Q_mu, Q_mu^T (in the plan's precision) and lambda_mu.
+ * Synchronous.  Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+int fcgle_setup(int d, const int64_t* n, const double* alpha, const double* h,
+                const fcgle_params* params, int fd_order, int precision, double tau,
+                fcgle_plan** out);
+
+/* Release every device and host resource of the plan (NULL is a no-op).
+ * Synchronises the plan's device before freeing. */
+void fcgle_destroy(fcgle_plan* plan);
+
+/* Message describing the last failure on the calling thread ("" if none).
+ * The pointer stays valid until the next failing call on the same thread. */
+const char* fcgle_last_error(void);
+
+/* Eigenpairs of axis mu (0-based) in FP64: Q[n_mu * n_mu] row-major with
+ * column k the eigenvector of lambda[k]; lambda ascending.  Host buffers.
+ * Errors: ERR_ARG. */
+int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda);
+
+/* Register the source s(t) = sum_k exp(rate[k] t) S_k (Section 2, the term s of
+ * g), nterms <= 4, each S_k a device tensor of the plan's state type that must
+ * stay alive while steps run.  nterms = 0 removes the source.  Errors: ERR_ARG. */
+int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const void* const* S_dev);
+
+/* ---------------------------------------------------------------------------
+ * Matrix-function action and time steps
+ * ------------------------------------------------------------------------- */
+
+/* out = f(theta K) u (Section 3, eq. fKu_diag) for f = kind.  u_dev and out_dev
+ * may be the same buffer.  The f-grid for (kind, theta) is built in FP64 on the
+ * first call with that pair (synchronous upload); later calls only launch
+ * kernels.  The exponential uses the separable grid exp(theta(nu+i eta)lambda_1) x ...
+ * (the Kronecker-product form, eq. Neudeckerd).  Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, void* out_dev,
+                  void* stream);
+
+/* Forget the cached eigenspace state and the LBDF2 history, then (if u_prev_dev
+ * is not NULL) record u_prev_dev as u_{n-1} for the next FCGLE_LBDF2 step on
+ * u_dev.  Call it whenever the caller writes u_dev between steps.  Errors: ERR_ARG. */
+int fcgle_set_state(fcgle_plan* plan, const void* u_dev, const void* u_prev_dev, void* stream);
+
+/* Advance u_dev in place from time t to t + tau by one step of `scheme`.
+ * tau must equal the plan's tau (ERR_ARG otherwise).
+ * FCGLE_EXP_EULER keeps u_hat = u x_mu Q_mu^T in the plan between calls on the
+ * same u_dev, so a steady-state step costs one forward and one backward Tucker
+ * operator; the first step on a buffer (or after fcgle_set_state) adds one
+ * forward transform.  FCGLE_LBDF2 takes the BFE start when it has no history
+ * for u_dev and keeps u_{n-1} in the plan afterwards.  Errors: ERR_ARG, ERR_HIP. */
+int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, void* stream);
+
+/* nsteps consecutive fcgle_step calls from t0 (t_k = t0 + k tau). */
+int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps,
+              void* stream);
+
+/* Vector-Jacobian product of one FCGLE_EXP_EULER step u_{n+1} = E u_n + tau P1 g(t, u_n)
+ * (E = e^{tau K}, P1 = phi_1(tau K)) for a real loss, cotangent convention
+ * ubar = dL/dRe u + i dL/dIm u:
+ *   w        = tau P1^H ubar_{n+1}
+ *   ubar_n   = E^H ubar_{n+1} + (gamma - 2 conj(c)|u_n|^2) w - c u_n^2 conj(w),  c = kappa + i zeta
+ *   pbar    += dL/d(nu, eta, gamma, kappa, zeta)
+ * u_n_dev: the state the step started from; ubar_next_dev: cotangent of u_{n+1};
+ * ubar_n_dev: output (may alias ubar_next_dev); pbar_dev: 5 doubles on the
+ * device, ADDED to.  The source must not depend on the parameters.
+ * Other schemes: ERR_UNSUPPORTED.  Errors: ERR_ARG, ERR_HIP. */
+int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* ubar_next_dev,
+              void* ubar_n_dev, double* pbar_dev, double t, double tau, void* stream);
+
+/* Scan a state tensor for NaN/Inf.  Synchronises `stream`.
+ * Returns FCGLE_OK or FCGLE_ERR_NONFINITE (or ERR_ARG / ERR_HIP). */
+int fcgle_check_finite(fcgle_plan* plan, const void* u_dev, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Introspection, tuning and timing
+ * ------------------------------------------------------------------------- */
+
+/* Number of elements N = prod n_mu and bytes per complex element (16 or 8). */
+int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
+
+/* Time every candidate tile configuration of each mode product on `stream`
+ * (scratch inputs, `reps` launches each) and keep the fastest per axis and
+ * direction.  Synchronous.  Errors: ERR_HIP. */
+int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
+
+/* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */
+int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len);
+
+/* Enable (capacity > 0) or disable (0) per-launch HIP-event timing of the
+ * mode-product kernels.  While enabled, each mode-product launch records an
+ * event pair on its stream (up to `capacity` launches, further ones untimed).
+ * Errors: ERR_NOMEM, ERR_HIP. */
+int fcgle_timing_enable(fcgle_plan* plan, int capacity);
+
+/* Copy out the recorded launches (synchronising on their events) and clear the
+ * record.  For launch i < *count (at most cap): axis[i] = mode axis (0-based),
+ * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
+ * its duration, sig[i] = the kernel instantiation it ran:
+ *   sig = (((prec * 4 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
+ * (prec 0..3 as fcgle_precision; t_loader 1 for the fastest axis; prologue 0 none,
+ * 1 nonlinearity; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
+ * 4 keep-old, 5/6 adjoint stages).  Errors: ERR_STATE if timing is off, ERR_HIP. */
+int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
+                      int64_t* count);
+
+/* ---------------------------------------------------------------------------
+ * Batched independent 2-D instances
+ * ------------------------------------------------------------------------- */
+
+/* A batch of `count` independent 2-D problems of uneven sizes n[2i], n[2i+1],
+ * each with its own alpha[2i..2i+1], h[2i..2i+1] and params[i], one shared tau,
+ * FD2, complex64 state, FP32 MFMA (precision must be FCGLE_FP32).  State buffers
+ * are per instance (u_dev[i] of n[2i] * n[2i+1] complex64).  Synchronous.
+ * Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h,
+                      const fcgle_params* params, int precision, double tau, fcgle_plan** out);
+
+/* nsteps exponential-Euler steps of every instance from t0 (sources are not
+ * supported in batches).  Each phase of a step is one grouped launch over all
+ * instances; the whole trajectory is replayed from a captured HIP graph.
+ * scheme must be FCGLE_EXP_EULER.  Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_HIP. */
+int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau,
+                    int64_t nsteps, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Host-only helpers (no device calls; usable without a GPU)
+ * ------------------------------------------------------------------------- */
+
+/* FD weights g_0..g_{n-1} of order fd_order (2: recurrence of Section 2;
+ * 4: extrapolation of eq. FD4) into g[n].  Errors: ERR_ARG. */
+int fcgle_host_fd_weights(double alpha, int64_t n, int fd_order, double* g);
+
+/* D = -h^{-alpha} Toeplitz(g) and its FP64 eigendecomposition by this library's
+ * own solver (Householder tridiagonalisation + implicit symmetric QR with
+ * Wilkinson shifts).  Q[n*n] row-major, column k = eigenvector of lambda[k]
+ * (ascending).  Errors: ERR_ARG, ERR_NOMEM. */
+int fcgle_host_eig(int64_t n, double alpha, double h, int fd_order, double* Q, double* lambda);
+
+/* f(z) for `count` complex z (interleaved re, im) in FP64, as used for the
+ * device f-grids: kind = fcgle_kind.  phi_l uses its Taylor series for |z| < 1
+ * and the recurrence of eq. phi elsewhere.  Errors: ERR_ARG. */
+int fcgle_host_fz(int kind, int64_t count, const double* z, double* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FCGLE_H */

@@ -1,0 +1,807 @@
+// The plan and the C ABI declared in include/fcgle.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fcgle.h"
+#include "fz.hpp"
+#include "host_math.h"
+#include "launch.h"
+
+using namespace fcgle;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(FCGLE_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                      \
+  } while (0)
+
+#define FC_TRY(expr)            \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != FCGLE_OK) return r_; \
+  } while (0)
+
+// Restores the calling thread's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct GridBuf {
+  int kind;
+  double theta;
+  void* F;
+};
+
+struct SepBuf {
+  double theta;
+  void* fac[4];  // double2[n_mu] each
+};
+
+struct TimedLaunch {
+  hipEvent_t e0, e1;
+  int axis, fwd, sig;
+};
+
+}  // namespace
+
+struct fcgle_plan {
+  int device = 0;
+  int d = 0;
+  int64_t n[4] = {1, 1, 1, 1};
+  double alpha[4] = {0, 0, 0, 0};
+  double h[4] = {0, 0, 0, 0};
+  fcgle_params p{};
+  int fd_order = 2;
+  int prec = FCGLE_FP64;
+  double tau = 0;
+  int64_t N = 1;
+  int elem = 16;
+  int npad[4] = {0, 0, 0, 0};
+  std::vector<double> Q[4], lam[4];  // host FP64: Q row-major, column k <-> lam[k]
+  void* Mf[4] = {nullptr, nullptr, nullptr, nullptr};  // Q^T in the precision layout
+  void* Mb[4] = {nullptr, nullptr, nullptr, nullptr};  // Q
+  double* dlam[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<GridBuf> grids;
+  std::vector<SepBuf> seps;
+  void* s[3] = {nullptr, nullptr, nullptr};  // scratch tensors
+  void* uhat = nullptr;
+  bool uhat_valid = false;
+  const void* uhat_src = nullptr;
+  void* uprev = nullptr;
+  bool hist_valid = false;
+  const void* hist_src = nullptr;
+  int ns = 0;
+  double rate[4] = {0, 0, 0, 0};
+  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
+  int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd]
+  bool tuned = false;
+  int* dflag = nullptr;
+  // adjoint work buffers (allocated on first use)
+  void* adj[4] = {nullptr, nullptr, nullptr, nullptr};
+  double* partial = nullptr;
+  int64_t partial_rows = 0;
+  // timing
+  int timing_cap = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<TimedLaunch> timed;
+};
+
+namespace {
+
+hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+int plan_alloc(void** p, size_t bytes) {
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(FCGLE_ERR_NOMEM, "hipMalloc(%zu bytes) failed: %s", bytes, hipGetErrorString(e));
+  }
+  return FCGLE_OK;
+}
+
+int precision_of(const fcgle_plan* P) {
+  switch (P->prec) {
+    case FCGLE_FP64: return P_F64;
+    case FCGLE_FP32: return P_F32;
+    case FCGLE_BF16X3: return P_BF16X3;
+    default: return P_BF16X6;
+  }
+}
+
+// Upload M (n x n FP64, M[i][k]) in the plan's precision layout, zero padded to npad.
+int upload_matrix(fcgle_plan* P, const std::vector<double>& M, int64_t n, int64_t npad, void** dst) {
+  const int pr = precision_of(P);
+  if (pr == P_F64) {
+    std::vector<double> buf(npad * npad, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < n; ++k) buf[i * npad + k] = M[i * n + k];
+    FC_TRY(plan_alloc(dst, buf.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(*dst, buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  } else if (pr == P_F32) {
+    std::vector<float> buf(npad * npad, 0.0f);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < n; ++k) buf[i * npad + k] = (float)M[i * n + k];
+    FC_TRY(plan_alloc(dst, buf.size() * sizeof(float)));
+    HIP_TRY(hipMemcpy(*dst, buf.data(), buf.size() * sizeof(float), hipMemcpyHostToDevice));
+  } else {
+    const int np = (pr == P_BF16X3) ? 2 : 3;
+    std::vector<uint16_t> buf(np * npad * npad, 0);
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t k = 0; k < n; ++k) {
+        double r = M[i * n + k];  // split in FP64: q0 = bf16(q), q1 = bf16(q - q0), ...
+        for (int q = 0; q < np; ++q) {
+          const uint16_t b = bf16_round(r);
+          buf[q * npad * npad + i * npad + k] = b;
+          r -= bf16_value(b);
+        }
+      }
+    FC_TRY(plan_alloc(dst, buf.size() * sizeof(uint16_t)));
+    HIP_TRY(hipMemcpy(*dst, buf.data(), buf.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+  }
+  return FCGLE_OK;
+}
+
+SepParams sep_base(const fcgle_plan* P) {
+  SepParams s;
+  s.d = P->d;
+  for (int m = 0; m < P->d; ++m) {
+    s.n[m] = (int)P->n[m];
+    s.lam[m] = P->dlam[m];
+  }
+  return s;
+}
+
+// Device f-grid for (kind, theta), built on first use.
+int get_grid(fcgle_plan* P, int kind, double theta, hipStream_t st, const void** out) {
+  for (auto& g : P->grids)
+    if (g.kind == kind && g.theta == theta) {
+      *out = g.F;
+      return FCGLE_OK;
+    }
+  GridBuf g{kind, theta, nullptr};
+  FC_TRY(plan_alloc(&g.F, (size_t)P->N * P->elem));
+  SepParams s = sep_base(P);
+  HIP_TRY(launch_fgrid(precision_of(P), kind, theta * P->p.nu, theta * P->p.eta, s, P->N, g.F, st));
+  P->grids.push_back(g);
+  *out = g.F;
+  return FCGLE_OK;
+}
+
+// Separable exponential factors exp(theta (nu + i eta) lambda_mu[j]) per axis, FP64 on the host.
+int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
+  *sp = sep_base(P);
+  for (auto& e : P->seps)
+    if (e.theta == theta) {
+      for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
+      return FCGLE_OK;
+    }
+  SepBuf e{theta, {nullptr, nullptr, nullptr, nullptr}};
+  for (int m = 0; m < P->d; ++m) {
+    std::vector<double> buf(2 * P->n[m]);
+    for (int64_t j = 0; j < P->n[m]; ++j) {
+      const zc z = fz_eval(1, zc{theta * P->p.nu * P->lam[m][j], theta * P->p.eta * P->lam[m][j]});
+      buf[2 * j] = z.re;
+      buf[2 * j + 1] = z.im;
+    }
+    FC_TRY(plan_alloc(&e.fac[m], buf.size() * sizeof(double)));
+    HIP_TRY(hipMemcpy(e.fac[m], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+  }
+  P->seps.push_back(e);
+  for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
+  return FCGLE_OK;
+}
+
+int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
+  const bool timed = P->timing_cap > 0 && (int)P->timed.size() < P->timing_cap;
+  TimedLaunch tl{};
+  if (timed) {
+    tl.e0 = P->ev_pool[2 * P->timed.size()];
+    tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
+    tl.axis = axis;
+    tl.fwd = (L.M == P->Mf[axis]) ? 1 : 0;
+    tl.sig = ((((L.prec * 4 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
+    HIP_TRY(hipEventRecord(tl.e0, st));
+  }
+  HIP_TRY(launch_mode_product(L, st));
+  if (timed) {
+    HIP_TRY(hipEventRecord(tl.e1, st));
+    P->timed.push_back(tl);
+  }
+  return FCGLE_OK;
+}
+
+MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
+  MPLaunch L;
+  L.prec = precision_of(P);
+  L.cfg = P->cfg[mu][fwd ? 1 : 0];
+  int64_t A = 1, B = 1;
+  for (int m = 0; m < mu; ++m) A *= P->n[m];
+  for (int m = mu + 1; m < P->d; ++m) B *= P->n[m];
+  L.A = A;
+  L.B = B;
+  L.n = (int)P->n[mu];
+  L.npad = P->npad[mu];
+  L.M = fwd ? P->Mf[mu] : P->Mb[mu];
+  return L;
+}
+
+// One Tucker operator: out = epi( pro(in) x_1 M_1 ... x_d M_d ) with M = Q^T (fwd) or Q.
+// tmp0/tmp1 are scratch tensors distinct from in and from the epilogue's buffers.
+int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams& pp, EpiKind ek,
+           EpiParams ep, void* tmp0, void* tmp1, hipStream_t st) {
+  const int pr = precision_of(P);
+  void* tmps[2] = {tmp0, tmp1};
+  int next_tmp = 0;
+  auto pick = [&](const void* avoid) -> void* {
+    void* t = tmps[next_tmp];
+    if (t == avoid) {
+      next_tmp ^= 1;
+      t = tmps[next_tmp];
+    }
+    next_tmp ^= 1;
+    return t;
+  };
+  const void* cur = in;
+  for (int mu = 0; mu < P->d; ++mu) {
+    const bool first = (mu == 0), last = (mu == P->d - 1);
+    MPLaunch L = base_launch(P, mu, fwd);
+    const bool tl = (L.B == 1);
+    L.in = cur;
+    if (first && pk != ProKind::Id) {
+      if (mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
+        L.pk = pk;
+        L.pp = pp;
+      } else {
+        void* t = pick(cur);
+        HIP_TRY(launch_pointwise_pro(pr, P->N, cur, t, pp, st));
+        L.in = t;
+      }
+    }
+    if (last) {
+      ep.sep.mu = mu;
+      if (mp_supported(tl, L.pk, ek)) {
+        L.ek = ek;
+        L.ep = ep;
+        FC_TRY(launch_timed(P, L, mu, st));
+      } else {
+        void* t = pick(L.in);
+        L.ek = EpiKind::Store;
+        L.ep = EpiParams();
+        L.ep.out = t;
+        FC_TRY(launch_timed(P, L, mu, st));
+        HIP_TRY(launch_pointwise_epi(pr, P->N, (int)P->n[mu], t, ek, ep, st));
+      }
+    } else {
+      void* t = pick(L.in);
+      L.ek = EpiKind::Store;
+      L.ep.out = t;
+      FC_TRY(launch_timed(P, L, mu, st));
+      cur = t;
+    }
+  }
+  return FCGLE_OK;
+}
+
+ProParams nonlin_params(const fcgle_plan* P, double t_eval) {
+  ProParams pp;
+  pp.gamma = P->p.gamma;
+  pp.kappa = P->p.kappa;
+  pp.zeta = P->p.zeta;
+  pp.ns = P->ns;
+  for (int k = 0; k < P->ns; ++k) {
+    pp.S[k] = P->S[k];
+    pp.sc[k] = std::exp(P->rate[k] * t_eval);
+  }
+  return pp;
+}
+
+int check_plan(const fcgle_plan* P) {
+  if (!P) return fail(FCGLE_ERR_ARG, "plan is NULL");
+  return FCGLE_OK;
+}
+
+int ensure_state_buffers(fcgle_plan* P) {
+  if (!P->uhat) FC_TRY(plan_alloc(&P->uhat, (size_t)P->N * P->elem));
+  if (!P->uprev) FC_TRY(plan_alloc(&P->uprev, (size_t)P->N * P->elem));
+  return FCGLE_OK;
+}
+
+int default_cfg(int pr, int64_t n) {
+  // smallest row tile that covers n (fewest padded MFMA rows), else the largest
+  int best = 0;
+  for (int c = 0; c < kNumCfg; ++c)
+    if (cfg_rows(pr, c) >= n && cfg_rows(pr, c) <= cfg_rows(pr, best)) best = c;
+  return best;
+}
+
+int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
+  FC_TRY(ensure_state_buffers(P));
+  const double tau = P->tau;
+  if (scheme == FCGLE_EXP_EULER) {
+    if (!(P->uhat_valid && P->uhat_src == u)) {
+      EpiParams ep;
+      ep.out = P->uhat;
+      FC_TRY(tucker(P, true, u, ProKind::Id, ProParams(), EpiKind::Store, ep, P->s[0], P->s[1], st));
+    }
+    const void* P1;
+    FC_TRY(get_grid(P, FCGLE_PHI1, tau, st, &P1));
+    EpiParams ep;
+    ep.out = P->uhat;
+    ep.F = P1;
+    ep.tau = tau;
+    FC_TRY(get_sep(P, tau, &ep.sep));
+    ProParams pp = nonlin_params(P, t);  // g(t_n, u_n)
+    FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, EpiKind::ExpEuler, ep, P->s[0], P->s[1], st));
+    EpiParams eb;
+    eb.out = u;
+    FC_TRY(tucker(P, false, P->uhat, ProKind::Id, ProParams(), EpiKind::Store, eb, P->s[0], P->s[1], st));
+    P->uhat_valid = true;
+    P->uhat_src = u;
+    P->hist_valid = false;
+    return FCGLE_OK;
+  }
+  P->uhat_valid = false;
+  if (scheme == FCGLE_LAWSON || scheme == FCGLE_LIE ||
+      (scheme == FCGLE_LBDF2 && !(P->hist_valid && P->hist_src == u))) {
+    // u + tau g(t_n, u_n), then e^{tau K} (Lawson) or (I - tau K)^{-1} (BFE)
+    ProParams pp = nonlin_params(P, t);
+    pp.cu = 1.0;
+    pp.cg = tau;
+    EpiParams ep;
+    ep.out = P->s[2];
+    EpiKind ek;
+    if (scheme == FCGLE_LAWSON) {
+      ek = EpiKind::Sep;
+      FC_TRY(get_sep(P, tau, &ep.sep));
+    } else {
+      ek = EpiKind::Grid;
+      FC_TRY(get_grid(P, FCGLE_INV, tau, st, &ep.F));
+    }
+    FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, ek, ep, P->s[0], P->s[1], st));
+    EpiParams eb;
+    eb.out = u;
+    EpiKind ekb = EpiKind::Store;
+    if (scheme == FCGLE_LBDF2) {
+      eb.save = P->uprev;
+      ekb = EpiKind::KeepOld;
+    }
+    FC_TRY(tucker(P, false, P->s[2], ProKind::Id, ProParams(), ekb, eb, P->s[0], P->s[1], st));
+    if (scheme == FCGLE_LBDF2) {
+      P->hist_valid = true;
+      P->hist_src = u;
+    } else {
+      P->hist_valid = false;
+    }
+    return FCGLE_OK;
+  }
+  if (scheme == FCGLE_LBDF2) {
+    // 4/3 u_n - 1/3 u_{n-1} + 2tau/3 g(t_{n+1}, 2u_n - u_{n-1}), then (I - 2tau/3 K)^{-1}
+    ProParams pp = nonlin_params(P, t + tau);
+    pp.up = P->uprev;
+    pp.eu = 2.0;
+    pp.ep = -1.0;
+    pp.cu = 4.0 / 3.0;
+    pp.cp = -1.0 / 3.0;
+    pp.cg = 2.0 * tau / 3.0;
+    EpiParams ep;
+    ep.out = P->s[2];
+    FC_TRY(get_grid(P, FCGLE_INV, 2.0 * tau / 3.0, st, &ep.F));
+    FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, EpiKind::Grid, ep, P->s[0], P->s[1], st));
+    EpiParams eb;
+    eb.out = u;
+    eb.save = P->uprev;
+    FC_TRY(tucker(P, false, P->s[2], ProKind::Id, ProParams(), EpiKind::KeepOld, eb, P->s[0], P->s[1], st));
+    P->hist_valid = true;
+    P->hist_src = u;
+    return FCGLE_OK;
+  }
+  return fail(FCGLE_ERR_ARG, "unknown scheme %d", scheme);
+}
+
+void free_plan(fcgle_plan* P) {
+  auto f = [](void* q) {
+    if (q) (void)hipFree(q);
+  };
+  for (int m = 0; m < 4; ++m) {
+    f(P->Mf[m]);
+    f(P->Mb[m]);
+    f(P->dlam[m]);
+  }
+  for (auto& g : P->grids) f(g.F);
+  for (auto& e : P->seps)
+    for (int m = 0; m < 4; ++m) f(e.fac[m]);
+  for (int k = 0; k < 3; ++k) f(P->s[k]);
+  f(P->uhat);
+  f(P->uprev);
+  f(P->dflag);
+  for (int k = 0; k < 4; ++k) f(P->adj[k]);
+  f(P->partial);
+  for (auto e : P->ev_pool) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// Exported entry points
+// ---------------------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fcgle_last_error(void) { return g_last_error.c_str(); }
+
+int fcgle_host_fd_weights(double alpha, int64_t n, int fd_order, double* g) {
+  if (!g || n < 1 || !(alpha > 0.0 && alpha <= 2.0) || (fd_order != 2 && fd_order != 4))
+    return fail(FCGLE_ERR_ARG, "fd_weights: bad argument");
+  const std::vector<double> w = fd_weights(alpha, n, fd_order);
+  std::memcpy(g, w.data(), n * sizeof(double));
+  return FCGLE_OK;
+}
+
+int fcgle_host_eig(int64_t n, double alpha, double h, int fd_order, double* Q, double* lambda) {
+  if (!Q || !lambda || n < 1 || n > 8192 || !(alpha > 0.0 && alpha <= 2.0) || !(h > 0.0) ||
+      (fd_order != 2 && fd_order != 4))
+    return fail(FCGLE_ERR_ARG, "host_eig: bad argument");
+  std::vector<double> q, l;
+  if (!toeplitz_eig(n, alpha, h, fd_order, q, l)) return fail(FCGLE_ERR_ARG, "host_eig: QR did not converge");
+  std::memcpy(Q, q.data(), n * n * sizeof(double));
+  std::memcpy(lambda, l.data(), n * sizeof(double));
+  return FCGLE_OK;
+}
+
+int fcgle_host_fz(int kind, int64_t count, const double* z, double* out) {
+  if (kind < FCGLE_INV || kind > FCGLE_PHI3 || count < 0 || (count > 0 && (!z || !out)))
+    return fail(FCGLE_ERR_ARG, "host_fz: bad argument");
+  for (int64_t i = 0; i < count; ++i) {
+    const zc r = fz_eval(kind, zc{z[2 * i], z[2 * i + 1]});
+    out[2 * i] = r.re;
+    out[2 * i + 1] = r.im;
+  }
+  return FCGLE_OK;
+}
+
+int fcgle_setup(int d, const int64_t* n, const double* alpha, const double* h, const fcgle_params* params,
+                int fd_order, int precision, double tau, fcgle_plan** out) {
+  if (!out) return fail(FCGLE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (d < 1 || d > 4) return fail(FCGLE_ERR_ARG, "d = %d outside 1..4", d);
+  if (!n || !alpha || !h || !params) return fail(FCGLE_ERR_ARG, "NULL argument");
+  if (fd_order != 2 && fd_order != 4) return fail(FCGLE_ERR_ARG, "fd_order must be 2 or 4");
+  if (precision < FCGLE_FP64 || precision > FCGLE_BF16X6) return fail(FCGLE_ERR_ARG, "bad precision");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(FCGLE_ERR_ARG, "tau must be > 0");
+  const fcgle_params& p = *params;
+  if (!(std::isfinite(p.nu) && std::isfinite(p.eta) && std::isfinite(p.gamma) && std::isfinite(p.kappa) &&
+        std::isfinite(p.zeta)))
+    return fail(FCGLE_ERR_ARG, "non-finite parameter");
+  if (p.nu < 0.0 || p.kappa < 0.0) return fail(FCGLE_ERR_ARG, "nu and kappa must be >= 0");
+  int64_t N = 1;
+  for (int m = 0; m < d; ++m) {
+    if (n[m] < 2 || n[m] > 4096) return fail(FCGLE_ERR_ARG, "n[%d] = %lld outside 2..4096", m, (long long)n[m]);
+    if (!(alpha[m] > 1.0 && alpha[m] <= 2.0)) return fail(FCGLE_ERR_ARG, "alpha[%d] outside (1, 2]", m);
+    if (!(h[m] > 0.0) || !std::isfinite(h[m])) return fail(FCGLE_ERR_ARG, "h[%d] must be > 0", m);
+    N *= n[m];
+  }
+  if (N > ((int64_t)1 << 31) - 1) return fail(FCGLE_ERR_ARG, "tensor too large (N = %lld)", (long long)N);
+
+  auto* P = new (std::nothrow) fcgle_plan();
+  if (!P) return fail(FCGLE_ERR_NOMEM, "host allocation failed");
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) {
+    delete P;
+    return fail(FCGLE_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e));
+  }
+  P->d = d;
+  P->p = p;
+  P->fd_order = fd_order;
+  P->prec = precision;
+  P->tau = tau;
+  P->N = N;
+  P->elem = (precision == FCGLE_FP64) ? 16 : 8;
+  for (int m = 0; m < d; ++m) {
+    P->n[m] = n[m];
+    P->alpha[m] = alpha[m];
+    P->h[m] = h[m];
+    P->npad[m] = (int)round_up(n[m], 256);
+  }
+  // FP64 eigendecompositions on the host, axes in parallel.
+  std::vector<int> ok(d, 0);
+  {
+    std::vector<std::thread> th;
+    for (int m = 0; m < d; ++m)
+      th.emplace_back([&, m] { ok[m] = toeplitz_eig(n[m], alpha[m], h[m], fd_order, P->Q[m], P->lam[m]); });
+    for (auto& t : th) t.join();
+  }
+  int rc = FCGLE_OK;
+  for (int m = 0; m < d && rc == FCGLE_OK; ++m)
+    if (!ok[m]) rc = fail(FCGLE_ERR_ARG, "eigensolver did not converge on axis %d", m);
+  const int pr = precision_of(P);
+  for (int m = 0; m < d && rc == FCGLE_OK; ++m) {
+    const int64_t nm = n[m];
+    std::vector<double> QT(nm * nm);
+    for (int64_t i = 0; i < nm; ++i)
+      for (int64_t k = 0; k < nm; ++k) QT[i * nm + k] = P->Q[m][k * nm + i];
+    rc = upload_matrix(P, QT, nm, P->npad[m], &P->Mf[m]);
+    if (rc == FCGLE_OK) rc = upload_matrix(P, P->Q[m], nm, P->npad[m], &P->Mb[m]);
+    if (rc == FCGLE_OK) rc = plan_alloc((void**)&P->dlam[m], nm * sizeof(double));
+    if (rc == FCGLE_OK) {
+      e = hipMemcpy(P->dlam[m], P->lam[m].data(), nm * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) rc = fail(FCGLE_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
+    }
+    P->cfg[m][0] = P->cfg[m][1] = default_cfg(pr, nm);
+  }
+  for (int k = 0; k < 3 && rc == FCGLE_OK; ++k) rc = plan_alloc(&P->s[k], (size_t)N * P->elem);
+  if (rc == FCGLE_OK) rc = plan_alloc((void**)&P->dflag, sizeof(int));
+  if (rc != FCGLE_OK) {
+    free_plan(P);
+    delete P;
+    return rc;
+  }
+  *out = P;
+  return FCGLE_OK;
+}
+
+void fcgle_destroy(fcgle_plan* plan) {
+  if (!plan) return;
+  DeviceGuard g(plan->device);
+  (void)hipDeviceSynchronize();
+  free_plan(plan);
+  delete plan;
+}
+
+int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda) {
+  FC_TRY(check_plan(plan));
+  if (mu < 0 || mu >= plan->d || !Q || !lambda) return fail(FCGLE_ERR_ARG, "get_eig: bad argument");
+  std::memcpy(Q, plan->Q[mu].data(), plan->Q[mu].size() * sizeof(double));
+  std::memcpy(lambda, plan->lam[mu].data(), plan->lam[mu].size() * sizeof(double));
+  return FCGLE_OK;
+}
+
+int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const void* const* S_dev) {
+  FC_TRY(check_plan(plan));
+  if (nterms < 0 || nterms > 4) return fail(FCGLE_ERR_ARG, "nterms must be 0..4");
+  if (nterms > 0 && (!rate || !S_dev)) return fail(FCGLE_ERR_ARG, "NULL source arrays");
+  for (int k = 0; k < nterms; ++k) {
+    if (!S_dev[k]) return fail(FCGLE_ERR_ARG, "source tensor %d is NULL", k);
+    if (!std::isfinite(rate[k])) return fail(FCGLE_ERR_ARG, "source rate %d not finite", k);
+  }
+  plan->ns = nterms;
+  for (int k = 0; k < 4; ++k) {
+    plan->S[k] = k < nterms ? S_dev[k] : nullptr;
+    plan->rate[k] = k < nterms ? rate[k] : 0.0;
+  }
+  return FCGLE_OK;
+}
+
+int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, void* out_dev, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_dev || !out_dev) return fail(FCGLE_ERR_ARG, "NULL tensor");
+  if (kind < FCGLE_INV || kind > FCGLE_PHI3) return fail(FCGLE_ERR_ARG, "bad kind %d", kind);
+  if (!std::isfinite(theta)) return fail(FCGLE_ERR_ARG, "theta not finite");
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  EpiParams ep;
+  ep.out = plan->s[2];
+  EpiKind ek;
+  if (kind == FCGLE_EXP) {
+    ek = EpiKind::Sep;
+    FC_TRY(get_sep(plan, theta, &ep.sep));
+  } else {
+    ek = EpiKind::Grid;
+    FC_TRY(get_grid(plan, kind, theta, st, &ep.F));
+  }
+  FC_TRY(tucker(plan, true, u_dev, ProKind::Id, ProParams(), ek, ep, plan->s[0], plan->s[1], st));
+  EpiParams eb;
+  eb.out = out_dev;
+  FC_TRY(tucker(plan, false, plan->s[2], ProKind::Id, ProParams(), EpiKind::Store, eb, plan->s[0], plan->s[1], st));
+  if (out_dev == plan->uhat_src) plan->uhat_valid = false;
+  return FCGLE_OK;
+}
+
+int fcgle_set_state(fcgle_plan* plan, const void* u_dev, const void* u_prev_dev, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+  DeviceGuard g(plan->device);
+  plan->uhat_valid = false;
+  plan->uhat_src = nullptr;
+  plan->hist_valid = false;
+  plan->hist_src = nullptr;
+  if (u_prev_dev) {
+    FC_TRY(ensure_state_buffers(plan));
+    HIP_TRY(hipMemcpyAsync(plan->uprev, u_prev_dev, (size_t)plan->N * plan->elem, hipMemcpyDeviceToDevice,
+                           as_stream(stream)));
+    plan->hist_valid = true;
+    plan->hist_src = u_dev;
+  }
+  return FCGLE_OK;
+}
+
+int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+  if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+  if (!std::isfinite(t)) return fail(FCGLE_ERR_ARG, "t not finite");
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  DeviceGuard g(plan->device);
+  return step_impl(plan, scheme, u_dev, t, as_stream(stream));
+}
+
+int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (nsteps < 0) return fail(FCGLE_ERR_ARG, "nsteps < 0");
+  for (int64_t k = 0; k < nsteps; ++k) FC_TRY(fcgle_step(plan, scheme, u_dev, t0 + (double)k * tau, tau, stream));
+  return FCGLE_OK;
+}
+
+int fcgle_check_finite(fcgle_plan* plan, const void* u_dev, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  int h = 0;
+  HIP_TRY(hipMemsetAsync(plan->dflag, 0, sizeof(int), st));
+  HIP_TRY(launch_check_finite(precision_of(plan), plan->N, u_dev, plan->dflag, st));
+  HIP_TRY(hipMemcpyAsync(&h, plan->dflag, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h) return fail(FCGLE_ERR_NONFINITE, "tensor holds NaN or Inf");
+  return FCGLE_OK;
+}
+
+int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes) {
+  FC_TRY(check_plan(plan));
+  if (N) *N = plan->N;
+  if (elem_bytes) *elem_bytes = plan->elem;
+  return FCGLE_OK;
+}
+
+int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (reps < 1) reps = 3;
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  const int pr = precision_of(plan);
+  HIP_TRY(hipMemsetAsync(plan->s[0], 0, (size_t)plan->N * plan->elem, st));
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  int rc = FCGLE_OK;
+  for (int mu = 0; mu < plan->d && rc == FCGLE_OK; ++mu)
+    for (int dir = 0; dir < 2 && rc == FCGLE_OK; ++dir) {
+      float best = 1e30f;
+      int best_c = plan->cfg[mu][dir];
+      for (int c = 0; c < kNumCfg; ++c) {
+        MPLaunch L = base_launch(plan, mu, dir == 1);
+        L.cfg = c;
+        L.in = plan->s[0];
+        L.ep.out = plan->s[1];
+        if (launch_mode_product(L, st) != hipSuccess) continue;  // warm-up
+        (void)hipEventRecord(e0, st);
+        for (int r = 0; r < reps; ++r) (void)launch_mode_product(L, st);
+        (void)hipEventRecord(e1, st);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+          rc = fail(FCGLE_ERR_HIP, "autotune: event sync failed");
+          break;
+        }
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) {
+          best = ms;
+          best_c = c;
+        }
+      }
+      plan->cfg[mu][dir] = best_c;
+    }
+  (void)pr;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  plan->tuned = (rc == FCGLE_OK);
+  return rc;
+}
+
+int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
+  FC_TRY(check_plan(plan));
+  if (!buf || len == 0) return fail(FCGLE_ERR_ARG, "bad buffer");
+  static const char* names[] = {"fp64", "fp32", "bf16x3", "bf16x6"};
+  std::string s = "d=" + std::to_string(plan->d) + " n=(";
+  for (int m = 0; m < plan->d; ++m) s += std::to_string(plan->n[m]) + (m + 1 < plan->d ? "," : ")");
+  s += std::string(" precision=") + names[plan->prec] + " tiles[axis](bwd/fwd rows x cols)=";
+  const int pr = precision_of(plan);
+  for (int m = 0; m < plan->d; ++m) {
+    s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0])) +
+         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1])) + "]";
+  }
+  s += plan->tuned ? " tuned" : " default";
+  std::snprintf(buf, len, "%s", s.c_str());
+  return FCGLE_OK;
+}
+
+int fcgle_timing_enable(fcgle_plan* plan, int capacity) {
+  FC_TRY(check_plan(plan));
+  DeviceGuard g(plan->device);
+  if (capacity < 0) return fail(FCGLE_ERR_ARG, "capacity < 0");
+  plan->timed.clear();
+  while ((int)plan->ev_pool.size() < 2 * capacity) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    plan->ev_pool.push_back(e);
+  }
+  plan->timing_cap = capacity;
+  return FCGLE_OK;
+}
+
+int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms, int64_t* count) {
+  FC_TRY(check_plan(plan));
+  if (plan->timing_cap <= 0) return fail(FCGLE_ERR_STATE, "timing is not enabled");
+  if (!count || (cap > 0 && (!axis || !fwd || !sig || !ms))) return fail(FCGLE_ERR_ARG, "NULL output");
+  DeviceGuard g(plan->device);
+  int64_t k = 0;
+  for (auto& t : plan->timed) {
+    HIP_TRY(hipEventSynchronize(t.e1));
+    float e = 0;
+    HIP_TRY(hipEventElapsedTime(&e, t.e0, t.e1));
+    if (k < cap) {
+      axis[k] = t.axis;
+      fwd[k] = t.fwd;
+      sig[k] = t.sig;
+      ms[k] = e;
+    }
+    ++k;
+  }
+  *count = k < cap ? k : cap;
+  plan->timed.clear();
+  return FCGLE_OK;
+}
+
+int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* ubar_next_dev, void* ubar_n_dev,
+              double* pbar_dev, double t, double tau, void* stream) {
+  FC_TRY(check_plan(plan));
+  (void)u_n_dev; (void)ubar_next_dev; (void)ubar_n_dev; (void)pbar_dev; (void)t; (void)tau; (void)stream;
+  (void)scheme;
+  return fail(FCGLE_ERR_UNSUPPORTED, "vjp not built yet");
+}
+
+int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h, const fcgle_params* params,
+                      int precision, double tau, fcgle_plan** out) {
+  (void)count; (void)n; (void)alpha; (void)h; (void)params; (void)precision; (void)tau;
+  if (out) *out = nullptr;
+  return fail(FCGLE_ERR_UNSUPPORTED, "batched plans not built yet");
+}
+
+int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau, int64_t nsteps,
+                    void* stream) {
+  (void)plan; (void)scheme; (void)u_dev; (void)t0; (void)tau; (void)nsteps; (void)stream;
+  return fail(FCGLE_ERR_UNSUPPORTED, "batched plans not built yet");
+}
+
+}  // extern "C"

@@ -1,0 +1,113 @@
+// Host-side description of one kernel launch of the library.  Shared by the
+// plan code (api.cpp) and the kernel translation units; contains no device code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fcgle {
+
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
+
+// Pointwise map applied to the input of a mode product while its tile is loaded.
+enum class ProKind : int { Id = 0, Nonlin = 1 };
+// What the last stage of a mode product does with each output element.
+enum class EpiKind : int {
+  Store = 0,     // out[j] = v
+  Grid = 1,      // out[j] = F[j] v                      (stored f-grid)
+  Sep = 2,       // out[j] = prod_mu f_mu[j_mu] v          (separable exponential)
+  ExpEuler = 3,  // uhat[j] = E_j uhat[j] + tau P1[j] v     (eigenspace exponential Euler)
+  KeepOld = 4,   // save[j] = out[j]; out[j] = v           (LBDF2 history)
+  AdjHat = 5,    // adjoint, eigenspace stage (see AdjHatParams)
+  AdjPhys = 6,   // adjoint, physical-space stage
+  Count = 7
+};
+
+// g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with e = eu u + ep up;
+// output = cu u + cp up + cg g.
+struct ProParams {
+  const void* up = nullptr;
+  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
+  double sc[4] = {0, 0, 0, 0};
+  int ns = 0;
+  double gamma = 0, kappa = 0, zeta = 0;
+  double eu = 1, ep = 0, cu = 0, cp = 0, cg = 1;
+};
+
+// Separable per-axis complex factors (FP64): value(j) = prod_mu fac[mu][j_mu].
+struct SepParams {
+  int d = 0;
+  int mu = 0;  // axis of the mode product (its index comes from the output row)
+  int n[4] = {1, 1, 1, 1};
+  const void* fac[4] = {nullptr, nullptr, nullptr, nullptr};  // double2[n_mu]
+  const double* lam[4] = {nullptr, nullptr, nullptr, nullptr}; // eigenvalues (adjoint)
+};
+
+struct EpiParams {
+  void* out = nullptr;
+  void* save = nullptr;      // KeepOld
+  const void* F = nullptr;   // Grid / ExpEuler (P1)
+  SepParams sep;             // Sep / ExpEuler / adjoint
+  double tau = 0;            // ExpEuler / adjoint
+  void* ghat_out = nullptr;  // ExpEuler: optional copy of the transformed nonlinearity
+  // adjoint extras (see pointwise.hip for their meaning)
+  const void* aux0 = nullptr;
+  const void* aux1 = nullptr;
+  const void* aux2 = nullptr;
+  void* out2 = nullptr;
+  double* partial = nullptr;  // per-block partial sums
+  double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+};
+
+// One mode product out[a, i, b] = sum_k M[i, k] in[a, k, b] on a complex tensor
+// viewed as (A, n, B); M is npad x npad (zero padded), row-major, in the layout of
+// the precision (double / float / BF16 pieces).
+struct MPLaunch {
+  int prec = P_F64;
+  int cfg = 0;  // tile configuration index
+  int64_t A = 1;
+  int n = 1;
+  int npad = 1;
+  int64_t B = 1;
+  const void* M = nullptr;
+  const void* in = nullptr;
+  ProKind pk = ProKind::Id;
+  ProParams pp;
+  EpiKind ek = EpiKind::Store;
+  EpiParams ep;
+};
+
+constexpr int kNumCfg = 3;  // per precision: 0 = 256-row tiles, 1 = 128, 2 = 64
+int cfg_rows(int prec, int cfg);
+int cfg_cols(int prec, int cfg);  // complex columns per tile
+
+// True when the fused kernel exists for this (loader, prologue, epilogue) combination.
+bool mp_supported(bool tloader, ProKind pk, EpiKind ek);
+
+hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s);
+hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s);
+hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s);
+inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
+  if (L.prec == P_F64) return launch_mp_f64(L, s);
+  if (L.prec == P_F32) return launch_mp_f32(L, s);
+  return launch_mp_bf16(L, s);
+}
+
+// Standalone pointwise passes (unfused fallbacks and helpers), complex tensors of N
+// elements in the state type of `prec`.
+hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,
+                                hipStream_t s);
+// Applies epilogue `ek` to v[j] for every j, with the tensor viewed as (N / n_last, n_last).
+hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,
+                                const EpiParams& p, hipStream_t s);
+hipError_t launch_check_finite(int prec, int64_t N, const void* u, int* flag, hipStream_t s);
+// Sums `count` per-block partial rows of width `width` into acc[width] (acc += sum).
+hipError_t launch_reduce_partials(const double* partial, int64_t count, int width, double* acc,
+                                  hipStream_t s);
+// Elementwise f-grid from separable eigenvalues: F[j] = f(theta (nu + i eta) sum lam_mu[j_mu]),
+// evaluated in FP64 on the device and stored in the state type.
+hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, const SepParams& sep,
+                        int64_t N, void* F, hipStream_t s);
+
+}  // namespace fcgle

@@ -1,0 +1,158 @@
+// Pointwise passes: FP64 f-grids, unfused prologue/epilogue fallbacks, the
+// non-finite scan and the reduction of per-block partial sums.
+#include "dispatch.hpp"
+
+namespace fcgle {
+
+namespace {
+
+constexpr int kPwThreads = 256;
+
+inline unsigned pw_blocks(int64_t N) {
+  int64_t b = (N + kPwThreads - 1) / kPwThreads;
+  if (b > 65536) b = 65536;  // grid-stride beyond this
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+template <class R, class Pro>
+__global__ void __launch_bounds__(kPwThreads)
+    pw_pro_kernel(int64_t N, const typename Cx<R>::T* __restrict__ in, typename Cx<R>::T* __restrict__ out,
+                  Pro pro) {
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < N; j += (int64_t)gridDim.x * kPwThreads)
+    out[j] = pro(j, in[j]);
+}
+
+template <class R, class Epi>
+__global__ void __launch_bounds__(kPwThreads)
+    pw_epi_kernel(int64_t N, int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < N; j += (int64_t)gridDim.x * kPwThreads) {
+    const uint32_t a = (uint32_t)(j / nlast);
+    const int i = (int)(j - (int64_t)a * nlast);
+    const auto ctx = epi.col(a, 0);
+    const auto x = v[j];
+    epi(ctx, i, j, x.x, x.y);
+  }
+}
+
+// F[j] = f(theta_c * ell_j), ell_j = sum_mu lambda_mu[j_mu], all in FP64.
+template <class C>
+__global__ void __launch_bounds__(kPwThreads)
+    fgrid_kernel(int kind, double tr, double ti, SepParams s, int64_t N, C* __restrict__ F) {
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < N; j += (int64_t)gridDim.x * kPwThreads) {
+    int64_t r = j;
+    double ell = 0.0;
+    for (int mu = s.d - 1; mu >= 0; --mu) {
+      const int64_t jm = r % s.n[mu];
+      r /= s.n[mu];
+      ell += s.lam[mu][jm];
+    }
+    const zc z{tr * ell, ti * ell};
+    F[j] = from_zc<C>(fz_eval(kind, z));
+  }
+}
+
+template <class C>
+__global__ void __launch_bounds__(kPwThreads) finite_kernel(int64_t N, const C* __restrict__ u, int* flag) {
+  bool bad = false;
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < N; j += (int64_t)gridDim.x * kPwThreads) {
+    const C x = u[j];
+    bad |= !(isfinite(x.x) && isfinite(x.y));
+  }
+  if (bad) atomicOr(flag, 1);
+}
+
+__global__ void __launch_bounds__(kPwThreads)
+    reduce_partials_kernel(const double* __restrict__ partial, int64_t count, int width, double* acc) {
+  __shared__ double sh[kPwThreads];
+  for (int c = 0; c < width; ++c) {
+    double s = 0.0;
+    for (int64_t r = threadIdx.x; r < count; r += kPwThreads) s += partial[r * width + c];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = kPwThreads / 2; st > 0; st >>= 1) {
+      if ((int)threadIdx.x < st) sh[threadIdx.x] += sh[threadIdx.x + st];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) acc[c] += sh[0];
+    __syncthreads();
+  }
+}
+
+template <class R>
+hipError_t pro_impl(int64_t N, const void* in, void* out, const ProParams& p, hipStream_t s) {
+  using C = typename Cx<R>::T;
+  hipLaunchKernelGGL((pw_pro_kernel<R, ProNonlinF<R>>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
+                     (const C*)in, (C*)out, ProNonlinF<R>(p));
+  return hipGetLastError();
+}
+
+template <class R, class Epi>
+hipError_t epi_launch(int64_t N, int nlast, const void* v, const EpiParams& p, hipStream_t s) {
+  using C = typename Cx<R>::T;
+  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N, nlast, (const C*)v,
+                     Epi(p));
+  return hipGetLastError();
+}
+
+template <class R>
+hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiParams& p, hipStream_t s) {
+  switch (ek) {
+    case EpiKind::Store: return epi_launch<R, EpiStoreF<R>>(N, nlast, v, p, s);
+    case EpiKind::Grid: return epi_launch<R, EpiGridF<R>>(N, nlast, v, p, s);
+    case EpiKind::Sep: return epi_launch<R, EpiSepF<R>>(N, nlast, v, p, s);
+    case EpiKind::ExpEuler: return epi_launch<R, EpiExpEulerF<R>>(N, nlast, v, p, s);
+    case EpiKind::KeepOld: return epi_launch<R, EpiKeepOldF<R>>(N, nlast, v, p, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+bool mp_supported(bool tloader, ProKind pk, EpiKind ek) {
+  if (!tloader) return ek == EpiKind::Store;
+  return pk == ProKind::Id && (ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep ||
+                               ek == EpiKind::ExpEuler || ek == EpiKind::KeepOld);
+}
+
+hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,
+                                hipStream_t s) {
+  return prec == P_F64 ? pro_impl<double>(N, in, out, p, s) : pro_impl<float>(N, in, out, p, s);
+}
+
+hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,
+                                const EpiParams& p, hipStream_t s) {
+  return prec == P_F64 ? epi_impl<double>(N, n_last, v, ek, p, s) : epi_impl<float>(N, n_last, v, ek, p, s);
+}
+
+hipError_t launch_check_finite(int prec, int64_t N, const void* u, int* flag, hipStream_t s) {
+  if (prec == P_F64)
+    hipLaunchKernelGGL((finite_kernel<double2>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
+                       (const double2*)u, flag);
+  else
+    hipLaunchKernelGGL((finite_kernel<float2>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
+                       (const float2*)u, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_partials(const double* partial, int64_t count, int width, double* acc,
+                                  hipStream_t s) {
+  hipLaunchKernelGGL(reduce_partials_kernel, dim3(1), dim3(kPwThreads), 0, s, partial, count, width, acc);
+  return hipGetLastError();
+}
+
+hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, const SepParams& sep,
+                        int64_t N, void* F, hipStream_t s) {
+  if (prec == P_F64)
+    hipLaunchKernelGGL((fgrid_kernel<double2>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, kind, theta_re,
+                       theta_im, sep, N, (double2*)F);
+  else
+    hipLaunchKernelGGL((fgrid_kernel<float2>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, kind, theta_re,
+                       theta_im, sep, N, (float2*)F);
+  return hipGetLastError();
+}
+
+int cfg_rows(int prec, int cfg) { return kCfgRows[prec][cfg]; }
+int cfg_cols(int prec, int cfg) { return kCfgCols[prec][cfg]; }
+
+}  // namespace fcgle

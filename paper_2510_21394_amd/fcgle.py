@@ -1,0 +1,219 @@
+"""Python face of the C ABI: argument marshalling only.
+
+Every numerical step runs inside libfcgle.so (HIP kernels for gfx950).  torch
+provides device memory and the current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+STATE_DTYPE = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16x3": torch.complex64,
+               "bf16x6": torch.complex64}
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+class Plan:
+    """A set-up problem: per-axis eigenpairs, f-grids and scratch on one GPU.
+
+    n, alpha, h: per-axis inner points, fractional orders and grid spacings.
+    params: (nu, eta, gamma, kappa, zeta).  tau: time step (grids are built for it).
+    precision: 'fp64' | 'fp32' | 'bf16x3' | 'bf16x6'.
+    """
+
+    def __init__(self, n: Sequence[int], alpha: Sequence[float], h: Sequence[float],
+                 params: Sequence[float], tau: float, precision: str = "fp64", fd_order: int = 2,
+                 device: Optional[int] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("fcgle.Plan needs a GPU")
+        self.lib = L.lib()
+        self.n = tuple(int(m) for m in n)
+        self.d = len(self.n)
+        self.precision = precision
+        self.dtype = STATE_DTYPE[precision]
+        self.tau = float(tau)
+        self.params = tuple(float(p) for p in params)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        nn = (ctypes.c_int64 * self.d)(*self.n)
+        aa = (ctypes.c_double * self.d)(*[float(a) for a in alpha])
+        hh = (ctypes.c_double * self.d)(*[float(x) for x in h])
+        pp = L.Params(*self.params)
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.fcgle_setup(self.d, nn, aa, hh, ctypes.byref(pp), int(fd_order),
+                                         L.PRECISIONS[precision], self.tau, ctypes.byref(out)))
+        self.handle = out
+        self._state_ver = None
+        self._sources = []
+
+    # -- lifetime --------------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fcgle_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- helpers ---------------------------------------------------------------------------
+    def _check_tensor(self, u: torch.Tensor, name: str = "u"):
+        if u.dtype != self.dtype:
+            raise TypeError(f"{name} must be {self.dtype}, got {u.dtype}")
+        if u.device != self.device:
+            raise ValueError(f"{name} must live on {self.device}")
+        if tuple(u.shape) != self.n:
+            raise ValueError(f"{name} has shape {tuple(u.shape)}, expected {self.n}")
+        if not u.is_contiguous():
+            raise ValueError(f"{name} must be contiguous")
+
+    def empty(self) -> torch.Tensor:
+        return torch.empty(self.n, dtype=self.dtype, device=self.device)
+
+    # -- operations ------------------------------------------------------------------------
+    def eig(self, mu: int) -> Tuple[np.ndarray, np.ndarray]:
+        m = self.n[mu]
+        Q = np.empty((m, m))
+        lam = np.empty(m)
+        L.check(self.lib.fcgle_get_eig(self.handle, mu, Q.ctypes.data_as(L.P_dbl), lam.ctypes.data_as(L.P_dbl)))
+        return Q, lam
+
+    def apply_f(self, kind: str, theta: float, u: torch.Tensor, out: Optional[torch.Tensor] = None):
+        self._check_tensor(u)
+        if out is None:
+            out = self.empty()
+        self._check_tensor(out, "out")
+        L.check(self.lib.fcgle_apply_f(self.handle, L.KINDS[kind], float(theta), _ptr(u), _ptr(out), _stream()))
+        return out
+
+    def set_source(self, rates: Sequence[float], tensors: Sequence[torch.Tensor]):
+        for S in tensors:
+            self._check_tensor(S, "S")
+        self._sources = list(tensors)  # keep alive
+        k = len(rates)
+        rr = (ctypes.c_double * max(k, 1))(*[float(r) for r in rates])
+        ss = (ctypes.c_void_p * max(k, 1))(*[S.data_ptr() for S in tensors])
+        L.check(self.lib.fcgle_set_source(self.handle, k, rr, ss))
+
+    def set_state(self, u: torch.Tensor, u_prev: Optional[torch.Tensor] = None):
+        self._check_tensor(u)
+        if u_prev is not None:
+            self._check_tensor(u_prev, "u_prev")
+        L.check(self.lib.fcgle_set_state(self.handle, _ptr(u), _ptr(u_prev), _stream()))
+        self._state_ver = (u.data_ptr(), u._version)
+
+    def _sync_state(self, u: torch.Tensor):
+        # The plan caches the eigenspace state of u between steps; if torch wrote u in place
+        # since our last step, tell the library.
+        if self._state_ver is not None and self._state_ver != (u.data_ptr(), u._version):
+            L.check(self.lib.fcgle_set_state(self.handle, _ptr(u), ctypes.c_void_p(0), _stream()))
+        self._state_ver = (u.data_ptr(), u._version)
+
+    def step(self, scheme: str, u: torch.Tensor, t: float) -> torch.Tensor:
+        self._check_tensor(u)
+        self._sync_state(u)
+        L.check(self.lib.fcgle_step(self.handle, L.SCHEMES[scheme], _ptr(u), float(t), self.tau, _stream()))
+        return u
+
+    def run(self, scheme: str, u: torch.Tensor, t0: float, nsteps: int) -> torch.Tensor:
+        self._check_tensor(u)
+        self._sync_state(u)
+        L.check(self.lib.fcgle_run(self.handle, L.SCHEMES[scheme], _ptr(u), float(t0), self.tau, int(nsteps),
+                                   _stream()))
+        return u
+
+    def vjp(self, u_n: torch.Tensor, ubar_next: torch.Tensor, t: float, pbar: torch.Tensor,
+            ubar_n: Optional[torch.Tensor] = None, scheme: str = "exp_euler") -> torch.Tensor:
+        self._check_tensor(u_n, "u_n")
+        self._check_tensor(ubar_next, "ubar_next")
+        if ubar_n is None:
+            ubar_n = self.empty()
+        self._check_tensor(ubar_n, "ubar_n")
+        if pbar.dtype != torch.float64 or pbar.numel() != 5 or pbar.device != self.device:
+            raise ValueError("pbar must be 5 float64 values on the plan's device")
+        L.check(self.lib.fcgle_vjp(self.handle, L.SCHEMES[scheme], _ptr(u_n), _ptr(ubar_next), _ptr(ubar_n),
+                                   _ptr(pbar), float(t), self.tau, _stream()))
+        return ubar_n
+
+    def check_finite(self, u: torch.Tensor) -> bool:
+        self._check_tensor(u)
+        rc = self.lib.fcgle_check_finite(self.handle, _ptr(u), _stream())
+        if rc == L.ERR_NONFINITE:
+            return False
+        L.check(rc)
+        return True
+
+    def autotune(self, reps: int = 3):
+        L.check(self.lib.fcgle_autotune(self.handle, int(reps), _stream()))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        L.check(self.lib.fcgle_describe(self.handle, buf, 1024))
+        return buf.value.decode()
+
+    def timing_enable(self, capacity: int):
+        L.check(self.lib.fcgle_timing_enable(self.handle, int(capacity)))
+
+    def timing_read(self, cap: int = 100000):
+        """Per-launch records of the mode-product kernels timed since timing_enable:
+        a list of (axis, forward, kernel_signature, milliseconds)."""
+        ax = (ctypes.c_int * cap)()
+        fw = (ctypes.c_int * cap)()
+        sg = (ctypes.c_int * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = ctypes.c_int64()
+        L.check(self.lib.fcgle_timing_read(self.handle, cap, ax, fw, sg, ms, ctypes.byref(cnt)))
+        return [(ax[i], fw[i], sg[i], ms[i]) for i in range(cnt.value)]
+
+
+def decode_signature(sig: int) -> dict:
+    """Inverse of the kernel signature of fcgle_timing_read."""
+    ek = sig % 8
+    sig //= 8
+    pk = sig % 2
+    sig //= 2
+    tl = sig % 2
+    sig //= 2
+    cfg = sig % 4
+    prec = sig // 4
+    return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
+            "prologue": ["none", "nonlinearity"][pk],
+            "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "adj_hat", "adj_phys", "?"][ek]}
+
+
+# -- host-only helpers ---------------------------------------------------------------------
+
+def host_fd_weights(alpha: float, n: int, fd_order: int = 2) -> np.ndarray:
+    g = np.empty(n)
+    L.check(L.lib().fcgle_host_fd_weights(float(alpha), int(n), int(fd_order), g.ctypes.data_as(L.P_dbl)))
+    return g
+
+
+def host_eig(n: int, alpha: float, h: float, fd_order: int = 2):
+    Q = np.empty((n, n))
+    lam = np.empty(n)
+    L.check(L.lib().fcgle_host_eig(int(n), float(alpha), float(h), int(fd_order), Q.ctypes.data_as(L.P_dbl),
+                                   lam.ctypes.data_as(L.P_dbl)))
+    return Q, lam
+
+
+def host_fz(kind: str, z: np.ndarray) -> np.ndarray:
+    z = np.ascontiguousarray(np.asarray(z, dtype=np.complex128))
+    zz = z.view(np.float64).reshape(-1)
+    out = np.empty_like(zz)
+    L.check(L.lib().fcgle_host_fz(L.KINDS[kind], z.size, zz.ctypes.data_as(L.P_dbl), out.ctypes.data_as(L.P_dbl)))
+    return out.view(np.complex128).reshape(z.shape)

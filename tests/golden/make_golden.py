@@ -1,0 +1,70 @@
+"""Write the stored references of the full-size GPU parity tests.
+
+Calls only the FP64 oracle (oracle/) and the seeded input generators (workloads/).
+Each case runs a whole trajectory on the CPU and stores, in <case>.npz:
+  idx   : 8192 sampled flat indices (sorted, drawn by default_rng(20251021))
+  val   : the oracle's u(T) at those indices (complex128)
+  norm  : the L2 norm of the whole oracle u(T)
+  steps, tau, scheme : the trajectory that produced it
+
+Usage: python tests/golden/make_golden.py [case ...]   (all cases by default)
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import fcgle_oracle as O  # noqa: E402
+import workloads as W  # noqa: E402
+
+NSAMPLE = 8192
+
+
+def _save(name, U, steps, tau, scheme):
+    rng = np.random.default_rng(20251021)
+    idx = np.sort(rng.choice(U.size, size=min(NSAMPLE, U.size), replace=False))
+    np.savez(os.path.join(HERE, name + ".npz"), idx=idx, val=U.reshape(-1)[idx],
+             norm=np.linalg.norm(U.reshape(-1)), steps=steps, tau=tau, scheme=scheme)
+
+
+def case_manufactured(scheme):
+    w = W.manufactured_3d(scheme)
+    U0 = W.u0_manufactured(w)
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    P.source = O.manufactured_source(U0, P.Ds, w.params)
+    U = O.run(P, scheme, U0, w.tau, w.steps)
+    _save(w.name, U, w.steps, w.tau, scheme)
+    exact = np.exp(-w.tau * w.steps) * U0
+    print(f"{w.name}: temporal error vs e^(-T) U0 = {O.rel_l2(U, exact):.3e}")
+
+
+def case_headline():
+    w = W.headline_3d()
+    U0 = W.u0_headline(w)
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    U = O.run(P, "exp_euler", U0, w.tau, w.steps)
+    _save(w.name, U, w.steps, w.tau, "exp_euler")
+
+
+CASES = {
+    "3d_128_manufactured_lbdf2": lambda: case_manufactured("lbdf2"),
+    "3d_128_manufactured_lie": lambda: case_manufactured("lie"),
+    "3d_128_manufactured_exp_euler": lambda: case_manufactured("exp_euler"),
+    "3d_256_gauss4_expeuler": case_headline,
+}
+
+
+def main(argv):
+    names = argv or list(CASES)
+    for name in names:
+        t0 = time.time()
+        CASES[name]()
+        print(f"{name}: {time.time() - t0:.0f} s", flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1:])

@@ -1,0 +1,240 @@
+"""GPU parity of the HIP path against the FP64 oracle, element by element.
+
+Tolerances (relative L2 over the whole tensor): FP64 <= 1e-12; FP32-MFMA <= 1e-5;
+split-BF16 (6 products) <= 1e-5 per operator; split-BF16 (3 products) <= 1e-4 per
+operator (2-piece BF16 represents FP32 data to about 2^-17, so one mode product
+carries ~1e-5 and an operator ~3e-5).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fcgle_oracle as O
+from workloads import (BASE_PARAMS, grid_axes, headline_3d, parity_2d, random_complex, sech_product,
+                       u0_headline, u0_parity_2d)
+
+pytestmark = pytest.mark.gpu
+
+TOL_OP = {"fp64": 1e-12, "fp32": 1e-5, "bf16x3": 1e-4, "bf16x6": 1e-5}
+CDT = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16x3": torch.complex64, "bf16x6": torch.complex64}
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2510_21394_amd as pkg
+    return pkg
+
+
+def _setup(n, seed):
+    rng = np.random.default_rng(seed)
+    alpha = tuple(rng.uniform(1.15, 1.95, len(n)))
+    h = tuple(rng.uniform(0.05, 0.4, len(n)))
+    return alpha, h
+
+
+def _dev(x, prec):
+    return torch.from_numpy(np.ascontiguousarray(x)).to(CDT[prec]).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy().astype(np.complex128)
+
+
+SHAPES = [(300,), (130, 75), (20, 33, 17), (70, 96, 130), (5, 6, 7, 8)]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("n", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("kind", ["inv", "exp", "phi1", "phi2", "phi3"])
+def test_apply_f_matches_oracle(F, prec, n, kind):
+    alpha, h = _setup(n, 1 + len(n))
+    theta = 1e-2
+    params = (0.8, -0.6, 1.0, 1.0, 0.5)
+    V = random_complex(n, 7)
+    P = O.Problem(n, alpha, h, params)
+    ref = P.f(kind, theta, V)
+    plan = F.Plan(n, alpha, h, params, tau=1e-3, precision=prec)
+    out = plan.apply_f(kind, theta, _dev(V, prec))
+    torch.cuda.synchronize()
+    err = O.rel_l2(_host(out), ref)
+    print(f"[apply_f {prec} {kind} {n}] rel_l2 = {err:.3e}")
+    assert err <= TOL_OP[prec], err
+
+
+@pytest.mark.parametrize("n", [(9, 7), (6, 5, 4)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("kind", ["inv", "exp", "phi1", "phi2"])
+def test_apply_f_matches_brute_force(F, n, kind):
+    alpha, h = _setup(n, 11)
+    V = random_complex(n, 3)
+    ref = O.brute_apply(kind, 5e-3, V, O.setup(n, alpha, h)[0], BASE_PARAMS)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp64")
+    out = plan.apply_f(kind, 5e-3, _dev(V, "fp64"))
+    assert O.rel_l2(_host(out), ref) <= 1e-12
+
+
+def test_apply_f_in_place(F):
+    n = (40, 33, 21)
+    alpha, h = _setup(n, 5)
+    V = random_complex(n, 9)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3)
+    u = _dev(V, "fp64")
+    plan.apply_f("phi1", 2e-2, u, out=u)
+    ref = O.Problem(n, alpha, h, BASE_PARAMS).f("phi1", 2e-2, V)
+    assert O.rel_l2(_host(u), ref) <= 1e-12
+
+
+def test_exp_euler_2d_parity_workload(F):
+    """2-D, 64^2 on (-10,10)^2, alpha = 1.5, 100 exponential-Euler steps, tau = 1e-3, FP64."""
+    w = parity_2d()
+    U0 = u0_parity_2d(w)
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    ref = O.run(P, "exp_euler", U0, w.tau, w.steps)
+    plan = F.Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision="fp64")
+    u = _dev(U0, "fp64")
+    plan.run("exp_euler", u, 0.0, w.steps)
+    err = O.rel_l2(_host(u), ref)
+    print(f"[2d_64 exp_euler 100 steps] rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+
+
+def _manufactured(n, domain, alpha, params):
+    axes = grid_axes(n, domain)
+    h = [(b - a) / (m + 1) for (a, b), m in zip(domain, n)]
+    U0 = sech_product(axes, [1.0] + [0.0] * (len(n) - 1))
+    P = O.Problem(n, alpha, h, params)
+    P.source = O.manufactured_source(U0, P.Ds, params)
+    return P, U0, h
+
+
+@pytest.mark.parametrize("scheme", ["exp_euler", "lawson", "lie", "lbdf2"])
+def test_schemes_with_source_match_oracle(F, scheme):
+    n = (20, 37, 18)
+    params = BASE_PARAMS
+    P, U0, h = _manufactured(n, ((-8.0, 8.0),) * 3, (1.3, 1.6, 1.8), params)
+    tau, steps = 5e-3, 25
+    ref = O.run(P, scheme, U0, tau, steps)
+    plan = F.Plan(n, (1.3, 1.6, 1.8), h, params, tau=tau, precision="fp64")
+    S = [_dev(s, "fp64") for s in P.source.tensors]
+    plan.set_source(P.source.rates, S)
+    u = _dev(U0, "fp64")
+    for k in range(steps):
+        plan.step(scheme, u, k * tau)
+    err = O.rel_l2(_host(u), ref)
+    print(f"[{scheme} manufactured {n}] rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+    # the manufactured solution itself is reproduced to the scheme's temporal error
+    assert O.rel_l2(_host(u), math.exp(-tau * steps) * U0) < 5e-2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 1e-5), ("bf16x3", 1e-4), ("bf16x6", 1e-5)])
+def test_reduced_precision_trajectory(F, prec, tol):
+    n = (48, 40, 56)
+    alpha = (1.7, 1.5, 1.6)
+    dom = ((-12.0, 12.0),) * 3
+    h = [(b - a) / (m + 1) for (a, b), m in zip(dom, n)]
+    from workloads import gaussian_sum
+    U0 = gaussian_sum(grid_axes(n, dom), seed=21394)
+    tau, steps = 1e-3, 50
+    ref = O.run(O.Problem(n, alpha, h, BASE_PARAMS), "exp_euler", U0, tau, steps)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=tau, precision=prec)
+    u = _dev(U0, prec)
+    plan.run("exp_euler", u, 0.0, steps)
+    err = O.rel_l2(_host(u), ref)
+    print(f"[{prec} exp_euler {n} x{steps}] rel_l2 = {err:.3e}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_headline_size_first_steps(F, prec, tol):
+    """3-D 256^3 on (-12,12)^3, alpha = 1.7, 4 Gaussians: two exp-Euler steps vs the oracle."""
+    w = headline_3d()
+    U0 = u0_headline(w)
+    steps = 2
+    ref = O.run(O.Problem(w.n, w.alpha, w.h, w.params), "exp_euler", U0, w.tau, steps)
+    plan = F.Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
+    u = _dev(U0, prec)
+    plan.run("exp_euler", u, 0.0, steps)
+    err = O.rel_l2(_host(u), ref)
+    print(f"[256^3 {prec} 2 steps] rel_l2 = {err:.3e}")
+    assert err <= tol
+
+
+def test_state_cache_follows_in_place_edits(F):
+    n = (24, 30, 20)
+    alpha, h = _setup(n, 8)
+    U0 = random_complex(n, 1) * 0.3
+    P = O.Problem(n, alpha, h, BASE_PARAMS)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=2e-3)
+    u = _dev(U0, "fp64")
+    plan.step("exp_euler", u, 0.0)
+    u.mul_(0.5)  # torch edit between steps: the cached eigenspace state must be dropped
+    plan.step("exp_euler", u, 2e-3)
+    ref = O.step_exp_euler(P, 0.5 * O.step_exp_euler(P, U0, 0.0, 2e-3), 2e-3, 2e-3)
+    assert O.rel_l2(_host(u), ref) <= 1e-12
+
+
+def test_lbdf2_with_given_history(F):
+    n = (16, 21, 19)
+    alpha, h = _setup(n, 9)
+    U0 = random_complex(n, 2) * 0.3
+    U1 = random_complex(n, 3) * 0.3
+    P = O.Problem(n, alpha, h, BASE_PARAMS)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3)
+    u = _dev(U1, "fp64")
+    plan.set_state(u, _dev(U0, "fp64"))
+    plan.step("lbdf2", u, 1e-3)
+    ref = O.step_lbdf2(P, U1, U0, 1e-3, 1e-3)
+    assert O.rel_l2(_host(u), ref) <= 1e-12
+
+
+def test_check_finite_and_errors(F):
+    from paper_2510_21394_amd import _lib as L
+    n = (16, 12)
+    plan = F.Plan(n, (1.5, 1.5), (0.1, 0.1), BASE_PARAMS, tau=1e-3)
+    u = _dev(random_complex(n, 0), "fp64")
+    assert plan.check_finite(u)
+    u[3, 4] = complex(float("nan"), 0.0)
+    assert not plan.check_finite(u)
+    with pytest.raises(L.FcgleError) as e:
+        L.check(plan.lib.fcgle_step(plan.handle, 0, u.data_ptr(), 0.0, 2e-3, None))
+    assert e.value.code == L.ERR_ARG
+    with pytest.raises(TypeError):
+        plan.step("exp_euler", u.to(torch.complex64), 0.0)
+    with pytest.raises(L.FcgleError):
+        F.Plan(n, (0.9, 1.5), (0.1, 0.1), BASE_PARAMS, tau=1e-3)
+
+
+def test_deterministic_and_autotuned(F):
+    n = (64, 48, 80)
+    alpha, h = _setup(n, 12)
+    V = random_complex(n, 4)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+    a = plan.apply_f("phi1", 1e-2, _dev(V, "fp32"))
+    b = plan.apply_f("phi1", 1e-2, _dev(V, "fp32"))
+    assert torch.equal(a, b)
+    plan.autotune(2)
+    c = plan.apply_f("phi1", 1e-2, _dev(V, "fp32"))
+    ref = O.Problem(n, alpha, h, BASE_PARAMS).f("phi1", 1e-2, V)
+    assert O.rel_l2(_host(c), ref) <= 1e-5
+    print(plan.describe())
+
+
+def test_timing_counts_mode_products(F):
+    n = (32, 40, 24)
+    alpha, h = _setup(n, 13)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+    u = _dev(random_complex(n, 5) * 0.1, "fp32")
+    plan.step("exp_euler", u, 0.0)  # first step adds one forward transform
+    plan.timing_enable(64)
+    plan.run("exp_euler", u, 1e-3, 3)
+    rec = plan.timing_read()
+    assert len(rec) == 18  # 3 steps x (forward + backward) x 3 axes
+    for axis in range(3):
+        assert sum(1 for r in rec if r[0] == axis and r[1] == 1) == 3
+        assert sum(1 for r in rec if r[0] == axis and r[1] == 0) == 3
+    assert all(r[3] > 0 for r in rec)
+    sig = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[0] == 2 and r[1] == 1}
+    assert sig == {"exp_euler"}
