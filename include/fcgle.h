@@ -183,6 +183,17 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
  * direction.  Synchronous.  Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
+/* Choose the tile configuration (0: 256-row, 1: 128-row, 2: 64-row tiles; see
+ * fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
+ * Results do not depend on it beyond rounding order.  Errors: ERR_ARG. */
+int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
+
+/* Fusion switches: bit 0 fuses the pointwise prologue (nonlinearity) into the first
+ * mode product of a Tucker operator, bit 1 fuses the pointwise epilogue (f-scale,
+ * exponential-Euler update, LBDF2 history) into the last one; a cleared bit runs that
+ * map as a separate streaming kernel.  Default 3.  Errors: ERR_ARG. */
+int fcgle_set_fusion(fcgle_plan* plan, int flags);
+
 /* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */
 int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len);
 

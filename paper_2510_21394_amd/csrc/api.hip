@@ -107,6 +107,7 @@ struct fcgle_plan {
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
   int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd]
   bool tuned = false;
+  int fusion = 3;  // bit 0: prologue, bit 1: epilogue
   int* dflag = nullptr;
   // adjoint work buffers (allocated on first use)
   void* adj[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -281,7 +282,7 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
     const bool tl = (L.B == 1);
     L.in = cur;
     if (first && pk != ProKind::Id) {
-      if (mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
+      if ((P->fusion & 1) && mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
         L.pk = pk;
         L.pp = pp;
       } else {
@@ -292,7 +293,7 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
     }
     if (last) {
       ep.sep.mu = mu;
-      if (mp_supported(tl, L.pk, ek)) {
+      if ((ek == EpiKind::Store || (P->fusion & 2)) && mp_supported(tl, L.pk, ek)) {
         L.ek = ek;
         L.ep = ep;
         FC_TRY(launch_timed(P, L, mu, st));
@@ -685,19 +686,33 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes) {
   return FCGLE_OK;
 }
 
-int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
-  FC_TRY(check_plan(plan));
-  if (reps < 1) reps = 3;
-  DeviceGuard g(plan->device);
-  hipStream_t st = as_stream(stream);
+}  // extern "C"
+
+namespace {
+
+// Mean duration (ms) of `reps` runs of fn() on stream st after one warm-up run.
+template <class Fn>
+int time_ms(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, Fn fn, float* out) {
+  if (fn() != hipSuccess) return fail(FCGLE_ERR_HIP, "autotune: launch failed");
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r)
+    if (fn() != hipSuccess) return fail(FCGLE_ERR_HIP, "autotune: launch failed");
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float ms = 0;
+  HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+  *out = ms / reps;
+  return FCGLE_OK;
+}
+
+int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
   const int pr = precision_of(plan);
-  HIP_TRY(hipMemsetAsync(plan->s[0], 0, (size_t)plan->N * plan->elem, st));
-  hipEvent_t e0, e1;
-  HIP_TRY(hipEventCreate(&e0));
-  HIP_TRY(hipEventCreate(&e1));
-  int rc = FCGLE_OK;
-  for (int mu = 0; mu < plan->d && rc == FCGLE_OK; ++mu)
-    for (int dir = 0; dir < 2 && rc == FCGLE_OK; ++dir) {
+  const size_t bytes = (size_t)plan->N * plan->elem;
+  HIP_TRY(hipMemsetAsync(plan->s[0], 0, bytes, st));
+  HIP_TRY(hipMemsetAsync(plan->s[2], 0, bytes, st));
+  // 1. tile configuration of every plain mode product
+  for (int mu = 0; mu < plan->d; ++mu)
+    for (int dir = 0; dir < 2; ++dir) {
       float best = 1e30f;
       int best_c = plan->cfg[mu][dir];
       for (int c = 0; c < kNumCfg; ++c) {
@@ -705,16 +720,8 @@ int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
         L.cfg = c;
         L.in = plan->s[0];
         L.ep.out = plan->s[1];
-        if (launch_mode_product(L, st) != hipSuccess) continue;  // warm-up
-        (void)hipEventRecord(e0, st);
-        for (int r = 0; r < reps; ++r) (void)launch_mode_product(L, st);
-        (void)hipEventRecord(e1, st);
-        if (hipEventSynchronize(e1) != hipSuccess) {
-          rc = fail(FCGLE_ERR_HIP, "autotune: event sync failed");
-          break;
-        }
-        float ms = 0;
-        (void)hipEventElapsedTime(&ms, e0, e1);
+        float ms;
+        FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(L, st); }, &ms));
         if (ms < best) {
           best = ms;
           best_c = c;
@@ -722,11 +729,104 @@ int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
       }
       plan->cfg[mu][dir] = best_c;
     }
-  (void)pr;
+  // 2. fused or separate exponential-Euler update after the last forward mode product
+  const int last = plan->d - 1;
+  EpiParams ep;
+  ep.out = plan->s[2];
+  ep.tau = plan->tau;
+  FC_TRY(get_grid(plan, FCGLE_PHI1, plan->tau, st, &ep.F));
+  FC_TRY(get_sep(plan, plan->tau, &ep.sep));
+  ep.sep.mu = last;
+  float unfused;
+  {
+    MPLaunch L = base_launch(plan, last, true);
+    L.in = plan->s[0];
+    L.ep.out = plan->s[1];
+    FC_TRY(time_ms(st, e0, e1, reps, [&] {
+      hipError_t e = launch_mode_product(L, st);
+      if (e != hipSuccess) return e;
+      return launch_pointwise_epi(pr, plan->N, (int)plan->n[last], plan->s[1], EpiKind::ExpEuler, ep, st);
+    }, &unfused));
+  }
+  float fused = 1e30f;
+  int fused_c = plan->cfg[last][1];
+  for (int c = 0; c < kNumCfg; ++c) {
+    MPLaunch L = base_launch(plan, last, true);
+    L.cfg = c;
+    L.in = plan->s[0];
+    L.ek = EpiKind::ExpEuler;
+    L.ep = ep;
+    float ms;
+    FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(L, st); }, &ms));
+    if (ms < fused) {
+      fused = ms;
+      fused_c = c;
+    }
+  }
+  int fusion = 0;
+  if (fused < unfused) {
+    fusion |= 2;
+    plan->cfg[last][1] = fused_c;
+  }
+  // 3. fused or separate nonlinearity before the first forward mode product
+  if (plan->d > 1) {
+    ProParams pp = nonlin_params(plan, 0.0);
+    MPLaunch L = base_launch(plan, 0, true);
+    L.in = plan->s[0];
+    L.ep.out = plan->s[1];
+    float sep_ms, fus_ms;
+    FC_TRY(time_ms(st, e0, e1, reps, [&] {
+      hipError_t e = launch_pointwise_pro(pr, plan->N, plan->s[0], plan->s[2], pp, st);
+      if (e != hipSuccess) return e;
+      MPLaunch L2 = L;
+      L2.in = plan->s[2];
+      return launch_mode_product(L2, st);
+    }, &sep_ms));
+    MPLaunch Lf = L;
+    Lf.pk = ProKind::Nonlin;
+    Lf.pp = pp;
+    FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(Lf, st); }, &fus_ms));
+    if (fus_ms <= sep_ms) fusion |= 1;
+  } else {
+    fusion |= 1;
+  }
+  plan->fusion = fusion;
+  return FCGLE_OK;
+}
+
+}  // namespace
+
+extern "C" int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (reps < 1) reps = 3;
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int rc = autotune_impl(plan, reps, st, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   plan->tuned = (rc == FCGLE_OK);
+  plan->uhat_valid = false;  // scratch buffers were overwritten
   return rc;
+}
+
+extern "C" {
+
+int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
+  FC_TRY(check_plan(plan));
+  if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= kNumCfg)
+    return fail(FCGLE_ERR_ARG, "set_tiles: bad argument");
+  plan->cfg[axis][fwd] = cfg;
+  return FCGLE_OK;
+}
+
+int fcgle_set_fusion(fcgle_plan* plan, int flags) {
+  FC_TRY(check_plan(plan));
+  if (flags < 0 || flags > 3) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..3");
+  plan->fusion = flags;
+  return FCGLE_OK;
 }
 
 int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
@@ -741,6 +841,7 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
     s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0])) +
          "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1])) + "]";
   }
+  s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");
   s += plan->tuned ? " tuned" : " default";
   std::snprintf(buf, len, "%s", s.c_str());
   return FCGLE_OK;

@@ -133,8 +133,10 @@ struct ProNonlinF {
 
 // ---------------------------------------------------------------------------------------
 // Epilogue functors.  col(a, b) is evaluated once per output column (a: flat index over the
-// axes slower than mu, b: over the faster ones); op(ctx, i, j, re, im) once per element,
-// i being the mode-mu index and j the flat index.
+// axes slower than mu, b: over the faster ones).  apply<V>(ctx, i, j, ok, re, im) handles V
+// output elements of that column (i: mode-mu index, j: flat index, ok: inside the tensor):
+// every functor issues all of its global loads for the V elements before its first store,
+// so the loads are not serialised behind stores the compiler cannot prove independent.
 // ---------------------------------------------------------------------------------------
 
 struct NoCtx {};
@@ -155,6 +157,14 @@ __device__ __forceinline__ zc sep_other(const SepParams& s, uint32_t a, uint32_t
   return E;
 }
 
+template <class C, class R>
+__device__ __forceinline__ C mkc(R re, R im) {
+  C v;
+  v.x = re;
+  v.y = im;
+  return v;
+}
+
 template <class R>
 struct EpiStoreF {
   using C = typename Cx<R>::T;
@@ -163,11 +173,12 @@ struct EpiStoreF {
   EpiStoreF() = default;
   explicit EpiStoreF(const EpiParams& p) : out((C*)p.out) {}
   __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
-  __device__ __forceinline__ void operator()(const Ctx&, int, int64_t j, R re, R im) const {
-    C v;
-    v.x = re;
-    v.y = im;
-    out[j] = v;
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = mkc<C>(re[v], im[v]);
   }
 };
 
@@ -180,12 +191,15 @@ struct EpiGridF {
   EpiGridF() = default;
   explicit EpiGridF(const EpiParams& p) : out((C*)p.out), F((const C*)p.F) {}
   __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
-  __device__ __forceinline__ void operator()(const Ctx&, int, int64_t j, R re, R im) const {
-    const C f = F[j];
-    C v;
-    v.x = f.x * re - f.y * im;
-    v.y = f.x * im + f.y * re;
-    out[j] = v;
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im) const {
+    C f[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) f[v] = ok[v] ? F[j[v]] : C{0, 0};
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = mkc<C>(f[v].x * re[v] - f[v].y * im[v], f[v].x * im[v] + f[v].y * re[v]);
   }
 };
 
@@ -198,9 +212,15 @@ struct EpiSepF {
   EpiSepF() = default;
   explicit EpiSepF(const EpiParams& p) : out((C*)p.out), s(p.sep) {}
   __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
-  __device__ __forceinline__ void operator()(const Ctx& Eo, int i, int64_t j, R re, R im) const {
-    const zc E = zmul(Eo, ((const zc*)s.fac[s.mu])[i]);
-    out[j] = from_zc<C>(zmul(E, zc{(double)re, (double)im}));
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im) const {
+    zc f[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = from_zc<C>(zmul(zmul(Eo, f[v]), zc{(double)re[v], (double)im[v]}));
   }
 };
 
@@ -218,18 +238,25 @@ struct EpiExpEulerF {
   explicit EpiExpEulerF(const EpiParams& p)
       : uhat((C*)p.out), P1((const C*)p.F), ghat_out((C*)p.ghat_out), s(p.sep), tau(p.tau) {}
   __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
-  __device__ __forceinline__ void operator()(const Ctx& Eo, int i, int64_t j, R re, R im) const {
-    const zc E = zmul(Eo, ((const zc*)s.fac[s.mu])[i]);
-    const zc u = to_zc(uhat[j]);
-    const zc P = to_zc(P1[j]);
-    const zc g{(double)re, (double)im};
-    const zc r = zadd(zmul(E, u), zscale(zmul(P, g), tau));
-    uhat[j] = from_zc<C>(r);
-    if (ghat_out) {
-      C gv;
-      gv.x = re;
-      gv.y = im;
-      ghat_out[j] = gv;
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im) const {
+    C u[V], P[V];
+    zc f[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      u[v] = ok[v] ? uhat[j[v]] : C{0, 0};
+      P[v] = ok[v] ? P1[j[v]] : C{0, 0};
+      f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (!ok[v]) continue;
+      const zc E = zmul(Eo, f[v]);
+      const zc g{(double)re[v], (double)im[v]};
+      const zc r = zadd(zmul(E, to_zc(u[v])), zscale(zmul(to_zc(P[v]), g), tau));
+      uhat[j[v]] = from_zc<C>(r);
+      if (ghat_out) ghat_out[j[v]] = mkc<C>(re[v], im[v]);
     }
   }
 };
@@ -243,12 +270,18 @@ struct EpiKeepOldF {
   EpiKeepOldF() = default;
   explicit EpiKeepOldF(const EpiParams& p) : out((C*)p.out), save((C*)p.save) {}
   __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
-  __device__ __forceinline__ void operator()(const Ctx&, int, int64_t j, R re, R im) const {
-    save[j] = out[j];
-    C v;
-    v.x = re;
-    v.y = im;
-    out[j] = v;
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im) const {
+    C old[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) old[v] = ok[v] ? out[j[v]] : C{0, 0};
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) {
+        save[j[v]] = old[v];
+        out[j[v]] = mkc<C>(re[v], im[v]);
+      }
   }
 };
 
@@ -260,9 +293,11 @@ template <int TM_, int TNC_, int TK_, int WM_, int WN_>
 struct TileCfg {
   static constexpr int TM = TM_, TNC = TNC_, TK = TK_, WM = WM_, WN = WN_;
   static constexpr int THREADS = 64 * WM * WN;
+  static constexpr int NW = WM * WN;
   static constexpr int WTM = TM / WM, WTNC = TNC / WN;
   static constexpr int FM = WTM / 16, FNC = WTNC / 16;
   static_assert(FM >= 1 && FNC >= 1 && WTM % 16 == 0 && WTNC % 16 == 0, "wave tile");
+  static_assert(TM % 64 == 0, "rows per tile");
 };
 
 struct Geo {
@@ -271,7 +306,7 @@ struct Geo {
   int ntm;            // number of M tiles
   uint32_t bt;        // N loader: column tiles per batch index
   uint32_t nblocks;   // total workgroups
-  int vec_ok;         // T loader: rows are 16-byte aligned for vector loads
+  int vec_ok;         // unused by the kernels (kept for layout stability)
 };
 
 template <class R>
@@ -299,44 +334,125 @@ struct MfmaT<double> {
   __device__ __forceinline__ static int row(int lane, int r) { return (lane >> 4) + 4 * r; }
 };
 
-// Load G consecutive-k complex values of one tile column (the "unit" of the B loaders).
-// N loader: column b of batch a, k = kb .. kb+G-1 (stride B).  T loader: row a, k contiguous.
-template <class C, int G, bool TL, class Pro>
+// The B loaders move units of G consecutive k-values of one tile column.
+// N loader: column b of batch a (element stride B along k).  T loader: row a (k contiguous).
+// Loads are raw; the prologue is applied when the unit is written to LDS, so that the
+// global loads of the next k-tile stay in flight during the MFMA work of the current one.
+template <class C, int G, bool TL>
 __device__ __forceinline__ void load_b_unit(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
-                                            int kb, const Pro& pro, C (&v)[G]) {
+                                            int kb, C (&v)[G]) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const int k = kb + e;
+    const bool ok = TL ? (a < g.A && k < g.n) : (b < g.B && k < g.n);
+    const int64_t j = TL ? (int64_t)a * g.n + k : ((int64_t)a * g.n + k) * g.B + b;
+    v[e] = ok ? U[j] : C{0, 0};
+  }
+}
+
+template <class C, int G, bool TL, class Pro>
+__device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b, int kb, const Pro& pro,
+                                           C (&v)[G]) {
+  if (Pro::kId) return;
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const int k = kb + e;
+    const bool ok = TL ? (a < g.A && k < g.n) : (b < g.B && k < g.n);
+    const int64_t j = TL ? (int64_t)a * g.n + k : ((int64_t)a * g.n + k) * g.B + b;
+    if (ok) v[e] = pro(j, v[e]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// Shared epilogue.  get(fm, fn, p, r) returns accumulator slot r (p = 0 real, 1 imaginary)
+// of MFMA tile (fm, fn); rowmap(lane, r) its row inside the 16x16 tile.
+//  N loader: rows of one column are B elements apart; handled directly, 4 slots at a time.
+//  T loader: rows of one column are contiguous in memory, so the tile is passed through LDS
+//    in chunks of 16 columns and each wave then walks one column with 64 consecutive rows per
+//    instruction (dense 512-byte runs for complex64).
+// ---------------------------------------------------------------------------------------
+
+template <class R, class T, bool TL, class Epi, class Get, class RowMap>
+__device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint32_t c0, int m0, const Epi& epi,
+                                             Get get, RowMap rowmap, void* smem) {
+  using C = typename Cx<R>::T;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave / T::WN, wn = wave % T::WN;
+  const int lr = lane & 15;
   if (!TL) {
 #pragma unroll
-    for (int e = 0; e < G; ++e) {
-      const int k = kb + e;
-      C x = {0, 0};
-      if (b < g.B && k < g.n) {
-        const int64_t j = ((int64_t)a * g.n + k) * g.B + b;
-        x = U[j];
-        if (!Pro::kId) x = pro(j, x);
+    for (int fn = 0; fn < T::FNC; ++fn) {
+      const uint32_t col = c0 + wn * T::WTNC + fn * 16 + lr;
+      if (col >= g.B) continue;
+      const auto ctx = epi.col(a_fix, col);
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm) {
+        int i[4];
+        int64_t j[4];
+        bool ok[4];
+        R re[4], im[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          i[r] = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
+          ok[r] = i[r] < g.n;
+          j[r] = ((int64_t)a_fix * g.n + i[r]) * g.B + col;
+          re[r] = get(fm, fn, 0, r);
+          im[r] = get(fm, fn, 1, r);
+        }
+        epi.template apply<4>(ctx, i, j, ok, re, im);
       }
-      v[e] = x;
     }
   } else {
-    if (a < g.A) {
-      const int64_t jb = (int64_t)a * g.n + kb;
-      if (g.vec_ok && kb + G <= g.n) {
+    constexpr int CW = 16;         // columns per LDS chunk
+    constexpr int LDC = T::TM + 1; // padded column length in complex elements
+    constexpr int V = T::TM / 64;  // rows per lane per column
+    C* Cs = reinterpret_cast<C*>(smem);
 #pragma unroll
-        for (int e = 0; e < G; ++e) v[e] = U[jb + e];
-      } else {
+    for (int q = 0; q < T::TNC / CW; ++q) {
 #pragma unroll
-        for (int e = 0; e < G; ++e) v[e] = (kb + e < g.n) ? U[jb + e] : C{0, 0};
+      for (int fn = 0; fn < T::FNC; ++fn) {
+        const int colt = wn * T::WTNC + fn * 16;  // first tile column of this fragment
+        if (colt / CW != q) continue;
+#pragma unroll
+        for (int fm = 0; fm < T::FM; ++fm)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = wm * T::WTM + fm * 16 + rowmap(lane, r);
+            Cs[(colt - q * CW + lr) * LDC + row] = mkc<C>(get(fm, fn, 0, r), get(fm, fn, 1, r));
+          }
       }
-      if (!Pro::kId) {
+      __syncthreads();
+      for (int cc = wave; cc < CW; cc += T::NW) {
+        const uint32_t col = c0 + q * CW + cc;
+        if (col >= g.A) continue;
+        const auto ctx = epi.col(col, 0);
+        int i[V];
+        int64_t j[V];
+        bool ok[V];
+        R re[V], im[V];
 #pragma unroll
-        for (int e = 0; e < G; ++e)
-          if (kb + e < g.n) v[e] = pro(jb + e, v[e]);
+        for (int v = 0; v < V; ++v) {
+          const int row = lane + 64 * v;
+          i[v] = m0 + row;
+          ok[v] = i[v] < g.n;
+          j[v] = (int64_t)col * g.n + i[v];
+          const C x = Cs[cc * LDC + row];
+          re[v] = x.x;
+          im[v] = x.y;
+        }
+        epi.template apply<V>(ctx, i, j, ok, re, im);
       }
-    } else {
-#pragma unroll
-      for (int e = 0; e < G; ++e) v[e] = C{0, 0};
+      __syncthreads();
     }
   }
 }
+
+template <class C, class T>
+constexpr size_t epi_lds_bytes() {
+  return (size_t)16 * (T::TM + 1) * sizeof(C);
+}
+
+constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
 // ---------------------------------------------------------------------------------------
 // FP64 / FP32 MFMA mode product
@@ -354,8 +470,12 @@ __global__ void __launch_bounds__(T::THREADS)
   constexpr int TM = T::TM, TNC = T::TNC, TK = T::TK;
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
-  __shared__ __attribute__((aligned(16))) R As[2][TM * LDK];
-  __shared__ __attribute__((aligned(16))) R Bs[2][2 * TNC * LDK];
+  constexpr size_t kAsBytes = (size_t)2 * TM * LDK * sizeof(R);
+  constexpr size_t kBsBytes = (size_t)2 * 2 * TNC * LDK * sizeof(R);
+  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, TL ? epi_lds_bytes<C, T>() : 0);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
+  R (*As)[TM * LDK] = reinterpret_cast<R (*)[TM * LDK]>(smem);
+  R (*Bs)[2 * TNC * LDK] = reinterpret_cast<R (*)[2 * TNC * LDK]>(smem + kAsBytes);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
@@ -380,6 +500,15 @@ __global__ void __launch_bounds__(T::THREADS)
   fragT ra[AIT];
   C rb[BIT][G];
 
+  auto unit_b = [&](int u, int& row, int& kq) {
+    if (TL) {
+      row = u / KU;
+      kq = u % KU;
+    } else {
+      row = u % TNC;
+      kq = u / TNC;
+    }
+  };
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
@@ -395,21 +524,16 @@ __global__ void __launch_bounds__(T::THREADS)
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
-        if (TL) {
-          row = u / KU;
-          kq = u % KU;
-        } else {
-          row = u % TNC;
-          kq = u / TNC;
-        }
+        unit_b(u, row, kq);
         if (TL)
-          load_b_unit<C, G, TL, Pro>(g, U, c0 + row, 0, k0 + kq * G, pro, rb[it]);
+          load_b_unit<C, G, TL>(g, U, c0 + row, 0, k0 + kq * G, rb[it]);
         else
-          load_b_unit<C, G, TL, Pro>(g, U, a_fix, c0 + row, k0 + kq * G, pro, rb[it]);
+          load_b_unit<C, G, TL>(g, U, a_fix, c0 + row, k0 + kq * G, rb[it]);
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int kt) {
+    const int k0 = kt * TK;
 #pragma unroll
     for (int it = 0; it < AIT; ++it) {
       const int u = tid + it * T::THREADS;
@@ -423,13 +547,11 @@ __global__ void __launch_bounds__(T::THREADS)
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
-        if (TL) {
-          row = u / KU;
-          kq = u % KU;
-        } else {
-          row = u % TNC;
-          kq = u / TNC;
-        }
+        unit_b(u, row, kq);
+        if (TL)
+          pro_b_unit<C, G, TL, Pro>(g, c0 + row, 0, k0 + kq * G, pro, rb[it]);
+        else
+          pro_b_unit<C, G, TL, Pro>(g, a_fix, c0 + row, k0 + kq * G, pro, rb[it]);
         fragT re, im;
 #pragma unroll
         for (int e = 0; e < G; ++e) {
@@ -479,34 +601,19 @@ __global__ void __launch_bounds__(T::THREADS)
 
   const int KT = (g.n + TK - 1) / TK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < KT) gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) sstore(cur ^ 1);
+    if (kt + 1 < KT) sstore(cur ^ 1, kt + 1);
     __syncthreads();
   }
 
-  // Epilogue: slot r of a lane holds row MT::row(lane, r), column lane % 16 of each 16x16 tile.
-#pragma unroll
-  for (int fn = 0; fn < T::FNC; ++fn) {
-    const uint32_t col = c0 + wn * T::WTNC + fn * 16 + lr;
-    const bool cvalid = TL ? (col < g.A) : (col < g.B);
-    if (!cvalid) continue;
-    const auto ctx = TL ? epi.col(col, 0) : epi.col(a_fix, col);
-#pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm * T::WTM + fm * 16 + MT::row(lane, r);
-        if (i < g.n) {
-          const int64_t j = TL ? (int64_t)col * g.n + i : ((int64_t)a_fix * g.n + i) * g.B + col;
-          epi(ctx, i, j, (R)acc[fm][fn][0][r], (R)acc[fm][fn][1][r]);
-        }
-      }
-  }
+  run_epilogue<R, T, TL>(
+      g, a_fix, c0, m0, epi, [&](int fm, int fn, int p, int r) { return (R)acc[fm][fn][p][r]; },
+      [](int l, int r) { return MT::row(l, r); }, smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -535,8 +642,12 @@ __global__ void __launch_bounds__(T::THREADS)
   static_assert(TK % 32 == 0, "k tile");
   constexpr int LDK = TK + 8;  // 16-byte pad
   constexpr int LG = 4;        // B loader unit: 4 consecutive k of one column
-  __shared__ __attribute__((aligned(16))) __bf16 As[2][NP][TM * LDK];
-  __shared__ __attribute__((aligned(16))) __bf16 Bs[2][NP][2 * TNC * LDK];
+  constexpr size_t kAsBytes = (size_t)2 * NP * TM * LDK * sizeof(__bf16);
+  constexpr size_t kBsBytes = (size_t)2 * NP * 2 * TNC * LDK * sizeof(__bf16);
+  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, TL ? epi_lds_bytes<C, T>() : 0);
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
+  __bf16 (*As)[NP][TM * LDK] = reinterpret_cast<__bf16 (*)[NP][TM * LDK]>(smem);
+  __bf16 (*Bs)[NP][2 * TNC * LDK] = reinterpret_cast<__bf16 (*)[NP][2 * TNC * LDK]>(smem + kAsBytes);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
@@ -563,6 +674,15 @@ __global__ void __launch_bounds__(T::THREADS)
   v8bf ra[AIT];
   C rb[BIT][LG];
 
+  auto unit_b = [&](int u, int& row, int& kq) {
+    if (TL) {
+      row = u / KUB;
+      kq = u % KUB;
+    } else {
+      row = u % TNC;
+      kq = u / TNC;
+    }
+  };
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
@@ -579,19 +699,16 @@ __global__ void __launch_bounds__(T::THREADS)
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
-        if (TL) {
-          row = u / KUB;
-          kq = u % KUB;
-          load_b_unit<C, LG, TL, Pro>(g, U, c0 + row, 0, k0 + kq * LG, pro, rb[it]);
-        } else {
-          row = u % TNC;
-          kq = u / TNC;
-          load_b_unit<C, LG, TL, Pro>(g, U, a_fix, c0 + row, k0 + kq * LG, pro, rb[it]);
-        }
+        unit_b(u, row, kq);
+        if (TL)
+          load_b_unit<C, LG, TL>(g, U, c0 + row, 0, k0 + kq * LG, rb[it]);
+        else
+          load_b_unit<C, LG, TL>(g, U, a_fix, c0 + row, k0 + kq * LG, rb[it]);
       }
     }
   };
-  auto sstore = [&](int buf) {
+  auto sstore = [&](int buf, int kt) {
+    const int k0 = kt * TK;
 #pragma unroll
     for (int it = 0; it < AIT; ++it) {
       const int u = tid + it * T::THREADS;
@@ -606,13 +723,11 @@ __global__ void __launch_bounds__(T::THREADS)
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
-        if (TL) {
-          row = u / KUB;
-          kq = u % KUB;
-        } else {
-          row = u % TNC;
-          kq = u / TNC;
-        }
+        unit_b(u, row, kq);
+        if (TL)
+          pro_b_unit<C, LG, TL, Pro>(g, c0 + row, 0, k0 + kq * LG, pro, rb[it]);
+        else
+          pro_b_unit<C, LG, TL, Pro>(g, a_fix, c0 + row, k0 + kq * LG, pro, rb[it]);
         v4bf re[NP], im[NP];
 #pragma unroll
         for (int e = 0; e < LG; ++e) {
@@ -681,33 +796,19 @@ __global__ void __launch_bounds__(T::THREADS)
 
   const int KT = (g.n + TK - 1) / TK;
   gload(0);
-  sstore(0);
+  sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
     const int cur = kt & 1;
     if (kt + 1 < KT) gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) sstore(cur ^ 1);
+    if (kt + 1 < KT) sstore(cur ^ 1, kt + 1);
     __syncthreads();
   }
 
-#pragma unroll
-  for (int fn = 0; fn < T::FNC; ++fn) {
-    const uint32_t col = c0 + wn * T::WTNC + fn * 16 + lr;
-    const bool cvalid = TL ? (col < g.A) : (col < g.B);
-    if (!cvalid) continue;
-    const auto ctx = TL ? epi.col(col, 0) : epi.col(a_fix, col);
-#pragma unroll
-    for (int fm = 0; fm < T::FM; ++fm)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = m0 + wm * T::WTM + fm * 16 + (lane >> 4) * 4 + r;
-        if (i < g.n) {
-          const int64_t j = TL ? (int64_t)col * g.n + i : ((int64_t)a_fix * g.n + i) * g.B + col;
-          epi(ctx, i, j, acc[fm][fn][0][r], acc[fm][fn][1][r]);
-        }
-      }
-  }
+  run_epilogue<float, T, TL>(
+      g, a_fix, c0, m0, epi, [&](int fm, int fn, int p, int r) { return acc[fm][fn][p][r]; },
+      [](int l, int r) { return MfmaT<float>::row(l, r); }, smem);
 }
 
 // ---------------------------------------------------------------------------------------

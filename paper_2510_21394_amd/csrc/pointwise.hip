@@ -23,15 +23,22 @@ __global__ void __launch_bounds__(kPwThreads)
     out[j] = pro(j, in[j]);
 }
 
+// One workgroup per row of the fastest axis (the tensor viewed as (rows, nlast)): the
+// per-row context of the epilogue (the separable factor of the slower axes) is formed once
+// and no index division is needed per element.
 template <class R, class Epi>
 __global__ void __launch_bounds__(kPwThreads)
-    pw_epi_kernel(int64_t N, int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
-  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < N; j += (int64_t)gridDim.x * kPwThreads) {
-    const uint32_t a = (uint32_t)(j / nlast);
-    const int i = (int)(j - (int64_t)a * nlast);
-    const auto ctx = epi.col(a, 0);
-    const auto x = v[j];
-    epi(ctx, i, j, x.x, x.y);
+    pw_epi_kernel(int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
+  const uint32_t a = blockIdx.x;
+  const auto ctx = epi.col(a, 0);
+  const int64_t base = (int64_t)a * nlast;
+  for (int i = threadIdx.x; i < nlast; i += kPwThreads) {
+    const auto x = v[base + i];
+    const int ii[1] = {i};
+    const int64_t jj[1] = {base + i};
+    const bool ok[1] = {true};
+    const R re[1] = {x.x}, im[1] = {x.y};
+    epi.template apply<1>(ctx, ii, jj, ok, re, im);
   }
 }
 
@@ -90,8 +97,8 @@ hipError_t pro_impl(int64_t N, const void* in, void* out, const ProParams& p, hi
 template <class R, class Epi>
 hipError_t epi_launch(int64_t N, int nlast, const void* v, const EpiParams& p, hipStream_t s) {
   using C = typename Cx<R>::T;
-  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N, nlast, (const C*)v,
-                     Epi(p));
+  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(N / nlast)), dim3(kPwThreads), 0, s, nlast,
+                     (const C*)v, Epi(p));
   return hipGetLastError();
 }
 

@@ -160,6 +160,12 @@ class Plan:
     def autotune(self, reps: int = 3):
         L.check(self.lib.fcgle_autotune(self.handle, int(reps), _stream()))
 
+    def set_tiles(self, axis: int, fwd: bool, cfg: int):
+        L.check(self.lib.fcgle_set_tiles(self.handle, int(axis), int(bool(fwd)), int(cfg)))
+
+    def set_fusion(self, prologue: bool = True, epilogue: bool = True):
+        L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)))
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)
         L.check(self.lib.fcgle_describe(self.handle, buf, 1024))

@@ -238,3 +238,49 @@ def test_timing_counts_mode_products(F):
     assert all(r[3] > 0 for r in rec)
     sig = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[0] == 2 and r[1] == 1}
     assert sig == {"exp_euler"}
+
+
+@pytest.mark.parametrize("fusion", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("scheme", ["exp_euler", "lbdf2"])
+def test_unfused_paths_match_oracle(F, fusion, scheme):
+    n = (22, 35, 19)
+    params = BASE_PARAMS
+    P, U0, h = _manufactured(n, ((-8.0, 8.0),) * 3, (1.4, 1.5, 1.9), params)
+    tau, steps = 4e-3, 10
+    ref = O.run(P, scheme, U0, tau, steps)
+    plan = F.Plan(n, (1.4, 1.5, 1.9), h, params, tau=tau, precision="fp64")
+    plan.set_fusion(*fusion)
+    plan.set_source(P.source.rates, [_dev(s, "fp64") for s in P.source.tensors])
+    u = _dev(U0, "fp64")
+    plan.run(scheme, u, 0.0, steps)
+    assert O.rel_l2(_host(u), ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("cfg", [0, 1, 2])
+def test_every_tile_configuration(F, prec, cfg):
+    n = (300, 70, 129)
+    alpha, h = _setup(n, 21)
+    V = random_complex(n, 22)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
+    for ax in range(3):
+        for fwd in (0, 1):
+            plan.set_tiles(ax, fwd, cfg)
+    out = plan.apply_f("phi1", 1e-2, _dev(V, prec))
+    ref = O.Problem(n, alpha, h, BASE_PARAMS).f("phi1", 1e-2, V)
+    assert O.rel_l2(_host(out), ref) <= TOL_OP[prec]
+
+
+def test_autotuned_exp_euler_matches_oracle(F):
+    n = (64, 72, 80)
+    alpha, h = _setup(n, 23)
+    U0 = random_complex(n, 24) * 0.2
+    tau, steps = 1e-3, 8
+    ref = O.run(O.Problem(n, alpha, h, BASE_PARAMS), "exp_euler", U0, tau, steps)
+    for prec, tol in (("fp64", 1e-12), ("fp32", 1e-5)):
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=tau, precision=prec)
+        plan.autotune(2)
+        u = _dev(U0, prec)
+        plan.run("exp_euler", u, 0.0, steps)
+        print(plan.describe())
+        assert O.rel_l2(_host(u), ref) <= tol
