@@ -160,12 +160,29 @@ int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, 
  *   w        = tau P1^H ubar_{n+1}
  *   ubar_n   = E^H ubar_{n+1} + (gamma - 2 conj(c)|u_n|^2) w - c u_n^2 conj(w),  c = kappa + i zeta
  *   pbar    += dL/d(nu, eta, gamma, kappa, zeta)
- * u_n_dev: the state the step started from; ubar_next_dev: cotangent of u_{n+1};
- * ubar_n_dev: output (may alias ubar_next_dev); pbar_dev: 5 doubles on the
- * device, ADDED to.  The source must not depend on the parameters.
- * Other schemes: ERR_UNSUPPORTED.  Errors: ERR_ARG, ERR_HIP. */
+ * with dL/dnu = Re sum conj(Q^T ubar_{n+1}) tau ell (e^z Q^T u_n + tau phi_1'(z) Q^T g_n),
+ * z = tau (nu + i eta) ell, phi_1' = phi_1 - phi_2 (from eq. phi), and i tau ell for eta.
+ * u_n_dev: the state the step started from (not modified); ubar_next_dev: cotangent of
+ * u_{n+1}; ubar_n_dev: output (may alias ubar_next_dev, must not alias u_n_dev); pbar_dev:
+ * 5 doubles on the device, ADDED to.  The source must not depend on the parameters.
+ * Equivalent to copying ubar_next into ubar_n and calling fcgle_vjp_run with m = 1.
+ * Other schemes: ERR_UNSUPPORTED.  Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
 int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* ubar_next_dev,
               void* ubar_n_dev, double* pbar_dev, double t, double tau, void* stream);
+
+/* Adjoint of m consecutive FCGLE_EXP_EULER steps u_0 -> u_m starting at time t0 from
+ * u_start_dev = u_0 (a checkpoint; not modified).  The states u_0..u_{m-1} are recomputed
+ * inside the call (m forward steps, kept in plan-owned buffers of 2m state tensors that are
+ * allocated on first use and reused); the adjoint is then swept backwards with the adjoint
+ * state in eigenspace, so each adjoint step costs one backward and one forward Tucker
+ * operator plus two streaming passes.  On entry ubar_dev holds the cotangent of u_m, on
+ * return that of u_0 (in place; distinct from u_start_dev).  pbar_dev (5 doubles, device) is
+ * ADDED to, in the order (nu, eta, gamma, kappa, zeta); the per-row sums are formed in FP64
+ * and reduced in a fixed order, so results do not depend on scheduling.  The plan's cached
+ * eigenspace state and LBDF2 history are invalidated.  Other schemes: ERR_UNSUPPORTED.
+ * Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+int fcgle_vjp_run(fcgle_plan* plan, int scheme, const void* u_start_dev, int64_t m, void* ubar_dev,
+                  double* pbar_dev, double t0, double tau, void* stream);
 
 /* Scan a state tensor for NaN/Inf.  Synchronises `stream`.
  * Returns FCGLE_OK or FCGLE_ERR_NONFINITE (or ERR_ARG / ERR_HIP). */
@@ -210,7 +227,7 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  *   sig = (((prec * 4 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
  * (prec 0..3 as fcgle_precision; t_loader 1 for the fastest axis; prologue 0 none,
  * 1 nonlinearity; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
- * 4 keep-old, 5/6 adjoint stages).  Errors: ERR_STATE if timing is off, ERR_HIP. */
+ * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */
 int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
                       int64_t* count);
 

@@ -45,6 +45,7 @@ SIGNATURES = [
     ("fcgle_step", c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_vp]),
     ("fcgle_run", c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_i64, c_vp]),
     ("fcgle_vjp", c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_dbl, c_dbl, c_vp]),
+    ("fcgle_vjp_run", c_int, [c_vp, c_int, c_vp, c_i64, c_vp, c_vp, c_dbl, c_dbl, c_vp]),
     ("fcgle_check_finite", c_int, [c_vp, c_vp, c_vp]),
     ("fcgle_plan_shape", c_int, [c_vp, P_i64, ctypes.POINTER(c_int)]),
     ("fcgle_autotune", c_int, [c_vp, c_int, c_vp]),

@@ -109,8 +109,10 @@ struct fcgle_plan {
   bool tuned = false;
   int fusion = 3;  // bit 0: prologue, bit 1: epilogue
   int* dflag = nullptr;
-  // adjoint work buffers (allocated on first use)
-  void* adj[4] = {nullptr, nullptr, nullptr, nullptr};
+  // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled
+  // copy, the forward-transformed adjoint source, and the recomputed segment (u_k, X_k)
+  void* adj[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> traj_u, traj_x;
   double* partial = nullptr;
   int64_t partial_rows = 0;
   // timing
@@ -432,6 +434,103 @@ int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
   return fail(FCGLE_ERR_ARG, "unknown scheme %d", scheme);
 }
 
+int ensure_adjoint_buffers(fcgle_plan* P, int64_t m) {
+  const size_t bytes = (size_t)P->N * P->elem;
+  FC_TRY(ensure_state_buffers(P));
+  for (int k = 0; k < 3; ++k)
+    if (!P->adj[k]) FC_TRY(plan_alloc(&P->adj[k], bytes));
+  const int64_t rows = P->N / P->n[P->d - 1];
+  if (!P->partial) {
+    FC_TRY(plan_alloc((void**)&P->partial, (size_t)rows * 5 * sizeof(double)));
+    P->partial_rows = rows;
+  }
+  while ((int64_t)P->traj_u.size() < m) {
+    void *u = nullptr, *x = nullptr;
+    FC_TRY(plan_alloc(&u, bytes));
+    if (plan_alloc(&x, bytes) != FCGLE_OK) {
+      (void)hipFree(u);
+      return FCGLE_ERR_NOMEM;
+    }
+    P->traj_u.push_back(u);
+    P->traj_x.push_back(x);
+  }
+  return FCGLE_OK;
+}
+
+// Adjoint of m exponential-Euler steps from u_start (time t0).  ubar: cotangent of u_m on
+// entry, of u_start on exit.  pbar (device, 5 doubles) is added to.
+//  1. Recompute u_0..u_{m-1} (physical) and X_0..X_{m-1} with the eigenspace forward step.
+//  2. ahat = Q^T ubar; per step backwards: w = Q(tau conj(P1) ahat), pointwise adjoint of g,
+//     ahat <- conj(E) ahat + Q^T q (with the nu/eta sums); finally ubar = Q ahat.
+int vjp_run_impl(fcgle_plan* P, const void* u_start, int64_t m, void* ubar, double* pbar, double t0,
+                 hipStream_t st) {
+  if (m == 0) return FCGLE_OK;
+  FC_TRY(ensure_adjoint_buffers(P, m));
+  const int pr = precision_of(P);
+  const double tau = P->tau;
+  const size_t bytes = (size_t)P->N * P->elem;
+  const int nlast = (int)P->n[P->d - 1];
+  const void *P1, *P2;
+  FC_TRY(get_grid(P, FCGLE_PHI1, tau, st, &P1));
+  FC_TRY(get_grid(P, FCGLE_PHI2, tau, st, &P2));
+  SepParams sep;
+  FC_TRY(get_sep(P, tau, &sep));
+  void *ahat = P->adj[0], *pbuf = P->adj[1], *vbuf = P->adj[2];
+  void *s0 = P->s[0], *s1 = P->s[1], *s2 = P->s[2];
+  P->uhat_valid = false;  // the recompute below uses the plan's eigenspace buffer
+  P->hist_valid = false;
+
+  // 1. forward recompute of the segment
+  HIP_TRY(hipMemcpyAsync(P->traj_u[0], u_start, bytes, hipMemcpyDeviceToDevice, st));
+  {
+    EpiParams ep;
+    ep.out = P->uhat;
+    FC_TRY(tucker(P, true, P->traj_u[0], ProKind::Id, ProParams(), EpiKind::Store, ep, s0, s1, st));
+  }
+  for (int64_t k = 0; k < m; ++k) {
+    EpiParams ep;
+    ep.out = P->uhat;
+    ep.F = P1;
+    ep.F2 = P2;
+    ep.out2 = P->traj_x[k];
+    ep.tau = tau;
+    ep.sep = sep;
+    const ProParams pp = nonlin_params(P, t0 + (double)k * tau);
+    FC_TRY(tucker(P, true, P->traj_u[k], ProKind::Nonlin, pp, EpiKind::ExpEulerRec, ep, s0, s1, st));
+    if (k + 1 < m) {
+      EpiParams eb;
+      eb.out = P->traj_u[k + 1];
+      FC_TRY(tucker(P, false, P->uhat, ProKind::Id, ProParams(), EpiKind::Store, eb, s0, s1, st));
+    }
+  }
+
+  // 2. adjoint sweep in eigenspace
+  HIP_TRY(launch_fill_zero(P->partial, P->partial_rows * 5, st));
+  {
+    EpiParams ea;
+    ea.out = ahat;
+    FC_TRY(tucker(P, true, ubar, ProKind::Id, ProParams(), EpiKind::Store, ea, s0, s1, st));
+  }
+  HIP_TRY(launch_adj_init(pr, P->N, ahat, P1, tau, pbuf, st));
+  for (int64_t k = m - 1; k >= 0; --k) {
+    EpiParams ew;
+    ew.out = s2;
+    FC_TRY(tucker(P, false, pbuf, ProKind::Id, ProParams(), EpiKind::Store, ew, s0, s1, st));
+    HIP_TRY(launch_adj_phys(pr, P->N, nlast, s2, P->traj_u[k], P->p.gamma, P->p.kappa, P->p.zeta, P->partial, st));
+    EpiParams ev;
+    ev.out = vbuf;
+    FC_TRY(tucker(P, true, s2, ProKind::Id, ProParams(), EpiKind::Store, ev, s0, s1, st));
+    HIP_TRY(launch_adj_hat(pr, P->N, nlast, vbuf, ahat, pbuf, P->traj_x[k], P1, sep, tau, P->partial, st));
+  }
+  {
+    EpiParams eu;
+    eu.out = ubar;
+    FC_TRY(tucker(P, false, ahat, ProKind::Id, ProParams(), EpiKind::Store, eu, s0, s1, st));
+  }
+  HIP_TRY(launch_reduce_partials(P->partial, P->partial_rows, 5, pbar, st));
+  return FCGLE_OK;
+}
+
 void free_plan(fcgle_plan* P) {
   auto f = [](void* q) {
     if (q) (void)hipFree(q);
@@ -448,7 +547,9 @@ void free_plan(fcgle_plan* P) {
   f(P->uhat);
   f(P->uprev);
   f(P->dflag);
-  for (int k = 0; k < 4; ++k) f(P->adj[k]);
+  for (int k = 0; k < 3; ++k) f(P->adj[k]);
+  for (void* q : P->traj_u) f(q);
+  for (void* q : P->traj_x) f(q);
   f(P->partial);
   for (auto e : P->ev_pool) (void)hipEventDestroy(e);
 }
@@ -884,12 +985,35 @@ int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, 
   return FCGLE_OK;
 }
 
+int fcgle_vjp_run(fcgle_plan* plan, int scheme, const void* u_start_dev, int64_t m, void* ubar_dev,
+                  double* pbar_dev, double t0, double tau, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_start_dev || !ubar_dev || !pbar_dev) return fail(FCGLE_ERR_ARG, "vjp: NULL argument");
+  if (m < 0) return fail(FCGLE_ERR_ARG, "vjp: m < 0");
+  if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+  if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
+  if (u_start_dev == ubar_dev) return fail(FCGLE_ERR_ARG, "vjp: u_start and ubar must be distinct buffers");
+  DeviceGuard g(plan->device);
+  return vjp_run_impl(plan, u_start_dev, m, ubar_dev, pbar_dev, t0, as_stream(stream));
+}
+
 int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* ubar_next_dev, void* ubar_n_dev,
               double* pbar_dev, double t, double tau, void* stream) {
   FC_TRY(check_plan(plan));
-  (void)u_n_dev; (void)ubar_next_dev; (void)ubar_n_dev; (void)pbar_dev; (void)t; (void)tau; (void)stream;
-  (void)scheme;
-  return fail(FCGLE_ERR_UNSUPPORTED, "vjp not built yet");
+  if (!u_n_dev || !ubar_next_dev || !ubar_n_dev || !pbar_dev) return fail(FCGLE_ERR_ARG, "vjp: NULL argument");
+  if (u_n_dev == ubar_n_dev || u_n_dev == ubar_next_dev)
+    return fail(FCGLE_ERR_ARG, "vjp: u_n must not alias a cotangent buffer");
+  if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
+  if (ubar_n_dev != ubar_next_dev) {
+    DeviceGuard g(plan->device);
+    HIP_TRY(hipMemcpyAsync(ubar_n_dev, ubar_next_dev, (size_t)plan->N * plan->elem, hipMemcpyDeviceToDevice,
+                           as_stream(stream)));
+  }
+  return fcgle_vjp_run(plan, scheme, u_n_dev, 1, ubar_n_dev, pbar_dev, t, tau, stream);
 }
 
 int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h, const fcgle_params* params,

@@ -261,6 +261,48 @@ struct EpiExpEulerF {
   }
 };
 
+// Exponential-Euler update that also records what the adjoint needs for the derivatives
+// with respect to nu and eta (d u_{n+1} / dz = Q (e^z uhat_n + tau phi_1'(z) ghat_n), with
+// phi_1' = phi_1 - phi_2):
+//   uhat[j] <- E_j uhat[j] + tau P1[j] v,   X[j] = uhat_new[j] - tau P2[j] v,  in FP64.
+template <class R>
+struct EpiExpEulerRecF {
+  using C = typename Cx<R>::T;
+  using Ctx = zc;
+  C* uhat;
+  const C* P1;
+  const C* P2;
+  C* X;
+  SepParams s;
+  double tau;
+  EpiExpEulerRecF() = default;
+  explicit EpiExpEulerRecF(const EpiParams& p)
+      : uhat((C*)p.out), P1((const C*)p.F), P2((const C*)p.F2), X((C*)p.out2), s(p.sep), tau(p.tau) {}
+  __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
+  template <int V>
+  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im) const {
+    C u[V], p1[V], p2[V];
+    zc f[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      u[v] = ok[v] ? uhat[j[v]] : C{0, 0};
+      p1[v] = ok[v] ? P1[j[v]] : C{0, 0};
+      p2[v] = ok[v] ? P2[j[v]] : C{0, 0};
+      f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      if (!ok[v]) continue;
+      const zc E = zmul(Eo, f[v]);
+      const zc g{(double)re[v], (double)im[v]};
+      const zc r = zadd(zmul(E, to_zc(u[v])), zscale(zmul(to_zc(p1[v]), g), tau));
+      uhat[j[v]] = from_zc<C>(r);
+      X[j[v]] = from_zc<C>(zsub(r, zscale(zmul(to_zc(p2[v]), g), tau)));
+    }
+  }
+};
+
 template <class R>
 struct EpiKeepOldF {
   using C = typename Cx<R>::T;
@@ -458,10 +500,11 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // FP64 / FP32 MFMA mode product
 // ---------------------------------------------------------------------------------------
 
+// One workgroup's tile (logical block index bid) of the mode product described by g.
 template <class R, class T, bool TL, class Pro, class Epi>
-__global__ void __launch_bounds__(T::THREADS)
-    mp_mfma_kernel(Geo g, const R* __restrict__ M, const typename Cx<R>::T* __restrict__ U, Pro pro,
-                   Epi epi) {
+__device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__ M,
+                                             const typename Cx<R>::T* __restrict__ U, const Pro& pro,
+                                             const Epi& epi, uint32_t bid) {
   using C = typename Cx<R>::T;
   using MT = MfmaT<R>;
   using fragT = typename MT::fragT;
@@ -479,7 +522,6 @@ __global__ void __launch_bounds__(T::THREADS)
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
-  const uint32_t bid = xcd_remap(blockIdx.x, g.nblocks);
   const int mt = (int)(bid % (uint32_t)g.ntm);
   const uint32_t ct = bid / (uint32_t)g.ntm;
   const int m0 = mt * TM;
@@ -614,6 +656,52 @@ __global__ void __launch_bounds__(T::THREADS)
   run_epilogue<R, T, TL>(
       g, a_fix, c0, m0, epi, [&](int fm, int fn, int p, int r) { return (R)acc[fm][fn][p][r]; },
       [](int l, int r) { return MT::row(l, r); }, smem);
+}
+
+template <class R, class T, bool TL, class Pro, class Epi>
+__global__ void __launch_bounds__(T::THREADS)
+    mp_mfma_kernel(Geo g, const R* __restrict__ M, const typename Cx<R>::T* __restrict__ U, Pro pro,
+                   Epi epi) {
+  mp_mfma_tile<R, T, TL, Pro, Epi>(g, M, U, pro, epi, xcd_remap(blockIdx.x, g.nblocks));
+}
+
+// ---------------------------------------------------------------------------------------
+// Grouped mode products: one launch covers the same mode product of many independent
+// problems (items).  Item k owns logical blocks [first, first + g.nblocks); a workgroup
+// finds its item by binary search over `first` (items sorted by it).
+// ---------------------------------------------------------------------------------------
+
+template <class Pro, class Epi>
+struct GroupItem {
+  Geo g;
+  const void* M;
+  const void* U;
+  uint32_t first;
+  Pro pro;
+  Epi epi;
+};
+
+template <class Item>
+__device__ __forceinline__ int find_item(const Item* __restrict__ items, int count, uint32_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+template <class R, class T, bool TL, class Pro, class Epi>
+__global__ void __launch_bounds__(T::THREADS)
+    mp_group_kernel(const GroupItem<Pro, Epi>* __restrict__ items, int count, uint32_t nblocks) {
+  const uint32_t b = xcd_remap(blockIdx.x, nblocks);
+  const int k = find_item(items, count, b);
+  const GroupItem<Pro, Epi>& it = items[k];
+  mp_mfma_tile<R, T, TL, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro, it.epi,
+                                   b - it.first);
 }
 
 // ---------------------------------------------------------------------------------------

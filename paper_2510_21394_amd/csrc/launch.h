@@ -19,9 +19,9 @@ enum class EpiKind : int {
   Sep = 2,       // out[j] = prod_mu f_mu[j_mu] v          (separable exponential)
   ExpEuler = 3,  // uhat[j] = E_j uhat[j] + tau P1[j] v     (eigenspace exponential Euler)
   KeepOld = 4,   // save[j] = out[j]; out[j] = v           (LBDF2 history)
-  AdjHat = 5,    // adjoint, eigenspace stage (see AdjHatParams)
-  AdjPhys = 6,   // adjoint, physical-space stage
-  Count = 7
+  ExpEulerRec = 5,  // as ExpEuler, and X[j] = uhat_new[j] - tau P2[j] v  (adjoint recompute;
+                    //   streaming pass only)
+  Count = 6
 };
 
 // g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with e = eu u + ep up;
@@ -51,13 +51,8 @@ struct EpiParams {
   SepParams sep;             // Sep / ExpEuler / adjoint
   double tau = 0;            // ExpEuler / adjoint
   void* ghat_out = nullptr;  // ExpEuler: optional copy of the transformed nonlinearity
-  // adjoint extras (see pointwise.hip for their meaning)
-  const void* aux0 = nullptr;
-  const void* aux1 = nullptr;
-  const void* aux2 = nullptr;
-  void* out2 = nullptr;
-  double* partial = nullptr;  // per-block partial sums
-  double c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const void* F2 = nullptr;  // ExpEulerRec: phi_2 grid
+  void* out2 = nullptr;      // ExpEulerRec: X
 };
 
 // One mode product out[a, i, b] = sum_k M[i, k] in[a, k, b] on a complex tensor
@@ -102,6 +97,23 @@ hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, 
 hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,
                                 const EpiParams& p, hipStream_t s);
 hipError_t launch_check_finite(int prec, int64_t N, const void* u, int* flag, hipStream_t s);
+// Adjoint of exponential Euler (adjoint.hip).  Tensors of N elements viewed as
+// (N / nlast, nlast); `partial` holds one row of 5 FP64 sums per tensor row, ordered
+// (nu, eta, gamma, kappa, zeta), that these kernels ADD to (no atomics: row r is only
+// touched by workgroup r).
+hipError_t launch_fill_zero(double* x, int64_t count, hipStream_t s);
+// p = tau conj(P1) o ahat
+hipError_t launch_adj_init(int prec, int64_t N, const void* ahat, const void* P1, double tau, void* p,
+                           hipStream_t s);
+// wq <- (gamma - 2 conj(c)|u|^2) wq - c u^2 conj(wq),  c = kappa + i zeta; partial[r][2..4] +=
+// Re sum conj(w) (u, -|u|^2 u, -i |u|^2 u)
+hipError_t launch_adj_phys(int prec, int64_t N, int nlast, void* wq, const void* u, double gamma, double kappa,
+                           double zeta, double* partial, hipStream_t s);
+// S = sum conj(ahat) tau ell X;  ahat <- conj(E) o ahat + v;  p = tau conj(P1) o ahat;
+// partial[r][0] += Re S, partial[r][1] += -Im S   (E, ell from the separable factors / eigenvalues)
+hipError_t launch_adj_hat(int prec, int64_t N, int nlast, const void* v, void* ahat, void* p, const void* X,
+                          const void* P1, const SepParams& sep, double tau, double* partial, hipStream_t s);
+
 // Sums `count` per-block partial rows of width `width` into acc[width] (acc += sum).
 hipError_t launch_reduce_partials(const double* partial, int64_t count, int width, double* acc,
                                   hipStream_t s);

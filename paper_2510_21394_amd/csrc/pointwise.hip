@@ -28,17 +28,18 @@ __global__ void __launch_bounds__(kPwThreads)
 // and no index division is needed per element.
 template <class R, class Epi>
 __global__ void __launch_bounds__(kPwThreads)
-    pw_epi_kernel(int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
-  const uint32_t a = blockIdx.x;
-  const auto ctx = epi.col(a, 0);
-  const int64_t base = (int64_t)a * nlast;
-  for (int i = threadIdx.x; i < nlast; i += kPwThreads) {
-    const auto x = v[base + i];
-    const int ii[1] = {i};
-    const int64_t jj[1] = {base + i};
-    const bool ok[1] = {true};
-    const R re[1] = {x.x}, im[1] = {x.y};
-    epi.template apply<1>(ctx, ii, jj, ok, re, im);
+    pw_epi_kernel(uint32_t rows, int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
+  for (uint32_t a = blockIdx.x; a < rows; a += gridDim.x) {
+    const auto ctx = epi.col(a, 0);
+    const int64_t base = (int64_t)a * nlast;
+    for (int i = threadIdx.x; i < nlast; i += kPwThreads) {
+      const auto x = v[base + i];
+      const int ii[1] = {i};
+      const int64_t jj[1] = {base + i};
+      const bool ok[1] = {true};
+      const R re[1] = {x.x}, im[1] = {x.y};
+      epi.template apply<1>(ctx, ii, jj, ok, re, im);
+    }
   }
 }
 
@@ -97,8 +98,9 @@ hipError_t pro_impl(int64_t N, const void* in, void* out, const ProParams& p, hi
 template <class R, class Epi>
 hipError_t epi_launch(int64_t N, int nlast, const void* v, const EpiParams& p, hipStream_t s) {
   using C = typename Cx<R>::T;
-  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(N / nlast)), dim3(kPwThreads), 0, s, nlast,
-                     (const C*)v, Epi(p));
+  const int64_t rows = N / nlast;
+  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(rows < 65536 ? rows : 65536)), dim3(kPwThreads), 0,
+                     s, (uint32_t)rows, nlast, (const C*)v, Epi(p));
   return hipGetLastError();
 }
 
@@ -110,6 +112,7 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
     case EpiKind::Sep: return epi_launch<R, EpiSepF<R>>(N, nlast, v, p, s);
     case EpiKind::ExpEuler: return epi_launch<R, EpiExpEulerF<R>>(N, nlast, v, p, s);
     case EpiKind::KeepOld: return epi_launch<R, EpiKeepOldF<R>>(N, nlast, v, p, s);
+    case EpiKind::ExpEulerRec: return epi_launch<R, EpiExpEulerRecF<R>>(N, nlast, v, p, s);
     default: return hipErrorInvalidValue;
   }
 }

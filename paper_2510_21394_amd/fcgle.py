@@ -147,7 +147,21 @@ class Plan:
             raise ValueError("pbar must be 5 float64 values on the plan's device")
         L.check(self.lib.fcgle_vjp(self.handle, L.SCHEMES[scheme], _ptr(u_n), _ptr(ubar_next), _ptr(ubar_n),
                                    _ptr(pbar), float(t), self.tau, _stream()))
+        self._state_ver = None
         return ubar_n
+
+    def vjp_run(self, u_start: torch.Tensor, m: int, ubar: torch.Tensor, pbar: torch.Tensor, t0: float,
+                scheme: str = "exp_euler") -> torch.Tensor:
+        """Adjoint of m steps from the checkpoint u_start at t0: ubar (cotangent of u_m) is
+        replaced in place by the cotangent of u_start; pbar (5 float64 on the device) is added to."""
+        self._check_tensor(u_start, "u_start")
+        self._check_tensor(ubar, "ubar")
+        if pbar.dtype != torch.float64 or pbar.numel() != 5 or pbar.device != self.device:
+            raise ValueError("pbar must be 5 float64 values on the plan's device")
+        L.check(self.lib.fcgle_vjp_run(self.handle, L.SCHEMES[scheme], _ptr(u_start), int(m), _ptr(ubar),
+                                       _ptr(pbar), float(t0), self.tau, _stream()))
+        self._state_ver = None
+        return ubar
 
     def check_finite(self, u: torch.Tensor) -> bool:
         self._check_tensor(u)
@@ -198,7 +212,7 @@ def decode_signature(sig: int) -> dict:
     prec = sig // 4
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
             "prologue": ["none", "nonlinearity"][pk],
-            "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "adj_hat", "adj_phys", "?"][ek]}
+            "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "?", "?"][ek]}
 
 
 # -- host-only helpers ---------------------------------------------------------------------
@@ -223,3 +237,78 @@ def host_fz(kind: str, z: np.ndarray) -> np.ndarray:
     out = np.empty_like(zz)
     L.check(L.lib().fcgle_host_fz(L.KINDS[kind], z.size, zz.ctypes.data_as(L.P_dbl), out.ctypes.data_as(L.P_dbl)))
     return out.view(np.complex128).reshape(z.shape)
+
+
+# -- differentiable trajectory ---------------------------------------------------------------
+
+class ExpEulerTrajectory(torch.autograd.Function):
+    """u(T) after `steps` exponential-Euler steps from u0, differentiable with respect to u0
+    and the five parameters (nu, eta, gamma, kappa, zeta).
+
+    Forward: the library's eigenspace steps, with the physical state saved every
+    `every` steps (checkpoints).  Backward: for each checkpoint segment, last first, one
+    fcgle_vjp_run call recomputes the segment and sweeps the discrete adjoint through it.
+    Gradients follow torch's convention for complex inputs of a real loss,
+    dL/dRe u + i dL/dIm u.
+    """
+
+    @staticmethod
+    def forward(ctx, u0, params, problem, steps, every, t0):
+        plan = problem.plan_for(tuple(float(p) for p in params.detach().cpu().tolist()))
+        u = u0.detach().to(plan.dtype).contiguous().clone()
+        ckpts = []
+        k = 0
+        while k < steps:
+            m = min(every, steps - k)
+            ckpts.append((k, u.clone(), m))
+            plan.run("exp_euler", u, t0 + k * plan.tau, m)
+            k += m
+        ctx.plan = plan
+        ctx.ckpts = ckpts
+        ctx.t0 = t0
+        ctx.params_meta = (params.dtype, params.device)
+        ctx.u0_dtype = u0.dtype
+        return u
+
+    @staticmethod
+    def backward(ctx, grad_u):
+        plan = ctx.plan
+        ubar = grad_u.detach().to(plan.dtype).contiguous().clone()
+        pbar = torch.zeros(5, dtype=torch.float64, device=plan.device)
+        for k, uk, m in reversed(ctx.ckpts):
+            plan.vjp_run(uk, m, ubar, pbar, ctx.t0 + k * plan.tau)
+        dt, dev = ctx.params_meta
+        return ubar.to(ctx.u0_dtype), pbar.to(dtype=dt, device=dev), None, None, None, None
+
+
+class Problem:
+    """Grid, orders, time step and precision of a problem whose parameters may vary: keeps
+    the plan of the most recent parameter set (setting up a plan costs the FP64
+    eigendecompositions and the f-grids)."""
+
+    def __init__(self, n, alpha, h, tau: float, precision: str = "fp64", fd_order: int = 2):
+        self.n, self.alpha, self.h = tuple(n), tuple(alpha), tuple(h)
+        self.tau, self.precision, self.fd_order = float(tau), precision, fd_order
+        self._plan = None
+        self._key = None
+
+    def plan_for(self, params) -> Plan:
+        if self._key != params:
+            if self._plan is not None:
+                self._plan.close()
+            self._plan = Plan(self.n, self.alpha, self.h, params, tau=self.tau, precision=self.precision,
+                              fd_order=self.fd_order)
+            self._key = params
+        return self._plan
+
+    def trajectory(self, u0: torch.Tensor, params: torch.Tensor, steps: int, every: int = 20,
+                   t0: float = 0.0) -> torch.Tensor:
+        if every < 1:
+            raise ValueError("every must be >= 1")
+        return ExpEulerTrajectory.apply(u0, params, self, int(steps), int(every), float(t0))
+
+    def close(self):
+        if self._plan is not None:
+            self._plan.close()
+            self._plan = None
+            self._key = None

@@ -7,6 +7,8 @@ Each case runs a whole trajectory on the CPU and stores, in <case>.npz:
   norm  : the L2 norm of the whole oracle u(T)
   steps, tau, scheme : the trajectory that produced it
 
+The adjoint case stores the oracle's gradient instead (see case_adjoint).
+
 Usage: python tests/golden/make_golden.py [case ...]   (all cases by default)
 """
 import os
@@ -50,7 +52,24 @@ def case_headline():
     _save(w.name, U, w.steps, w.tau, "exp_euler")
 
 
+def case_adjoint():
+    """96^3 adjoint workload: L = ||u(T) - u_target||^2 with u_target the trajectory under the
+    perturbed parameters; stores the oracle gradient (u0 samples, five parameters) and L."""
+    w = W.adjoint_3d()
+    U0 = W.u0_adjoint(w)
+    pert = tuple(p + d for p, d in zip(w.params, W.ADJOINT_PERTURBATION))
+    Ut = O.run(O.Problem(w.n, w.alpha, w.h, pert), "exp_euler", U0, w.tau, w.steps)
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    L, g, p = O.expeuler_loss_and_grad(P, U0, Ut, w.tau, w.steps)
+    rng = np.random.default_rng(20251021)
+    idx = np.sort(rng.choice(g.size, size=min(NSAMPLE, g.size), replace=False))
+    np.savez(os.path.join(HERE, w.name + ".npz"), idx=idx, ubar0=g.reshape(-1)[idx],
+             norm=np.linalg.norm(g.reshape(-1)), pbar=p, loss=L, steps=w.steps, tau=w.tau)
+    print(f"{w.name}: L = {L:.6e}, pbar = {p}")
+
+
 CASES = {
+    "3d_96_adjoint": case_adjoint,
     "3d_128_manufactured_lbdf2": lambda: case_manufactured("lbdf2"),
     "3d_128_manufactured_lie": lambda: case_manufactured("lie"),
     "3d_128_manufactured_exp_euler": lambda: case_manufactured("exp_euler"),
