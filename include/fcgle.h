@@ -197,7 +197,9 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
 
 /* Time every candidate tile configuration of each mode product on `stream`
  * (scratch inputs, `reps` launches each) and keep the fastest per axis and
- * direction.  Synchronous.  Errors: ERR_HIP. */
+ * direction, and whether the pointwise prologue/epilogue are fused or streamed.
+ * For a batch plan: the same per grouped phase over all instances.  Overwrites the
+ * plan's scratch and cached eigenspace state.  Synchronous.  Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
 /* Choose the tile configuration (0: 256-row, 1: 128-row, 2: 64-row tiles; see
@@ -235,18 +237,30 @@ int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, 
  * Batched independent 2-D instances
  * ------------------------------------------------------------------------- */
 
-/* A batch of `count` independent 2-D problems of uneven sizes n[2i], n[2i+1],
- * each with its own alpha[2i..2i+1], h[2i..2i+1] and params[i], one shared tau,
- * FD2, complex64 state, FP32 MFMA (precision must be FCGLE_FP32).  State buffers
- * are per instance (u_dev[i] of n[2i] * n[2i+1] complex64).  Synchronous.
- * Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+/* A batch of `count` independent 2-D problems (1 <= count <= 65535) of uneven sizes
+ * n[2i] x n[2i+1] (2..4096 each), each with its own alpha[2i..2i+1], h[2i..2i+1] and
+ * params[i], one shared tau, FD2, complex64 state, FP32 MFMA (precision must be
+ * FCGLE_FP32, else ERR_UNSUPPORTED).  The eigendecompositions (Section 2, eq. diag) are
+ * formed in FP64 on the host, spread over host threads; all per-instance device buffers
+ * (Q, Q^T, eigenvalues, phi_1 grid, eigenspace state, two scratch tensors) live in one
+ * device allocation.  The returned plan is accepted by fcgle_batch_run, fcgle_autotune,
+ * fcgle_describe and fcgle_destroy only (ERR_ARG elsewhere).  Synchronous.
+ * Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_NOMEM, ERR_HIP. */
 int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h,
                       const fcgle_params* params, int precision, double tau, fcgle_plan** out);
 
-/* nsteps exponential-Euler steps of every instance from t0 (sources are not
- * supported in batches).  Each phase of a step is one grouped launch over all
- * instances; the whole trajectory is replayed from a captured HIP graph.
- * scheme must be FCGLE_EXP_EULER.  Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_HIP. */
+/* nsteps exponential-Euler steps (the scheme of fcgle_step) of every instance, in place on
+ * the caller's device buffers u_dev[i] (n[2i] * n[2i+1] complex64, C order), from t0.
+ * Sources are not supported in batches.  The call forms each eigenspace state from u_dev
+ * (two grouped launches), then replays a HIP graph that holds the whole trajectory (up to
+ * 500 steps per graph; longer runs replay it): each phase of a step -- forward mode product
+ * on axis 1 with the nonlinearity fused into its loads, forward mode product on axis 2
+ * with the eigenspace update, the two backward mode products -- is one grouped launch
+ * over all instances.  Graphs are captured on first use for each step count and reused;
+ * the per-instance launch descriptions live in device arrays that are rebuilt (after a
+ * device synchronisation) when the u_dev pointers change between calls.
+ * scheme must be FCGLE_EXP_EULER (else ERR_UNSUPPORTED); tau must equal the plan's.
+ * Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_NOMEM, ERR_HIP. */
 int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau,
                     int64_t nsteps, void* stream);
 

@@ -14,14 +14,16 @@
 #include "fz.hpp"
 #include "host_math.h"
 #include "launch.h"
+#include "plan.h"
 
 using namespace fcgle;
-
 namespace {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char* fmt, ...) {
+}  // namespace
+
+int fcgle::fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -31,101 +33,7 @@ int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                                          \
-  do {                                                                                         \
-    hipError_t e_ = (expr);                                                                    \
-    if (e_ != hipSuccess) return fail(FCGLE_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
-                                      __FILE__, __LINE__);                                      \
-  } while (0)
-
-#define FC_TRY(expr)            \
-  do {                          \
-    int r_ = (expr);            \
-    if (r_ != FCGLE_OK) return r_; \
-  } while (0)
-
-// Restores the calling thread's current device on scope exit.
-struct DeviceGuard {
-  int prev = -1;
-  explicit DeviceGuard(int dev) {
-    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
-  }
-  ~DeviceGuard() {
-    int cur;
-    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
-  }
-};
-
-int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
-
-struct GridBuf {
-  int kind;
-  double theta;
-  void* F;
-};
-
-struct SepBuf {
-  double theta;
-  void* fac[4];  // double2[n_mu] each
-};
-
-struct TimedLaunch {
-  hipEvent_t e0, e1;
-  int axis, fwd, sig;
-};
-
-}  // namespace
-
-struct fcgle_plan {
-  int device = 0;
-  int d = 0;
-  int64_t n[4] = {1, 1, 1, 1};
-  double alpha[4] = {0, 0, 0, 0};
-  double h[4] = {0, 0, 0, 0};
-  fcgle_params p{};
-  int fd_order = 2;
-  int prec = FCGLE_FP64;
-  double tau = 0;
-  int64_t N = 1;
-  int elem = 16;
-  int npad[4] = {0, 0, 0, 0};
-  std::vector<double> Q[4], lam[4];  // host FP64: Q row-major, column k <-> lam[k]
-  void* Mf[4] = {nullptr, nullptr, nullptr, nullptr};  // Q^T in the precision layout
-  void* Mb[4] = {nullptr, nullptr, nullptr, nullptr};  // Q
-  double* dlam[4] = {nullptr, nullptr, nullptr, nullptr};
-  std::vector<GridBuf> grids;
-  std::vector<SepBuf> seps;
-  void* s[3] = {nullptr, nullptr, nullptr};  // scratch tensors
-  void* uhat = nullptr;
-  bool uhat_valid = false;
-  const void* uhat_src = nullptr;
-  void* uprev = nullptr;
-  bool hist_valid = false;
-  const void* hist_src = nullptr;
-  int ns = 0;
-  double rate[4] = {0, 0, 0, 0};
-  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
-  int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd]
-  bool tuned = false;
-  int fusion = 3;  // bit 0: prologue, bit 1: epilogue
-  int* dflag = nullptr;
-  // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled
-  // copy, the forward-transformed adjoint source, and the recomputed segment (u_k, X_k)
-  void* adj[3] = {nullptr, nullptr, nullptr};
-  std::vector<void*> traj_u, traj_x;
-  double* partial = nullptr;
-  int64_t partial_rows = 0;
-  // timing
-  int timing_cap = 0;
-  std::vector<hipEvent_t> ev_pool;
-  std::vector<TimedLaunch> timed;
-};
-
-namespace {
-
-hipStream_t as_stream(void* s) { return (hipStream_t)s; }
-
-int plan_alloc(void** p, size_t bytes) {
+int fcgle::plan_alloc(void** p, size_t bytes) {
   hipError_t e = hipMalloc(p, bytes);
   if (e != hipSuccess) {
     *p = nullptr;
@@ -134,6 +42,8 @@ int plan_alloc(void** p, size_t bytes) {
   }
   return FCGLE_OK;
 }
+
+namespace {
 
 int precision_of(const fcgle_plan* P) {
   switch (P->prec) {
@@ -333,6 +243,7 @@ ProParams nonlin_params(const fcgle_plan* P, double t_eval) {
 
 int check_plan(const fcgle_plan* P) {
   if (!P) return fail(FCGLE_ERR_ARG, "plan is NULL");
+  if (P->batch) return fail(FCGLE_ERR_ARG, "this entry point takes a single-problem plan, not a batch plan");
   return FCGLE_OK;
 }
 
@@ -535,6 +446,10 @@ void free_plan(fcgle_plan* P) {
   auto f = [](void* q) {
     if (q) (void)hipFree(q);
   };
+  if (P->batch) {
+    batch_free(P->batch);
+    P->batch = nullptr;
+  }
   for (int m = 0; m < 4; ++m) {
     f(P->Mf[m]);
     f(P->Mb[m]);
@@ -898,8 +813,12 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
 }  // namespace
 
 extern "C" int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
-  FC_TRY(check_plan(plan));
   if (reps < 1) reps = 3;
+  if (plan && plan->batch) {
+    DeviceGuard g(plan->device);
+    return batch_autotune(plan, reps, as_stream(stream));
+  }
+  FC_TRY(check_plan(plan));
   DeviceGuard g(plan->device);
   hipStream_t st = as_stream(stream);
   hipEvent_t e0, e1;
@@ -931,8 +850,9 @@ int fcgle_set_fusion(fcgle_plan* plan, int flags) {
 }
 
 int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
-  FC_TRY(check_plan(plan));
   if (!buf || len == 0) return fail(FCGLE_ERR_ARG, "bad buffer");
+  if (plan && plan->batch) return batch_describe(plan, buf, len);
+  FC_TRY(check_plan(plan));
   static const char* names[] = {"fp64", "fp32", "bf16x3", "bf16x6"};
   std::string s = "d=" + std::to_string(plan->d) + " n=(";
   for (int m = 0; m < plan->d; ++m) s += std::to_string(plan->n[m]) + (m + 1 < plan->d ? "," : ")");
@@ -1014,19 +934,6 @@ int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* uba
                            as_stream(stream)));
   }
   return fcgle_vjp_run(plan, scheme, u_n_dev, 1, ubar_n_dev, pbar_dev, t, tau, stream);
-}
-
-int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h, const fcgle_params* params,
-                      int precision, double tau, fcgle_plan** out) {
-  (void)count; (void)n; (void)alpha; (void)h; (void)params; (void)precision; (void)tau;
-  if (out) *out = nullptr;
-  return fail(FCGLE_ERR_UNSUPPORTED, "batched plans not built yet");
-}
-
-int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau, int64_t nsteps,
-                    void* stream) {
-  (void)plan; (void)scheme; (void)u_dev; (void)t0; (void)tau; (void)nsteps; (void)stream;
-  return fail(FCGLE_ERR_UNSUPPORTED, "batched plans not built yet");
 }
 
 }  // extern "C"

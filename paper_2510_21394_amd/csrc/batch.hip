@@ -1,0 +1,560 @@
+// Batched independent 2-D problems: many instances of uneven sizes and parameters advanced
+// together by exponential Euler.  Each phase of a step (the nonlinearity fused into the
+// axis-0 forward mode product, the axis-1 forward mode product with the eigenspace update,
+// the two backward mode products) is ONE grouped launch over all instances, and the whole
+// trajectory of a call is captured once into a HIP graph and replayed with one launch.
+//
+// Per instance (C-order (n1, n2), axis 2 fastest), with the eigenspace state
+// uhat = Q_1^T U Q_2 (the tensor form of the Tucker operator, Section 3, eq. fKu_diag2):
+//   F0: T   = g(U) x_1 Q_1^T                 (N loader, nonlinearity in the loads)
+//   F1: uhat <- E o uhat + tau P1 o (T x_2 Q_2^T)   (T loader, fused or streaming update)
+//   B0: T   = uhat x_1 Q_1
+//   B1: U   = T x_2 Q_2
+// A call first forms uhat from U (two more grouped launches), so calls are independent.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "fz.hpp"
+#include "host_math.h"
+#include "plan.h"
+
+namespace fcgle {
+
+namespace {
+
+enum PhaseId { PH_T0 = 0, PH_T1, PH_F0, PH_F1, PH_B0, PH_B1, PH_COUNT };
+
+struct BatchInst {
+  int64_t n[2] = {0, 0};
+  int npad[2] = {0, 0};
+  double alpha[2] = {0, 0}, h[2] = {0, 0};
+  fcgle_params p{};
+  int64_t N = 0;
+  std::vector<double> Q[2], lam[2];
+  float* Mf[2] = {nullptr, nullptr};
+  float* Mb[2] = {nullptr, nullptr};
+  double* dlam[2] = {nullptr, nullptr};
+  double* fac[2] = {nullptr, nullptr};  // exp(tau (nu + i eta) lambda), complex FP64
+  float2* P1 = nullptr;
+  float2* uhat = nullptr;
+  float2* tmp = nullptr;
+  float2* tmp2 = nullptr;
+};
+
+struct Phase {
+  int cfg = 1;
+  bool tl = false;
+  ProKind pk = ProKind::Id;
+  EpiKind ek = EpiKind::Store;
+  void* items = nullptr;  // device item array
+  uint32_t nblocks = 0;
+};
+
+struct CachedGraph {
+  int64_t steps;
+  hipGraphExec_t exec;
+};
+
+}  // namespace
+
+struct BatchData {
+  int count = 0;
+  double tau = 0;
+  std::vector<BatchInst> inst;
+  void* pool = nullptr;
+  Phase ph[PH_COUNT];
+  bool fuse = true;       // F1 with the fused update (else Store + streaming pass)
+  void* pw_items = nullptr;
+  uint32_t pw_rows = 0;
+  std::vector<const void*> bound;  // state pointers the item arrays were built for
+  bool items_valid = false;
+  bool tuned = false;
+  hipStream_t cap = nullptr;
+  std::vector<CachedGraph> graphs;
+};
+
+void batch_free(BatchData* B) {
+  if (!B) return;
+  for (auto& g : B->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& p : B->ph)
+    if (p.items) (void)hipFree(p.items);
+  if (B->pw_items) (void)hipFree(B->pw_items);
+  if (B->pool) (void)hipFree(B->pool);
+  if (B->cap) (void)hipStreamDestroy(B->cap);
+  delete B;
+}
+
+namespace {
+
+void clear_graphs(BatchData* B) {
+  for (auto& g : B->graphs) (void)hipGraphExecDestroy(g.exec);
+  B->graphs.clear();
+}
+
+MPLaunch inst_launch(const BatchData* B, const BatchInst& I, int phase, const void* u) {
+  MPLaunch L;
+  L.prec = P_F32;
+  const Phase& ph = B->ph[phase];
+  L.cfg = ph.cfg;
+  const bool axis1 = (phase == PH_T1 || phase == PH_F1 || phase == PH_B1);
+  const bool fwd = (phase == PH_T0 || phase == PH_T1 || phase == PH_F0 || phase == PH_F1);
+  const int mu = axis1 ? 1 : 0;
+  L.A = axis1 ? I.n[0] : 1;
+  L.B = axis1 ? 1 : I.n[1];
+  L.n = (int)I.n[mu];
+  L.npad = I.npad[mu];
+  L.M = fwd ? (const void*)I.Mf[mu] : (const void*)I.Mb[mu];
+  L.pk = ph.pk;
+  L.ek = ph.ek;
+  switch (phase) {
+    case PH_T0:
+      L.in = u;
+      L.ep.out = I.tmp;
+      break;
+    case PH_T1:
+      L.in = I.tmp;
+      L.ep.out = I.uhat;
+      break;
+    case PH_F0:
+      L.in = u;
+      L.ep.out = I.tmp;
+      L.pp.gamma = I.p.gamma;
+      L.pp.kappa = I.p.kappa;
+      L.pp.zeta = I.p.zeta;
+      break;
+    case PH_F1:
+      L.in = I.tmp;
+      if (ph.ek == EpiKind::ExpEuler) {
+        L.ep.out = I.uhat;
+        L.ep.F = I.P1;
+        L.ep.tau = B->tau;
+        L.ep.sep.d = 2;
+        L.ep.sep.mu = 1;
+        L.ep.sep.n[0] = (int)I.n[0];
+        L.ep.sep.n[1] = (int)I.n[1];
+        L.ep.sep.fac[0] = I.fac[0];
+        L.ep.sep.fac[1] = I.fac[1];
+      } else {
+        L.ep.out = I.tmp2;
+      }
+      break;
+    case PH_B0:
+      L.in = I.uhat;
+      L.ep.out = I.tmp;
+      break;
+    case PH_B1:
+      L.in = I.tmp;
+      L.ep.out = const_cast<void*>(u);
+      break;
+  }
+  return L;
+}
+
+EpiParams update_params(const BatchData* B, const BatchInst& I) {
+  EpiParams ep;
+  ep.out = I.uhat;
+  ep.F = I.P1;
+  ep.tau = B->tau;
+  ep.sep.d = 2;
+  ep.sep.mu = 1;
+  ep.sep.n[0] = (int)I.n[0];
+  ep.sep.n[1] = (int)I.n[1];
+  ep.sep.fac[0] = I.fac[0];
+  ep.sep.fac[1] = I.fac[1];
+  return ep;
+}
+
+// (Re)build and upload every item array for the state pointers u[0..count).  Synchronises
+// the device first: an item array may still be read by work in flight.
+int build_items(BatchData* B, const void* const* u) {
+  HIP_TRY(hipDeviceSynchronize());
+  B->ph[PH_F1].ek = B->fuse ? EpiKind::ExpEuler : EpiKind::Store;
+  std::vector<MPLaunch> L(B->count);
+  for (int p = 0; p < PH_COUNT; ++p) {
+    Phase& ph = B->ph[p];
+    for (int i = 0; i < B->count; ++i) L[i] = inst_launch(B, B->inst[i], p, u[i]);
+    const size_t bytes = group_item_bytes(ph.pk, ph.ek) * (size_t)B->count;
+    if (bytes == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no grouped kernel for phase %d", p);
+    std::vector<unsigned char> host(bytes);
+    ph.nblocks = group_build_f32(ph.cfg, ph.tl, ph.pk, ph.ek, L.data(), B->count, host.data());
+    if (!ph.items) {
+      // largest item type over the epilogue choices of this phase
+      const size_t cap = std::max(group_item_bytes(ph.pk, EpiKind::Store), group_item_bytes(ph.pk, EpiKind::ExpEuler));
+      FC_TRY(plan_alloc(&ph.items, cap * (size_t)B->count));
+    }
+    HIP_TRY(hipMemcpy(ph.items, host.data(), bytes, hipMemcpyHostToDevice));
+  }
+  {
+    std::vector<int64_t> rows(B->count);
+    std::vector<int> nl(B->count);
+    std::vector<const void*> v(B->count);
+    std::vector<EpiParams> ep(B->count);
+    for (int i = 0; i < B->count; ++i) {
+      rows[i] = B->inst[i].n[0];
+      nl[i] = (int)B->inst[i].n[1];
+      v[i] = B->inst[i].tmp2;
+      ep[i] = update_params(B, B->inst[i]);
+    }
+    const size_t bytes = pw_group_item_bytes(EpiKind::ExpEuler) * (size_t)B->count;
+    std::vector<unsigned char> host(bytes);
+    B->pw_rows = pw_group_build_f32(EpiKind::ExpEuler, rows.data(), nl.data(), v.data(), ep.data(), B->count,
+                                    host.data());
+    if (!B->pw_items) FC_TRY(plan_alloc(&B->pw_items, bytes));
+    HIP_TRY(hipMemcpy(B->pw_items, host.data(), bytes, hipMemcpyHostToDevice));
+  }
+  B->bound.assign(u, u + B->count);
+  B->items_valid = true;
+  return FCGLE_OK;
+}
+
+int launch_phase(const BatchData* B, int p, hipStream_t st) {
+  const Phase& ph = B->ph[p];
+  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, ph.items, B->count, ph.nblocks, st));
+  return FCGLE_OK;
+}
+
+int launch_step(const BatchData* B, hipStream_t st) {
+  FC_TRY(launch_phase(B, PH_F0, st));
+  FC_TRY(launch_phase(B, PH_F1, st));
+  if (!B->fuse) HIP_TRY(launch_pw_group_f32(EpiKind::ExpEuler, B->pw_items, B->count, B->pw_rows, st));
+  FC_TRY(launch_phase(B, PH_B0, st));
+  FC_TRY(launch_phase(B, PH_B1, st));
+  return FCGLE_OK;
+}
+
+// Graph of `steps` consecutive steps, captured on the plan's private stream on first use.
+int get_graph(BatchData* B, int64_t steps, hipGraphExec_t* out) {
+  for (auto& g : B->graphs)
+    if (g.steps == steps) {
+      *out = g.exec;
+      return FCGLE_OK;
+    }
+  HIP_TRY(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+  int rc = FCGLE_OK;
+  for (int64_t k = 0; k < steps && rc == FCGLE_OK; ++k) rc = launch_step(B, B->cap);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(B->cap, &graph);
+  if (rc != FCGLE_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(FCGLE_ERR_HIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(FCGLE_ERR_HIP, "hipGraphInstantiate: %s", hipGetErrorString(e2));
+  B->graphs.push_back({steps, exec});
+  *out = exec;
+  return FCGLE_OK;
+}
+
+constexpr int64_t kGraphChunk = 500;  // steps per captured graph (longer runs replay it)
+
+int batch_run_impl(fcgle_plan* P, void* const* u, int64_t nsteps, hipStream_t st) {
+  BatchData* B = P->batch;
+  bool same = B->items_valid && (int)B->bound.size() == B->count;
+  for (int i = 0; same && i < B->count; ++i) same = (B->bound[i] == u[i]);
+  if (!same) FC_TRY(build_items(B, (const void* const*)u));
+  if (nsteps == 0) return FCGLE_OK;
+  FC_TRY(launch_phase(B, PH_T0, st));
+  FC_TRY(launch_phase(B, PH_T1, st));
+  int64_t left = nsteps;
+  while (left > 0) {
+    const int64_t k = left > kGraphChunk ? kGraphChunk : left;
+    hipGraphExec_t g;
+    FC_TRY(get_graph(B, k, &g));
+    HIP_TRY(hipGraphLaunch(g, st));
+    left -= k;
+  }
+  return FCGLE_OK;
+}
+
+template <class Fn>
+int time_phase(hipStream_t st, hipEvent_t e0, hipEvent_t e1, int reps, Fn fn, float* ms) {
+  FC_TRY(fn());
+  HIP_TRY(hipEventRecord(e0, st));
+  for (int r = 0; r < reps; ++r) FC_TRY(fn());
+  HIP_TRY(hipEventRecord(e1, st));
+  HIP_TRY(hipEventSynchronize(e1));
+  float t = 0;
+  HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+  *ms = t / reps;
+  return FCGLE_OK;
+}
+
+int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEvent_t e1) {
+  BatchData* B = P->batch;
+  // bind the phases to plan-owned buffers (tmp2 stands in for the states)
+  std::vector<const void*> scratch(B->count);
+  for (int i = 0; i < B->count; ++i) {
+    scratch[i] = B->inst[i].tmp2;
+    HIP_TRY(hipMemsetAsync(B->inst[i].tmp2, 0, (size_t)B->inst[i].N * 8, st));
+    HIP_TRY(hipMemsetAsync(B->inst[i].tmp, 0, (size_t)B->inst[i].N * 8, st));
+    HIP_TRY(hipMemsetAsync(B->inst[i].uhat, 0, (size_t)B->inst[i].N * 8, st));
+  }
+  const int order[] = {PH_F0, PH_B0, PH_B1};
+  for (int p : order) {
+    float best = 1e30f;
+    int best_c = B->ph[p].cfg;
+    for (int c = 0; c < kNumCfg; ++c) {
+      B->ph[p].cfg = c;
+      FC_TRY(build_items(B, scratch.data()));
+      float ms;
+      FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_phase(B, p, st); }, &ms));
+      if (ms < best) {
+        best = ms;
+        best_c = c;
+      }
+    }
+    B->ph[p].cfg = best_c;
+  }
+  // F1: fused update (each tile configuration) against Store + streaming pass
+  float best = 1e30f;
+  int best_c = 1;
+  bool best_fuse = true;
+  for (int f = 0; f < 2; ++f)
+    for (int c = 0; c < kNumCfg; ++c) {
+      B->fuse = (f == 0);
+      B->ph[PH_F1].cfg = c;
+      FC_TRY(build_items(B, scratch.data()));
+      float ms;
+      FC_TRY(time_phase(st, e0, e1, reps, [&]() -> int {
+        FC_TRY(launch_phase(B, PH_F1, st));
+        if (!B->fuse) HIP_TRY(launch_pw_group_f32(EpiKind::ExpEuler, B->pw_items, B->count, B->pw_rows, st));
+        return (int)FCGLE_OK;
+      }, &ms));
+      if (ms < best) {
+        best = ms;
+        best_c = c;
+        best_fuse = B->fuse;
+      }
+    }
+  B->fuse = best_fuse;
+  B->ph[PH_F1].cfg = best_c;
+  B->ph[PH_T0].cfg = B->ph[PH_F0].cfg;
+  B->ph[PH_T1].cfg = B->ph[PH_B1].cfg;
+  B->items_valid = false;
+  clear_graphs(B);
+  return FCGLE_OK;
+}
+
+}  // namespace
+
+int batch_autotune(fcgle_plan* P, int reps, hipStream_t st) {
+  hipEvent_t e0, e1;
+  HIP_TRY(hipEventCreate(&e0));
+  HIP_TRY(hipEventCreate(&e1));
+  const int rc = autotune_impl(P, reps, st, e0, e1);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  P->batch->tuned = (rc == FCGLE_OK);
+  P->batch->items_valid = false;
+  return rc;
+}
+
+int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
+  const BatchData* B = P->batch;
+  int64_t nmin = 1 << 30, nmax = 0;
+  double flop = 0;
+  for (const auto& I : B->inst) {
+    nmin = std::min({nmin, I.n[0], I.n[1]});
+    nmax = std::max({nmax, I.n[0], I.n[1]});
+    flop += 8.0 * (double)I.N * (double)(I.n[0] + I.n[1]);
+  }
+  static const char* names[] = {"t0", "t1", "f0", "f1", "b0", "b1"};
+  std::string s = "batch count=" + std::to_string(B->count) + " n in [" + std::to_string(nmin) + "," +
+                  std::to_string(nmax) + "] precision=fp32 tiles(rows)=";
+  for (int p = 0; p < PH_COUNT; ++p)
+    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg)) + (p + 1 < PH_COUNT ? "," : "");
+  s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
+  char tail[96];
+  std::snprintf(tail, sizeof(tail), " flop/step=%.4g%s", flop, B->tuned ? " tuned" : " default");
+  s += tail;
+  std::snprintf(buf, len, "%s", s.c_str());
+  return FCGLE_OK;
+}
+
+}  // namespace fcgle
+
+using namespace fcgle;
+
+extern "C" {
+
+int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h, const fcgle_params* params,
+                      int precision, double tau, fcgle_plan** out) {
+  if (!out) return fail(FCGLE_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (count < 1 || count > 65535) return fail(FCGLE_ERR_ARG, "batch: count = %d outside 1..65535", count);
+  if (!n || !alpha || !h || !params) return fail(FCGLE_ERR_ARG, "batch: NULL argument");
+  if (precision != FCGLE_FP32) return fail(FCGLE_ERR_UNSUPPORTED, "batch: only FCGLE_FP32 plans are built");
+  if (!(tau > 0.0) || !std::isfinite(tau)) return fail(FCGLE_ERR_ARG, "tau must be > 0");
+  for (int i = 0; i < count; ++i) {
+    const fcgle_params& p = params[i];
+    if (!(std::isfinite(p.nu) && std::isfinite(p.eta) && std::isfinite(p.gamma) && std::isfinite(p.kappa) &&
+          std::isfinite(p.zeta)))
+      return fail(FCGLE_ERR_ARG, "batch: non-finite parameter in instance %d", i);
+    if (p.nu < 0.0 || p.kappa < 0.0) return fail(FCGLE_ERR_ARG, "batch: nu and kappa must be >= 0 (instance %d)", i);
+    for (int m = 0; m < 2; ++m) {
+      if (n[2 * i + m] < 2 || n[2 * i + m] > 4096)
+        return fail(FCGLE_ERR_ARG, "batch: n[%d] = %lld outside 2..4096", 2 * i + m, (long long)n[2 * i + m]);
+      if (!(alpha[2 * i + m] > 1.0 && alpha[2 * i + m] <= 2.0))
+        return fail(FCGLE_ERR_ARG, "batch: alpha[%d] outside (1, 2]", 2 * i + m);
+      if (!(h[2 * i + m] > 0.0) || !std::isfinite(h[2 * i + m]))
+        return fail(FCGLE_ERR_ARG, "batch: h[%d] must be > 0", 2 * i + m);
+    }
+  }
+  auto* P = new (std::nothrow) fcgle_plan();
+  auto* B = new (std::nothrow) BatchData();
+  if (!P || !B) {
+    delete P;
+    delete B;
+    return fail(FCGLE_ERR_NOMEM, "host allocation failed");
+  }
+  P->batch = B;
+  P->prec = FCGLE_FP32;
+  P->elem = 8;
+  P->tau = tau;
+  P->d = 2;
+  B->count = count;
+  B->tau = tau;
+  B->inst.resize(count);
+  auto cleanup = [&](int rc) {
+    (void)hipDeviceSynchronize();
+    batch_free(B);
+    P->batch = nullptr;
+    delete P;
+    return rc;
+  };
+  hipError_t e = hipGetDevice(&P->device);
+  if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e)));
+  for (int i = 0; i < count; ++i) {
+    BatchInst& I = B->inst[i];
+    I.p = params[i];
+    for (int m = 0; m < 2; ++m) {
+      I.n[m] = n[2 * i + m];
+      I.alpha[m] = alpha[2 * i + m];
+      I.h[m] = h[2 * i + m];
+      I.npad[m] = (int)round_up(I.n[m], 256);
+    }
+    I.N = I.n[0] * I.n[1];
+  }
+  // FP64 eigendecompositions on the host, spread over the host threads
+  {
+    const int jobs = 2 * count;
+    std::vector<int> ok(jobs, 0);
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<std::thread> th;
+    for (unsigned w = 0; w < hw; ++w)
+      th.emplace_back([&, w] {
+        for (int j = (int)w; j < jobs; j += (int)hw) {
+          BatchInst& I = B->inst[j / 2];
+          const int m = j % 2;
+          ok[j] = toeplitz_eig(I.n[m], I.alpha[m], I.h[m], 2, I.Q[m], I.lam[m]);
+        }
+      });
+    for (auto& t : th) t.join();
+    for (int j = 0; j < jobs; ++j)
+      if (!ok[j]) return cleanup(fail(FCGLE_ERR_ARG, "batch: eigensolver did not converge (instance %d)", j / 2));
+  }
+  // one device pool for every per-instance buffer
+  auto al = [](size_t b) { return (size_t)round_up((int64_t)b, 256); };
+  size_t total = 0;
+  for (const auto& I : B->inst) {
+    for (int m = 0; m < 2; ++m)
+      total += 2 * al((size_t)I.npad[m] * I.npad[m] * sizeof(float)) + al(I.n[m] * sizeof(double)) +
+               al(2 * I.n[m] * sizeof(double));
+    total += 4 * al((size_t)I.N * 8);
+  }
+  if (plan_alloc(&B->pool, total) != FCGLE_OK) return cleanup(FCGLE_ERR_NOMEM);
+  {
+    unsigned char* base = (unsigned char*)B->pool;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+      void* p = base + off;
+      off += al(b);
+      return p;
+    };
+    for (auto& I : B->inst) {
+      for (int m = 0; m < 2; ++m) {
+        const size_t mb = (size_t)I.npad[m] * I.npad[m] * sizeof(float);
+        I.Mf[m] = (float*)take(mb);
+        I.Mb[m] = (float*)take(mb);
+        I.dlam[m] = (double*)take(I.n[m] * sizeof(double));
+        I.fac[m] = (double*)take(2 * I.n[m] * sizeof(double));
+      }
+      I.P1 = (float2*)take((size_t)I.N * 8);
+      I.uhat = (float2*)take((size_t)I.N * 8);
+      I.tmp = (float2*)take((size_t)I.N * 8);
+      I.tmp2 = (float2*)take((size_t)I.N * 8);
+    }
+  }
+  // uploads: Q^T and Q (FP32, zero padded), eigenvalues, separable exponential factors
+  for (int i = 0; i < count; ++i) {
+    BatchInst& I = B->inst[i];
+    for (int m = 0; m < 2; ++m) {
+      const int64_t nm = I.n[m], np = I.npad[m];
+      std::vector<float> qt(np * np, 0.0f), q(np * np, 0.0f);
+      for (int64_t r = 0; r < nm; ++r)
+        for (int64_t k = 0; k < nm; ++k) {
+          q[r * np + k] = (float)I.Q[m][r * nm + k];
+          qt[r * np + k] = (float)I.Q[m][k * nm + r];
+        }
+      std::vector<double> fac(2 * nm);
+      for (int64_t j = 0; j < nm; ++j) {
+        const zc z = fz_eval(1, zc{tau * I.p.nu * I.lam[m][j], tau * I.p.eta * I.lam[m][j]});
+        fac[2 * j] = z.re;
+        fac[2 * j + 1] = z.im;
+      }
+      e = hipMemcpy(I.Mf[m], qt.data(), qt.size() * sizeof(float), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(I.Mb[m], q.data(), q.size() * sizeof(float), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(I.dlam[m], I.lam[m].data(), nm * sizeof(double), hipMemcpyHostToDevice);
+      if (e == hipSuccess) e = hipMemcpy(I.fac[m], fac.data(), fac.size() * sizeof(double), hipMemcpyHostToDevice);
+      if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "batch upload: %s", hipGetErrorString(e)));
+    }
+    SepParams s;
+    s.d = 2;
+    s.n[0] = (int)I.n[0];
+    s.n[1] = (int)I.n[1];
+    s.lam[0] = I.dlam[0];
+    s.lam[1] = I.dlam[1];
+    e = launch_fgrid(P_F32, FCGLE_PHI1, tau * I.p.nu, tau * I.p.eta, s, I.N, I.P1, nullptr);
+    if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "batch f-grid: %s", hipGetErrorString(e)));
+  }
+  e = hipDeviceSynchronize();
+  if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "batch setup: %s", hipGetErrorString(e)));
+  e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
+  if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e)));
+  // phase kinds and default tiles (128-row tiles suit the 96..512 sizes)
+  for (int p = 0; p < PH_COUNT; ++p) {
+    Phase& ph = B->ph[p];
+    ph.cfg = 1;
+    ph.tl = (p == PH_T1 || p == PH_F1 || p == PH_B1);
+    ph.pk = (p == PH_F0) ? ProKind::Nonlin : ProKind::Id;
+    ph.ek = (p == PH_F1) ? EpiKind::ExpEuler : EpiKind::Store;
+  }
+  B->fuse = true;
+  *out = P;
+  return FCGLE_OK;
+}
+
+int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau, int64_t nsteps,
+                    void* stream) {
+  if (!plan) return fail(FCGLE_ERR_ARG, "plan is NULL");
+  if (!plan->batch) return fail(FCGLE_ERR_ARG, "fcgle_batch_run needs a plan made by fcgle_batch_setup");
+  if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "batch: only FCGLE_EXP_EULER is built");
+  if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+  if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
+  if (nsteps < 0) return fail(FCGLE_ERR_ARG, "nsteps < 0");
+  if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+  for (int i = 0; i < plan->batch->count; ++i)
+    if (!u_dev[i]) return fail(FCGLE_ERR_ARG, "u_dev[%d] is NULL", i);
+  DeviceGuard g(plan->device);
+  return batch_run_impl(plan, u_dev, nsteps, as_stream(stream));
+}
+
+}  // extern "C"

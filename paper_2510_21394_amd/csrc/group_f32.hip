@@ -1,0 +1,171 @@
+// Grouped FP32 MFMA mode products and grouped streaming epilogues: one launch per phase
+// of a time step over many independent problems of uneven sizes (batched instances).
+#include <cstring>
+
+#include "dispatch.hpp"
+
+namespace fcgle {
+
+namespace {
+
+template <bool TL, class Pro, class Epi>
+struct Combo {
+  static constexpr bool tl = TL;
+  using P = Pro;
+  using E = Epi;
+};
+
+// Calls f(Combo<...>{}) for the supported (loader, prologue, epilogue) combination.
+template <class F>
+bool with_combo(bool tl, ProKind pk, EpiKind ek, F&& f) {
+  using R = float;
+  if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
+    f(Combo<false, ProNonlinF<R>, EpiStoreF<R>>{});
+    return true;
+  }
+  if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
+    f(Combo<false, ProIdF, EpiStoreF<R>>{});
+    return true;
+  }
+  if (tl && pk == ProKind::Id && ek == EpiKind::Store) {
+    f(Combo<true, ProIdF, EpiStoreF<R>>{});
+    return true;
+  }
+  if (tl && pk == ProKind::Id && ek == EpiKind::ExpEuler) {
+    f(Combo<true, ProIdF, EpiExpEulerF<R>>{});
+    return true;
+  }
+  return false;
+}
+
+// The FP32 tile configurations (same as the single-problem FP32 kernels).
+template <class F>
+bool with_cfg(int cfg, F&& f) {
+  switch (cfg) {
+    case 0: f(TileCfg<256, 64, 16, 2, 2>{}); return true;
+    case 1: f(TileCfg<128, 64, 16, 2, 2>{}); return true;
+    case 2: f(TileCfg<64, 64, 16, 1, 2>{}); return true;
+    default: return false;
+  }
+}
+
+template <class Epi>
+struct PwItem {
+  uint32_t first;  // first row of this item in the launch
+  int nlast;
+  const void* v;
+  Epi epi;
+};
+
+template <class R, class Epi>
+__global__ void __launch_bounds__(256)
+    pw_group_kernel(const PwItem<Epi>* __restrict__ items, int count, uint32_t total_rows) {
+  using C = typename Cx<R>::T;
+  for (uint32_t r = blockIdx.x; r < total_rows; r += gridDim.x) {
+    const int k = find_item(items, count, r);
+    const PwItem<Epi>& it = items[k];
+    const uint32_t a = r - it.first;
+    const auto ctx = it.epi.col(a, 0);
+    const int64_t base = (int64_t)a * it.nlast;
+    const C* v = (const C*)it.v;
+    for (int i = threadIdx.x; i < it.nlast; i += 256) {
+      const C x = v[base + i];
+      const int ii[1] = {i};
+      const int64_t jj[1] = {base + i};
+      const bool ok[1] = {true};
+      const R re[1] = {x.x}, im[1] = {x.y};
+      it.epi.template apply<1>(ctx, ii, jj, ok, re, im);
+    }
+  }
+}
+
+}  // namespace
+
+bool group_supported(bool tloader, ProKind pk, EpiKind ek) {
+  return with_combo(tloader, pk, ek, [](auto) {});
+}
+
+size_t group_item_bytes(ProKind pk, EpiKind ek) {
+  size_t b = 0;
+  for (int tl = 0; tl < 2; ++tl)
+    with_combo(tl != 0, pk, ek, [&](auto c) {
+      using Cb = decltype(c);
+      b = sizeof(GroupItem<typename Cb::P, typename Cb::E>);
+    });
+  return b;
+}
+
+uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
+                         void* items_host) {
+  uint32_t total = 0;
+  with_cfg(cfg, [&](auto t) {
+    using T = decltype(t);
+    with_combo(tloader, pk, ek, [&](auto c) {
+      using Cb = decltype(c);
+      using Item = GroupItem<typename Cb::P, typename Cb::E>;
+      unsigned char* dst = (unsigned char*)items_host;
+      for (int k = 0; k < count; ++k) {
+        Item it;
+        it.g = make_geo<T>(L[k], Cb::tl, 4);
+        it.M = L[k].M;
+        it.U = L[k].in;
+        it.first = total;
+        it.pro = typename Cb::P(L[k].pp);
+        it.epi = typename Cb::E(L[k].ep);
+        std::memcpy(dst + k * sizeof(Item), &it, sizeof(Item));
+        total += it.g.nblocks;
+      }
+    });
+  });
+  return total;
+}
+
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const void* items_dev, int count,
+                            uint32_t nblocks, hipStream_t s) {
+  hipError_t err = hipErrorInvalidValue;
+  if (count < 1 || nblocks == 0) return err;
+  with_cfg(cfg, [&](auto t) {
+    using T = decltype(t);
+    with_combo(tloader, pk, ek, [&](auto c) {
+      using Cb = decltype(c);
+      using Item = GroupItem<typename Cb::P, typename Cb::E>;
+      hipLaunchKernelGGL((mp_group_kernel<float, T, Cb::tl, typename Cb::P, typename Cb::E>), dim3(nblocks),
+                         dim3(T::THREADS), 0, s, (const Item*)items_dev, count, nblocks);
+      err = hipGetLastError();
+    });
+  });
+  return err;
+}
+
+size_t pw_group_item_bytes(EpiKind ek) {
+  return ek == EpiKind::ExpEuler ? sizeof(PwItem<EpiExpEulerF<float>>) : 0;
+}
+
+uint32_t pw_group_build_f32(EpiKind ek, const int64_t* rows, const int* nlast, const void* const* v,
+                            const EpiParams* ep, int count, void* items_host) {
+  if (ek != EpiKind::ExpEuler) return 0;
+  using Item = PwItem<EpiExpEulerF<float>>;
+  unsigned char* dst = (unsigned char*)items_host;
+  uint32_t total = 0;
+  for (int k = 0; k < count; ++k) {
+    Item it;
+    it.first = total;
+    it.nlast = nlast[k];
+    it.v = v[k];
+    it.epi = EpiExpEulerF<float>(ep[k]);
+    std::memcpy(dst + k * sizeof(Item), &it, sizeof(Item));
+    total += (uint32_t)rows[k];
+  }
+  return total;
+}
+
+hipError_t launch_pw_group_f32(EpiKind ek, const void* items_dev, int count, uint32_t total_rows, hipStream_t s) {
+  if (ek != EpiKind::ExpEuler || count < 1 || total_rows == 0) return hipErrorInvalidValue;
+  using Item = PwItem<EpiExpEulerF<float>>;
+  const uint32_t blocks = total_rows < 65536 ? total_rows : 65536;
+  hipLaunchKernelGGL((pw_group_kernel<float, EpiExpEulerF<float>>), dim3(blocks), dim3(256), 0, s,
+                     (const Item*)items_dev, count, total_rows);
+  return hipGetLastError();
+}
+
+}  // namespace fcgle

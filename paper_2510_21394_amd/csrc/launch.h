@@ -89,6 +89,25 @@ inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
   return launch_mp_bf16(L, s);
 }
 
+// Grouped FP32 mode products: the same mode product (same loader, prologue and epilogue
+// kinds, tile configuration `cfg`) of `count` independent problems in one launch.
+// group_build_f32 writes the item array for the per-problem descriptions L[0..count) into
+// host memory (group_item_bytes(pk, ek) bytes per item) and returns the total number of
+// workgroups; the array must then be copied to the device and passed to launch_group_f32.
+// Supported: (N loader, Nonlin or Id, Store), (T loader, Id, Store or ExpEuler).
+bool group_supported(bool tloader, ProKind pk, EpiKind ek);
+size_t group_item_bytes(ProKind pk, EpiKind ek);
+uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
+                         void* items_host);
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const void* items_dev, int count,
+                            uint32_t nblocks, hipStream_t s);
+// Grouped streaming epilogue (FP32): item k applies `ek` (ExpEuler) to v[k] viewed as
+// (rows[k], nlast[k]) with parameters ep[k]; returns the total number of rows.
+size_t pw_group_item_bytes(EpiKind ek);
+uint32_t pw_group_build_f32(EpiKind ek, const int64_t* rows, const int* nlast, const void* const* v,
+                            const EpiParams* ep, int count, void* items_host);
+hipError_t launch_pw_group_f32(EpiKind ek, const void* items_dev, int count, uint32_t total_rows, hipStream_t s);
+
 // Standalone pointwise passes (unfused fallbacks and helpers), complex tensors of N
 // elements in the state type of `prec`.
 hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,

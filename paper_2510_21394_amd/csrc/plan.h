@@ -1,0 +1,119 @@
+// Internal definitions shared by the host translation units of the library: the plan
+// object behind the opaque fcgle_plan handle, error helpers and small utilities.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/fcgle.h"
+#include "launch.h"
+
+namespace fcgle {
+
+// Records a message for fcgle_last_error() on the calling thread and returns `code`.
+int fail(int code, const char* fmt, ...);
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess) return fail(FCGLE_ERR_HIP, "%s: %s (%s:%d)", #expr, hipGetErrorString(e_), \
+                                      __FILE__, __LINE__);                                      \
+  } while (0)
+
+#define FC_TRY(expr)            \
+  do {                          \
+    int r_ = (expr);            \
+    if (r_ != FCGLE_OK) return r_; \
+  } while (0)
+
+// Restores the calling thread's current device on scope exit.
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) == hipSuccess && prev != dev) (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    int cur;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+
+inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
+
+// hipMalloc that reports FCGLE_ERR_NOMEM with a message on failure.
+int plan_alloc(void** p, size_t bytes);
+
+// Batched independent problems (batch.hip).
+struct BatchData;
+void batch_free(BatchData* B);
+int batch_autotune(fcgle_plan* plan, int reps, hipStream_t st);
+int batch_describe(const fcgle_plan* plan, char* buf, size_t len);
+
+struct GridBuf {
+  int kind;
+  double theta;
+  void* F;
+};
+
+struct SepBuf {
+  double theta;
+  void* fac[4];  // double2[n_mu] each
+};
+
+struct TimedLaunch {
+  hipEvent_t e0, e1;
+  int axis, fwd, sig;
+};
+
+}  // namespace fcgle
+
+struct fcgle_plan {
+  int device = 0;
+  fcgle::BatchData* batch = nullptr;  // set for plans made by fcgle_batch_setup
+  int d = 0;
+  int64_t n[4] = {1, 1, 1, 1};
+  double alpha[4] = {0, 0, 0, 0};
+  double h[4] = {0, 0, 0, 0};
+  fcgle_params p{};
+  int fd_order = 2;
+  int prec = FCGLE_FP64;
+  double tau = 0;
+  int64_t N = 1;
+  int elem = 16;
+  int npad[4] = {0, 0, 0, 0};
+  std::vector<double> Q[4], lam[4];  // host FP64: Q row-major, column k <-> lam[k]
+  void* Mf[4] = {nullptr, nullptr, nullptr, nullptr};  // Q^T in the precision layout
+  void* Mb[4] = {nullptr, nullptr, nullptr, nullptr};  // Q
+  double* dlam[4] = {nullptr, nullptr, nullptr, nullptr};
+  std::vector<fcgle::GridBuf> grids;
+  std::vector<fcgle::SepBuf> seps;
+  void* s[3] = {nullptr, nullptr, nullptr};  // scratch tensors
+  void* uhat = nullptr;
+  bool uhat_valid = false;
+  const void* uhat_src = nullptr;
+  void* uprev = nullptr;
+  bool hist_valid = false;
+  const void* hist_src = nullptr;
+  int ns = 0;
+  double rate[4] = {0, 0, 0, 0};
+  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
+  int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd]
+  bool tuned = false;
+  int fusion = 3;  // bit 0: prologue, bit 1: epilogue
+  int* dflag = nullptr;
+  // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled
+  // copy, the forward-transformed adjoint source, and the recomputed segment (u_k, X_k)
+  void* adj[3] = {nullptr, nullptr, nullptr};
+  std::vector<void*> traj_u, traj_x;
+  double* partial = nullptr;
+  int64_t partial_rows = 0;
+  // timing
+  int timing_cap = 0;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<fcgle::TimedLaunch> timed;
+};

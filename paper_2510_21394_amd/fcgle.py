@@ -200,6 +200,65 @@ class Plan:
         return [(ax[i], fw[i], sg[i], ms[i]) for i in range(cnt.value)]
 
 
+class BatchPlan:
+    """Independent 2-D problems of uneven sizes advanced together (FP32 MFMA, complex64).
+
+    instances: sequence of (n, alpha, h, params) with n = (n1, n2), alpha/h per axis and
+    params = (nu, eta, gamma, kappa, zeta).  tau: shared time step.
+    """
+
+    def __init__(self, instances, tau: float, precision: str = "fp32", device: Optional[int] = None):
+        if not torch.cuda.is_available():
+            raise RuntimeError("fcgle.BatchPlan needs a GPU")
+        self.lib = L.lib()
+        self.shapes = [tuple(int(m) for m in inst[0]) for inst in instances]
+        if any(len(n) != 2 for n in self.shapes):
+            raise ValueError("batched instances are 2-D")
+        self.count = len(self.shapes)
+        self.tau = float(tau)
+        self.dtype = STATE_DTYPE[precision]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        nn = (ctypes.c_int64 * (2 * self.count))(*[m for n in self.shapes for m in n])
+        aa = (ctypes.c_double * (2 * self.count))(*[float(a) for inst in instances for a in inst[1]])
+        hh = (ctypes.c_double * (2 * self.count))(*[float(x) for inst in instances for x in inst[2]])
+        pp = (L.Params * self.count)(*[L.Params(*[float(v) for v in inst[3]]) for inst in instances])
+        out = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            L.check(self.lib.fcgle_batch_setup(self.count, nn, aa, hh, pp, L.PRECISIONS[precision], self.tau,
+                                               ctypes.byref(out)))
+        self.handle = out
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.fcgle_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, us, t0: float, nsteps: int, scheme: str = "exp_euler"):
+        if len(us) != self.count:
+            raise ValueError(f"expected {self.count} state tensors")
+        for u, n in zip(us, self.shapes):
+            if u.dtype != self.dtype or u.device != self.device or tuple(u.shape) != n or not u.is_contiguous():
+                raise ValueError(f"state tensors must be contiguous {self.dtype} of the instance shapes on {self.device}")
+        ptrs = (ctypes.c_void_p * self.count)(*[u.data_ptr() for u in us])
+        L.check(self.lib.fcgle_batch_run(self.handle, L.SCHEMES[scheme], ptrs, float(t0), self.tau, int(nsteps),
+                                         _stream()))
+        return us
+
+    def autotune(self, reps: int = 3):
+        L.check(self.lib.fcgle_autotune(self.handle, int(reps), _stream()))
+
+    def describe(self) -> str:
+        buf = ctypes.create_string_buffer(1024)
+        L.check(self.lib.fcgle_describe(self.handle, buf, 1024))
+        return buf.value.decode()
+
+
 def decode_signature(sig: int) -> dict:
     """Inverse of the kernel signature of fcgle_timing_read."""
     ek = sig % 8

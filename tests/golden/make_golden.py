@@ -68,7 +68,26 @@ def case_adjoint():
     print(f"{w.name}: L = {L:.6e}, pbar = {p}")
 
 
+def case_batch():
+    """64 batched 2-D instances, 500 exponential-Euler steps each; stores 256 sampled
+    outputs per instance (seeded) and each instance's full-tensor norm."""
+    insts = W.batch_2d()
+    rng = np.random.default_rng(20251021)
+    idx = np.zeros((len(insts), 256), np.int64)
+    val = np.zeros((len(insts), 256), np.complex128)
+    norm = np.zeros(len(insts))
+    for i, inst in enumerate(insts):
+        P = O.Problem(inst.n, inst.alpha, inst.h, inst.params)
+        U = O.run(P, "exp_euler", W.u0_batch(inst), W.BATCH_TAU, W.BATCH_STEPS)
+        ii = np.sort(rng.choice(U.size, size=256, replace=False))
+        idx[i], val[i], norm[i] = ii, U.reshape(-1)[ii], np.linalg.norm(U.reshape(-1))
+        print(f"batch instance {i} {inst.n} done", flush=True)
+    np.savez(os.path.join(HERE, "2d_batch64_expeuler.npz"), idx=idx, val=val, norm=norm,
+             steps=W.BATCH_STEPS, tau=W.BATCH_TAU)
+
+
 CASES = {
+    "2d_batch64_expeuler": case_batch,
     "3d_96_adjoint": case_adjoint,
     "3d_128_manufactured_lbdf2": lambda: case_manufactured("lbdf2"),
     "3d_128_manufactured_lie": lambda: case_manufactured("lie"),
