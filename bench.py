@@ -26,6 +26,37 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6, "bf16x6": 2516.6}
+# Sources that define the mode-product kernels; the stored HBM-traffic measurement is only
+# reported while their hash matches the one it was taken with.
+KERNEL_SOURCES = ["kernels.hpp", "dispatch.hpp", "launch.h", "fz.hpp", "mp_f32.hip", "mp_f64.hip", "mp_bf16.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_3d_256_expeuler.txt")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2510_21394_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel: dict):
+    """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary, or
+    None if there is none for it or the kernel sources changed since it was measured."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith(" "):
+            k, v = line.strip().split("=", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    key = "bytes_per_launch[{precision},cfg{tile_cfg},{loader},{prologue},{epilogue}]".format(
+        loader="T" if kernel["t_loader"] else "N", **{k: kernel[k] for k in ("precision", "tile_cfg", "prologue",
+                                                                             "epilogue")})
+    return float(vals[key]) if key in vals else None
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "3d_256_gauss4_expeuler.npz")
 
@@ -40,6 +71,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device-to-device once (a plain copy kernel of known size, "
+                         "to scale hardware byte counters)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint context timings")
     return ap.parse_args()
 
 
@@ -114,6 +149,59 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden):
     return out
 
 
+def batch_timing(steps=500):
+    """Context: the 64-instance batched 2-D workload (seed 2510, sizes 96..512), FP32 MFMA,
+    one HIP-graph launch per call; steps/s over all instances."""
+    import torch
+    import workloads as W
+    from paper_2510_21394_amd import BatchPlan
+    insts = W.batch_2d()
+    plan = BatchPlan([(i.n, i.alpha, i.h, i.params) for i in insts], tau=W.BATCH_TAU)
+    plan.autotune(2)
+    us = [torch.from_numpy(W.u0_batch(i)).to(torch.complex64).cuda() for i in insts]
+    plan.run(us, 0.0, steps)  # captures the graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.run(us, 0.0, steps)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    flop = sum(8.0 * i.n[0] * i.n[1] * (i.n[0] + i.n[1]) for i in insts)
+    out = {"workload": "2d_batch64_expeuler", "instances": len(insts), "steps": steps,
+           "steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
+           "mode_product_tflops": flop * steps / el / 1e12, "tiles": plan.describe()}
+    plan.close()
+    return out
+
+
+def adjoint_timing():
+    """Context: gradient of ||u(T) - u_target||^2 on the 96^3 adjoint workload (200 steps,
+    checkpoints every 20), FP32 MFMA; forward + checkpointed backward wall time."""
+    import torch
+    import workloads as W
+    from paper_2510_21394_amd import Problem
+    w = W.adjoint_3d()
+    prob = Problem(w.n, w.alpha, w.h, tau=w.tau, precision="fp32")
+    u0 = torch.from_numpy(W.u0_adjoint(w)).to(torch.complex64).cuda()
+    target = torch.zeros_like(u0)
+    res = {}
+    for rep in range(2):  # the first pass sets up the plan and allocates
+        x = u0.clone().requires_grad_(True)
+        p = torch.tensor(w.params, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        uT = prob.trajectory(x, p, w.steps, every=W.ADJOINT_CHECKPOINT_EVERY)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        (uT - target).abs().pow(2).sum().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"workload": w.name, "steps": w.steps, "checkpoint_every": W.ADJOINT_CHECKPOINT_EVERY,
+               "forward_ms": 1e3 * (t1 - t0), "backward_ms": 1e3 * (t2 - t1),
+               "backward_over_forward": (t2 - t1) / (t1 - t0)}
+    prob.close()
+    return res
+
+
 def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
     """The FP64 oracle as it stands, timed on the host cores (bounded sample of the workload)."""
     from oracle import fcgle_oracle as O
@@ -145,6 +233,12 @@ def main():
         print(json.dumps({"error": "no GPU visible"}))
         sys.exit(1)
     import workloads as W
+    if a.copy_calibration > 0:
+        src = torch.empty(a.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = W.headline_3d(n=a.n)
     U0 = W.u0_headline(w)
     golden = None
@@ -184,13 +278,17 @@ def main():
             "peak": peak,
             "unit": "TFLOP/s",
             "frac": dom["achieved_tflops"] / peak,
-            "traffic": None,
+            "traffic": stored_traffic(dom["kernel"]),
             "per_launch_flop": 4.0 * w.n[0] * float(np.prod(w.n)),
             "avg_launch_ms": dom["avg_ms"],
         },
         "variants": {p: {k: v for k, v in d.items() if k != "kernels"} for p, d in variants.items()},
         "kernels": head["kernels"],
     }
+    if not a.no_extras:
+        line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing()}
+        print(f"# batch: {line['context']['batch']['steps_per_s']:.1f} steps/s; adjoint backward/forward = "
+              f"{line['context']['adjoint']['backward_over_forward']:.2f}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, U0)
     print(json.dumps(line, default=lambda o: list(o) if isinstance(o, (set, tuple)) else str(o)))

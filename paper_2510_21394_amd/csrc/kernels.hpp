@@ -203,6 +203,18 @@ struct EpiGridF {
   }
 };
 
+// Complex arithmetic in the state precision (float2 / double2).
+template <class C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  C o;
+  o.x = a.x * b.x - a.y * b.y;
+  o.y = a.x * b.y + a.y * b.x;
+  return o;
+}
+
+// out[j] = E_j v with E the separable exponential (product of the per-axis FP64 factors),
+// formed and applied in FP64: E is the same every step, so a rounding of E in the state
+// precision would act as a fixed per-element bias that grows linearly over a trajectory.
 template <class R>
 struct EpiSepF {
   using C = typename Cx<R>::T;
@@ -224,7 +236,8 @@ struct EpiSepF {
   }
 };
 
-// uhat[j] <- E_j uhat[j] + tau P1[j] v   (v = transformed nonlinearity), in FP64.
+// uhat[j] <- E_j uhat[j] + tau P1[j] v   (v = transformed nonlinearity).  E uhat is formed in
+// FP64 (see EpiSepF); the small correction tau P1 v in the state precision.
 template <class R>
 struct EpiExpEulerF {
   using C = typename Cx<R>::T;
@@ -252,10 +265,9 @@ struct EpiExpEulerF {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       if (!ok[v]) continue;
-      const zc E = zmul(Eo, f[v]);
-      const zc g{(double)re[v], (double)im[v]};
-      const zc r = zadd(zmul(E, to_zc(u[v])), zscale(zmul(to_zc(P[v]), g), tau));
-      uhat[j[v]] = from_zc<C>(r);
+      const zc eu = zmul(zmul(Eo, f[v]), to_zc(u[v]));
+      const C pg = cmul(P[v], mkc<C>(re[v], im[v]));
+      uhat[j[v]] = from_zc<C>(zc{eu.re + tau * (double)pg.x, eu.im + tau * (double)pg.y});
       if (ghat_out) ghat_out[j[v]] = mkc<C>(re[v], im[v]);
     }
   }
@@ -414,6 +426,16 @@ __device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b,
 //    instruction (dense 512-byte runs for complex64).
 // ---------------------------------------------------------------------------------------
 
+// The T-loader epilogue passes the tile through LDS so that each wave stores dense
+// 512-byte runs of one column; building with FCGLE_TL_EPI_DIRECT stores straight from the
+// accumulators instead (64-128 byte runs, fewer LDS round trips).  Measured on the 256^3
+// workload the LDS form is as fast or faster for every precision.
+#ifdef FCGLE_TL_EPI_DIRECT
+constexpr bool kTlDirectEpilogue = true;
+#else
+constexpr bool kTlDirectEpilogue = false;
+#endif
+
 template <class R, class T, bool TL, class Epi, class Get, class RowMap>
 __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint32_t c0, int m0, const Epi& epi,
                                              Get get, RowMap rowmap, void* smem) {
@@ -438,6 +460,32 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
           i[r] = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
           ok[r] = i[r] < g.n;
           j[r] = ((int64_t)a_fix * g.n + i[r]) * g.B + col;
+          re[r] = get(fm, fn, 0, r);
+          im[r] = get(fm, fn, 1, r);
+        }
+        epi.template apply<4>(ctx, i, j, ok, re, im);
+      }
+    }
+  } else if (kTlDirectEpilogue) {
+    // A lane's accumulator slots of one column cover consecutive rows (4 for FP32, 1 per
+    // 16-lane group for FP64), so each store instruction writes 64-128 byte runs of 16
+    // columns; no LDS round trip and no accumulator copies are needed.
+#pragma unroll
+    for (int fn = 0; fn < T::FNC; ++fn) {
+      const uint32_t col = c0 + wn * T::WTNC + fn * 16 + lr;
+      if (col >= g.A) continue;
+      const auto ctx = epi.col(col, 0);
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm) {
+        int i[4];
+        int64_t j[4];
+        bool ok[4];
+        R re[4], im[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          i[r] = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
+          ok[r] = i[r] < g.n;
+          j[r] = (int64_t)col * g.n + i[r];
           re[r] = get(fm, fn, 0, r);
           im[r] = get(fm, fn, 1, r);
         }
@@ -515,7 +563,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   static_assert(TK % (4 * G) == 0, "k tile");
   constexpr size_t kAsBytes = (size_t)2 * TM * LDK * sizeof(R);
   constexpr size_t kBsBytes = (size_t)2 * 2 * TNC * LDK * sizeof(R);
-  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, TL ? epi_lds_bytes<C, T>() : 0);
+  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? epi_lds_bytes<C, T>() : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   R (*As)[TM * LDK] = reinterpret_cast<R (*)[TM * LDK]>(smem);
   R (*Bs)[2 * TNC * LDK] = reinterpret_cast<R (*)[2 * TNC * LDK]>(smem + kAsBytes);
@@ -732,7 +780,7 @@ __global__ void __launch_bounds__(T::THREADS)
   constexpr int LG = 4;        // B loader unit: 4 consecutive k of one column
   constexpr size_t kAsBytes = (size_t)2 * NP * TM * LDK * sizeof(__bf16);
   constexpr size_t kBsBytes = (size_t)2 * NP * 2 * TNC * LDK * sizeof(__bf16);
-  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, TL ? epi_lds_bytes<C, T>() : 0);
+  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? epi_lds_bytes<C, T>() : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   __bf16 (*As)[NP][TM * LDK] = reinterpret_cast<__bf16 (*)[NP][TM * LDK]>(smem);
   __bf16 (*Bs)[NP][2 * TNC * LDK] = reinterpret_cast<__bf16 (*)[NP][2 * TNC * LDK]>(smem + kAsBytes);
