@@ -53,9 +53,9 @@ def stored_traffic(kernel: dict):
             vals[k.strip()] = v.strip()
     if vals.get("source_hash") != kernel_source_hash():
         return None
-    key = "bytes_per_launch[{precision},cfg{tile_cfg},{loader},{prologue},{epilogue}]".format(
-        loader="T" if kernel["t_loader"] else "N", **{k: kernel[k] for k in ("precision", "tile_cfg", "prologue",
-                                                                             "epilogue")})
+    key = "bytes_per_launch[{precision},{structure},cfg{tile_cfg},{loader},{prologue},{epilogue}]".format(
+        loader="T" if kernel["t_loader"] else "N",
+        **{k: kernel[k] for k in ("precision", "structure", "tile_cfg", "prologue", "epilogue")})
     return float(vals[key]) if key in vals else None
 HBM_PEAK_GBS = 8000.0
 GOLDEN = os.path.join(ROOT, "tests", "golden", "3d_256_gauss4_expeuler.npz")
@@ -76,6 +76,20 @@ def parse():
                          "to scale hardware byte counters)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint context timings")
     return ap.parse_args()
+
+
+def mode_product_flop(n, structure):
+    """Algorithmic real flops of one mode product on a complex tensor of shape n (all axes of
+    the workload have the same length): a real Q times complex fibres is 4 flops per
+    multiply-add.  Dense: n^2 multiply-adds per fibre.  Even/odd split: me^2 + mo^2
+    (me = n - n/2, mo = n/2) multiply-adds per fibre plus one complex add or subtract per
+    fibre entry for the butterfly."""
+    m = n[0]
+    N = float(np.prod(n))
+    if structure == "dense":
+        return 4.0 * m * N
+    me, mo = m - m // 2, m // 2
+    return 4.0 * (me * me + mo * mo) * N / m + 2.0 * N
 
 
 def time_precision(prec, w, U0, steps, warmup, autotune, golden):
@@ -116,31 +130,32 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden):
         d["ms"] += ms
         d["count"] += 1
         d["launches"].add((axis, fwd))
-    n = w.n[0]
-    N = int(np.prod(w.n))
-    flop_per_launch = 4.0 * n * N  # real Q (n x n) times complex fibres: 2 real flop per MAC x 2 parts
     total_mp_ms = sum(d["ms"] for d in per.values())
+    total_flop = sum(mode_product_flop(w.n, decode_signature(sig)["structure"]) * d["count"]
+                     for sig, d in per.items())
     dom_sig = max(per, key=lambda s: per[s]["ms"])
     dom = per[dom_sig]
     avg_ms = dom["ms"] / dom["count"]
-    achieved = flop_per_launch / (avg_ms * 1e-3) / 1e12
+    dom_flop = mode_product_flop(w.n, decode_signature(dom_sig)["structure"])
+    achieved = dom_flop / (avg_ms * 1e-3) / 1e12
     kernels = []
     for sig, d in sorted(per.items(), key=lambda kv: -kv[1]["ms"]):
         a = d["ms"] / d["count"]
+        fl = mode_product_flop(w.n, decode_signature(sig)["structure"])
         kernels.append({"kernel": decode_signature(sig), "signature": sig, "launches_per_step": d["count"] / steps,
-                        "avg_us": round(a * 1e3, 2),
-                        "tflops": round(flop_per_launch / (a * 1e-3) / 1e12, 2),
+                        "avg_us": round(a * 1e3, 2), "flop_per_launch": fl,
+                        "tflops": round(fl / (a * 1e-3) / 1e12, 2),
                         "axes_dirs": sorted(d["launches"])})
     out = {
         "precision": prec,
         "steps_per_s": steps / elapsed,
         "ms_per_step": 1e3 * elapsed / steps,
         "mode_products_ms_per_step": total_mp_ms / steps,
-        "mode_product_tflops_avg": 6 * steps * flop_per_launch / (total_mp_ms * 1e-3) / 1e12,
+        "mode_product_tflops_avg": total_flop / (total_mp_ms * 1e-3) / 1e12,
         "rel_l2_vs_fp64_oracle_at_T": err,
         "tiles": plan.describe(),
         "dominant": {"signature": dom_sig, "kernel": decode_signature(dom_sig), "avg_ms": avg_ms,
-                     "achieved_tflops": achieved, "count": dom["count"]},
+                     "flop_per_launch": dom_flop, "achieved_tflops": achieved, "count": dom["count"]},
         "kernels": kernels,
     }
     plan.close()
@@ -279,7 +294,7 @@ def main():
             "unit": "TFLOP/s",
             "frac": dom["achieved_tflops"] / peak,
             "traffic": stored_traffic(dom["kernel"]),
-            "per_launch_flop": 4.0 * w.n[0] * float(np.prod(w.n)),
+            "per_launch_flop": dom["flop_per_launch"],
             "avg_launch_ms": dom["avg_ms"],
         },
         "variants": {p: {k: v for k, v in d.items() if k != "kernels"} for p, d in variants.items()},

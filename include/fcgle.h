@@ -115,7 +115,8 @@ void fcgle_destroy(fcgle_plan* plan);
 const char* fcgle_last_error(void);
 
 /* Eigenpairs of axis mu (0-based) in FP64: Q[n_mu * n_mu] row-major with
- * column k the eigenvector of lambda[k]; lambda ascending.  Host buffers.
+ * column k the eigenvector of lambda[k]; lambda ascending (the plan itself keeps them in
+ * even/odd block order, see fcgle_set_structure).  Host buffers.
  * Errors: ERR_ARG. */
 int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda);
 
@@ -202,10 +203,21 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
  * plan's scratch and cached eigenspace state.  Synchronous.  Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
-/* Choose the tile configuration (0: 256-row, 1: 128-row, 2: 64-row tiles; see
- * fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
+/* Choose the tile configuration (0..2; rows x columns per tile depend on the precision and
+ * structure, see fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
  * Results do not depend on it beyond rounding order.  Errors: ERR_ARG. */
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
+
+/* Structure of the mode products.  Every D_mu is symmetric Toeplitz, hence persymmetric
+ * (J D J = D with J the exchange matrix), so Q_mu = Z diag(Ve, Vo) with Z built from
+ * (e_k +- e_{n-1-k})/sqrt(2) and Ve, Vo the eigenvectors of two half-size blocks (the
+ * set-up always diagonalises D_mu this way).  split = 1 (the default where available,
+ * FCGLE_FP64 and FCGLE_FP32): each mode product contracts the half-length sums and
+ * differences of mirrored fibre entries with the half-size blocks -- half the multiply-adds
+ * of the dense product for the same bytes moved; split = 0: dense Q_mu^T / Q_mu products.
+ * Results agree to rounding.  Resets the tile choice to its default (autotune again after).
+ * Errors: ERR_ARG, ERR_UNSUPPORTED (split = 1 for the split-BF16 precisions). */
+int fcgle_set_structure(fcgle_plan* plan, int split);
 
 /* Fusion switches: bit 0 fuses the pointwise prologue (nonlinearity) into the first
  * mode product of a Tucker operator, bit 1 fuses the pointwise epilogue (f-scale,
@@ -226,8 +238,9 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * record.  For launch i < *count (at most cap): axis[i] = mode axis (0-based),
  * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
  * its duration, sig[i] = the kernel instantiation it ran:
- *   sig = (((prec * 4 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
- * (prec 0..3 as fcgle_precision; t_loader 1 for the fastest axis; prologue 0 none,
+ *   sig = structure * 512 + (((prec * 4 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
+ * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q; prec 0..3 as fcgle_precision;
+ * t_loader 1 for the fastest axis; prologue 0 none,
  * 1 nonlinearity; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
  * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */
 int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
@@ -273,8 +286,9 @@ int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0,
 int fcgle_host_fd_weights(double alpha, int64_t n, int fd_order, double* g);
 
 /* D = -h^{-alpha} Toeplitz(g) and its FP64 eigendecomposition by this library's
- * own solver (Householder tridiagonalisation + implicit symmetric QR with
- * Wilkinson shifts).  Q[n*n] row-major, column k = eigenvector of lambda[k]
+ * own solver: the even/odd half-size blocks of the persymmetric D (see
+ * fcgle_set_structure), each by Householder tridiagonalisation + implicit symmetric QR
+ * with Wilkinson shifts and one extended-precision orthogonalisation sweep.  Q[n*n] row-major, column k = eigenvector of lambda[k]
  * (ascending).  Errors: ERR_ARG, ERR_NOMEM. */
 int fcgle_host_eig(int64_t n, double alpha, double h, int fd_order, double* Q, double* lambda);
 

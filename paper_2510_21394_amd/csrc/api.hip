@@ -87,6 +87,43 @@ int upload_matrix(fcgle_plan* P, const std::vector<double>& M, int64_t n, int64_
   return FCGLE_OK;
 }
 
+// Upload the stacked split block matrices of one axis, forward [Fe; Fo] and backward
+// [Be; Bo], each block ld x ld zero padded, in the plan's precision.  They are read off the
+// plan's Q (exact even/odd structure, Q = Z diag(Ve, Vo)), so the split products round like
+// the dense ones (i, k < me resp. mo; m = n/2):
+//   Fe[i][k] = Q[k][i] (k < m), Q[m][i]/2 (k = m, odd n);   Fo[i][k] = Q[k][me + i]
+//   Be[i][k] = Q[i][k];                                       Bo[i][k] = Q[i][me + k]
+int upload_split(fcgle_plan* P, int mu) {
+  const int64_t n = P->n[mu], me = P->me[mu], mo = P->mo[mu], m = n / 2, ld = P->ldsp[mu];
+  const std::vector<double>& Q = P->Q[mu];
+  std::vector<double> F(2 * ld * ld, 0.0), B(2 * ld * ld, 0.0);
+  for (int64_t i = 0; i < me; ++i)
+    for (int64_t k = 0; k < me; ++k) {
+      F[i * ld + k] = (k < m) ? Q[k * n + i] : 0.5 * Q[m * n + i];
+      B[i * ld + k] = Q[i * n + k];
+    }
+  for (int64_t i = 0; i < mo; ++i)
+    for (int64_t k = 0; k < mo; ++k) {
+      F[ld * ld + i * ld + k] = Q[k * n + me + i];
+      B[ld * ld + i * ld + k] = Q[i * n + me + k];
+    }
+  const int pr = precision_of(P);
+  auto up = [&](const std::vector<double>& M, void** dst) -> int {
+    if (pr == P_F64) {
+      FC_TRY(plan_alloc(dst, M.size() * sizeof(double)));
+      HIP_TRY(hipMemcpy(*dst, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(M.begin(), M.end());
+      FC_TRY(plan_alloc(dst, f.size() * sizeof(float)));
+      HIP_TRY(hipMemcpy(*dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    return FCGLE_OK;
+  };
+  FC_TRY(up(F, &P->Mfs[mu]));
+  FC_TRY(up(B, &P->Mbs[mu]));
+  return FCGLE_OK;
+}
+
 SepParams sep_base(const fcgle_plan* P) {
   SepParams s;
   s.d = P->d;
@@ -144,8 +181,8 @@ int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
     tl.e0 = P->ev_pool[2 * P->timed.size()];
     tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
     tl.axis = axis;
-    tl.fwd = (L.M == P->Mf[axis]) ? 1 : 0;
-    tl.sig = ((((L.prec * 4 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
+    tl.fwd = L.split ? (L.split == 1 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
+    tl.sig = L.split * 512 + ((((L.prec * 4 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
     HIP_TRY(hipEventRecord(tl.e0, st));
   }
   HIP_TRY(launch_mode_product(L, st));
@@ -166,8 +203,16 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
   L.A = A;
   L.B = B;
   L.n = (int)P->n[mu];
-  L.npad = P->npad[mu];
-  L.M = fwd ? P->Mf[mu] : P->Mb[mu];
+  if (P->split) {
+    L.split = fwd ? 1 : 2;
+    L.me = P->me[mu];
+    L.mo = P->mo[mu];
+    L.npad = P->ldsp[mu];
+    L.M = fwd ? P->Mfs[mu] : P->Mbs[mu];
+  } else {
+    L.npad = P->npad[mu];
+    L.M = fwd ? P->Mf[mu] : P->Mb[mu];
+  }
   return L;
 }
 
@@ -253,11 +298,14 @@ int ensure_state_buffers(fcgle_plan* P) {
   return FCGLE_OK;
 }
 
-int default_cfg(int pr, int64_t n) {
-  // smallest row tile that covers n (fewest padded MFMA rows), else the largest
+int default_cfg(int pr, int64_t n, bool split) {
+  // smallest row tile that covers the rows of one tile column (fewest padded MFMA rows),
+  // else the largest; the split forms tile blocks of n - n/2 rows
+  const int64_t rows = split ? n - n / 2 : n;
+  const int sp = split ? 1 : 0;
   int best = 0;
   for (int c = 0; c < kNumCfg; ++c)
-    if (cfg_rows(pr, c) >= n && cfg_rows(pr, c) <= cfg_rows(pr, best)) best = c;
+    if (cfg_rows(pr, c, sp) >= rows && cfg_rows(pr, c, sp) <= cfg_rows(pr, best, sp)) best = c;
   return best;
 }
 
@@ -442,6 +490,18 @@ int vjp_run_impl(fcgle_plan* P, const void* u_start, int64_t m, void* ubar, doub
   return FCGLE_OK;
 }
 
+// Eigenpairs (Q row-major, column k <-> l[k]) reordered by ascending eigenvalue.
+void sorted_eigenpairs(int64_t n, const std::vector<double>& q, const std::vector<double>& l, double* Q,
+                       double* lambda) {
+  std::vector<int64_t> order(n);
+  for (int64_t k = 0; k < n; ++k) order[k] = k;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return l[a] < l[b]; });
+  for (int64_t k = 0; k < n; ++k) {
+    lambda[k] = l[order[k]];
+    for (int64_t i = 0; i < n; ++i) Q[i * n + k] = q[i * n + order[k]];
+  }
+}
+
 void free_plan(fcgle_plan* P) {
   auto f = [](void* q) {
     if (q) (void)hipFree(q);
@@ -453,6 +513,8 @@ void free_plan(fcgle_plan* P) {
   for (int m = 0; m < 4; ++m) {
     f(P->Mf[m]);
     f(P->Mb[m]);
+    f(P->Mfs[m]);
+    f(P->Mbs[m]);
     f(P->dlam[m]);
   }
   for (auto& g : P->grids) f(g.F);
@@ -491,10 +553,9 @@ int fcgle_host_eig(int64_t n, double alpha, double h, int fd_order, double* Q, d
   if (!Q || !lambda || n < 1 || n > 8192 || !(alpha > 0.0 && alpha <= 2.0) || !(h > 0.0) ||
       (fd_order != 2 && fd_order != 4))
     return fail(FCGLE_ERR_ARG, "host_eig: bad argument");
-  std::vector<double> q, l;
-  if (!toeplitz_eig(n, alpha, h, fd_order, q, l)) return fail(FCGLE_ERR_ARG, "host_eig: QR did not converge");
-  std::memcpy(Q, q.data(), n * n * sizeof(double));
-  std::memcpy(lambda, l.data(), n * sizeof(double));
+  SplitEig se;
+  if (!toeplitz_eig_split(n, alpha, h, fd_order, se)) return fail(FCGLE_ERR_ARG, "host_eig: QR did not converge");
+  sorted_eigenpairs(n, se.Q, se.lam, Q, lambda);
   return FCGLE_OK;
 }
 
@@ -552,13 +613,27 @@ int fcgle_setup(int d, const int64_t* n, const double* alpha, const double* h, c
     P->h[m] = h[m];
     P->npad[m] = (int)round_up(n[m], 256);
   }
-  // FP64 eigendecompositions on the host, axes in parallel.
+  // FP64 eigendecompositions on the host, axes in parallel, through the even/odd blocks of
+  // the persymmetric D (eigenpairs in block order: even block, then odd block).
   std::vector<int> ok(d, 0);
+  std::vector<SplitEig> se(d);
   {
     std::vector<std::thread> th;
     for (int m = 0; m < d; ++m)
-      th.emplace_back([&, m] { ok[m] = toeplitz_eig(n[m], alpha[m], h[m], fd_order, P->Q[m], P->lam[m]); });
+      th.emplace_back([&, m] {
+        ok[m] = toeplitz_eig_split(n[m], alpha[m], h[m], fd_order, se[m]);
+        if (ok[m]) {
+          P->Q[m].swap(se[m].Q);
+          P->lam[m].swap(se[m].lam);
+        }
+      });
     for (auto& t : th) t.join();
+  }
+  P->split = split_supported(precision_of(P));
+  for (int m = 0; m < d; ++m) {
+    P->me[m] = (int)se[m].me;
+    P->mo[m] = (int)se[m].mo;
+    P->ldsp[m] = (int)round_up(se[m].me, 128);
   }
   int rc = FCGLE_OK;
   for (int m = 0; m < d && rc == FCGLE_OK; ++m)
@@ -571,12 +646,13 @@ int fcgle_setup(int d, const int64_t* n, const double* alpha, const double* h, c
       for (int64_t k = 0; k < nm; ++k) QT[i * nm + k] = P->Q[m][k * nm + i];
     rc = upload_matrix(P, QT, nm, P->npad[m], &P->Mf[m]);
     if (rc == FCGLE_OK) rc = upload_matrix(P, P->Q[m], nm, P->npad[m], &P->Mb[m]);
+    if (rc == FCGLE_OK && split_supported(pr)) rc = upload_split(P, m);
     if (rc == FCGLE_OK) rc = plan_alloc((void**)&P->dlam[m], nm * sizeof(double));
     if (rc == FCGLE_OK) {
       e = hipMemcpy(P->dlam[m], P->lam[m].data(), nm * sizeof(double), hipMemcpyHostToDevice);
       if (e != hipSuccess) rc = fail(FCGLE_ERR_HIP, "hipMemcpy: %s", hipGetErrorString(e));
     }
-    P->cfg[m][0] = P->cfg[m][1] = default_cfg(pr, nm);
+    P->cfg[m][0] = P->cfg[m][1] = default_cfg(pr, nm, P->split);
   }
   for (int k = 0; k < 3 && rc == FCGLE_OK; ++k) rc = plan_alloc(&P->s[k], (size_t)N * P->elem);
   if (rc == FCGLE_OK) rc = plan_alloc((void**)&P->dflag, sizeof(int));
@@ -600,8 +676,7 @@ void fcgle_destroy(fcgle_plan* plan) {
 int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda) {
   FC_TRY(check_plan(plan));
   if (mu < 0 || mu >= plan->d || !Q || !lambda) return fail(FCGLE_ERR_ARG, "get_eig: bad argument");
-  std::memcpy(Q, plan->Q[mu].data(), plan->Q[mu].size() * sizeof(double));
-  std::memcpy(lambda, plan->lam[mu].data(), plan->lam[mu].size() * sizeof(double));
+  sorted_eigenpairs(plan->n[mu], plan->Q[mu], plan->lam[mu], Q, lambda);
   return FCGLE_OK;
 }
 
@@ -842,6 +917,20 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
   return FCGLE_OK;
 }
 
+int fcgle_set_structure(fcgle_plan* plan, int split) {
+  FC_TRY(check_plan(plan));
+  if (split != 0 && split != 1) return fail(FCGLE_ERR_ARG, "set_structure: split must be 0 or 1");
+  if (split && !split_supported(precision_of(plan)))
+    return fail(FCGLE_ERR_UNSUPPORTED, "set_structure: no even/odd kernels for this precision");
+  if ((bool)split != plan->split) {
+    plan->split = (split != 0);
+    for (int m = 0; m < plan->d; ++m)
+      plan->cfg[m][0] = plan->cfg[m][1] = default_cfg(precision_of(plan), plan->n[m], plan->split);
+    plan->tuned = false;
+  }
+  return FCGLE_OK;
+}
+
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
   if (flags < 0 || flags > 3) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..3");
@@ -858,10 +947,12 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   for (int m = 0; m < plan->d; ++m) s += std::to_string(plan->n[m]) + (m + 1 < plan->d ? "," : ")");
   s += std::string(" precision=") + names[plan->prec] + " tiles[axis](bwd/fwd rows x cols)=";
   const int pr = precision_of(plan);
+  const int sp = plan->split ? 1 : 0;
   for (int m = 0; m < plan->d; ++m) {
-    s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0])) +
-         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1])) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1])) + "]";
+    s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0], sp)) +
+         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1], sp)) + "]";
   }
+  s += plan->split ? " structure=even-odd" : " structure=dense";
   s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");
   s += plan->tuned ? " tuned" : " default";
   std::snprintf(buf, len, "%s", s.c_str());

@@ -6,34 +6,57 @@
 namespace fcgle {
 
 // Rows (M tile) and complex columns per workgroup of the three configurations of each
-// precision; index [prec][cfg].
-constexpr int kCfgRows[4][kNumCfg] = {{256, 128, 64}, {256, 128, 64}, {256, 128, 64}, {128, 64, 64}};
-constexpr int kCfgCols[4][kNumCfg] = {{32, 32, 32}, {64, 64, 64}, {64, 64, 64}, {64, 64, 32}};
+// precision; index [split ? 1 : 0][prec][cfg].  The even/odd split kernels contract half-size
+// blocks (at most n/2 + 1 rows each) and the backward form carries two accumulator sets, so
+// their tiles are smaller.
+constexpr int kCfgRows[2][4][kNumCfg] = {{{256, 128, 64}, {256, 128, 64}, {256, 128, 64}, {128, 64, 64}},
+                                         {{128, 64, 64}, {128, 64, 128}, {128, 64, 64}, {64, 64, 64}}};
+constexpr int kCfgCols[2][4][kNumCfg] = {{{32, 32, 32}, {64, 64, 64}, {64, 64, 64}, {64, 64, 32}},
+                                         {{32, 32, 16}, {64, 64, 32}, {64, 64, 32}, {64, 32, 32}}};
 
-template <class K, class T>
-hipError_t dispatch_cfg(const MPLaunch& L, hipStream_t s) {
+// Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
+// combinations a structure never needs are not instantiated.
+template <class K, class T, int SP>
+hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   using R = typename K::R;
   const bool tl = (L.B == 1);
   if (!tl) {
     if (L.ek != EpiKind::Store) return hipErrorInvalidValue;
-    if (L.pk == ProKind::Id) return K::template go<T, false, ProIdF, EpiStoreF<R>>(L, s);
-    return K::template go<T, false, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+    if (L.pk == ProKind::Id) return K::template go<T, false, SP, ProIdF, EpiStoreF<R>>(L, s);
+    if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+    return hipErrorInvalidValue;
   }
   if (L.pk != ProKind::Id) return hipErrorInvalidValue;
   switch (L.ek) {
     case EpiKind::Store:
-      return K::template go<T, true, ProIdF, EpiStoreF<R>>(L, s);
+      return K::template go<T, true, SP, ProIdF, EpiStoreF<R>>(L, s);
     case EpiKind::Grid:
-      return K::template go<T, true, ProIdF, EpiGridF<R>>(L, s);
+      if constexpr (SP != kSplitBwd) return K::template go<T, true, SP, ProIdF, EpiGridF<R>>(L, s);
+      return hipErrorInvalidValue;
     case EpiKind::Sep:
-      return K::template go<T, true, ProIdF, EpiSepF<R>>(L, s);
+      if constexpr (SP != kSplitBwd) return K::template go<T, true, SP, ProIdF, EpiSepF<R>>(L, s);
+      return hipErrorInvalidValue;
     case EpiKind::ExpEuler:
-      return K::template go<T, true, ProIdF, EpiExpEulerF<R>>(L, s);
+      if constexpr (SP != kSplitBwd) return K::template go<T, true, SP, ProIdF, EpiExpEulerF<R>>(L, s);
+      return hipErrorInvalidValue;
     case EpiKind::KeepOld:
-      return K::template go<T, true, ProIdF, EpiKeepOldF<R>>(L, s);
+      if constexpr (SP != kSplitFwd) return K::template go<T, true, SP, ProIdF, EpiKeepOldF<R>>(L, s);
+      return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
   }
+}
+
+template <class K, class T>
+hipError_t dispatch_cfg(const MPLaunch& L, hipStream_t s) {
+  return dispatch_combo<K, T, kDense>(L, s);
+}
+
+template <class K, class T>
+hipError_t dispatch_split(const MPLaunch& L, hipStream_t s) {
+  if (L.split == kSplitFwd) return dispatch_combo<K, T, kSplitFwd>(L, s);
+  if (L.split == kSplitBwd) return dispatch_combo<K, T, kSplitBwd>(L, s);
+  return hipErrorInvalidValue;
 }
 
 }  // namespace fcgle

@@ -264,6 +264,92 @@ bool toeplitz_eig(int64_t n, double alpha, double h, int fd_order, std::vector<d
   return true;
 }
 
+namespace {
+
+// One Newton-Schulz sweep X <- X + X (I - X^T X) / 2 of the m x m block eigenvector matrix
+// V (row-major, columns = eigenvectors) in long double, and Rayleigh quotients
+// lam_c = x_c^T A x_c with the block A given in long double.
+void sweep_block(int64_t m, const std::vector<double>& V, const std::vector<long double>& A,
+                 std::vector<long double>& X, std::vector<long double>& lam) {
+  using ld = long double;
+  X.assign(V.begin(), V.end());
+  std::vector<ld> H(m * m);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t j = i; j < m; ++j) {
+      ld acc = 0;
+      for (int64_t k = 0; k < m; ++k) acc += X[k * m + i] * X[k * m + j];
+      const ld v = (i == j ? (ld)1 : (ld)0) - acc;
+      H[i * m + j] = v;
+      H[j * m + i] = v;
+    }
+  std::vector<ld> Xn(X);
+  for (int64_t r = 0; r < m; ++r)
+    for (int64_t k = 0; k < m; ++k) {
+      const ld f = X[r * m + k] / 2;
+      for (int64_t c = 0; c < m; ++c) Xn[r * m + c] += f * H[k * m + c];
+    }
+  lam.assign(m, 0);
+  for (int64_t r = 0; r < m; ++r)
+    for (int64_t k = 0; k < m; ++k) {
+      const ld a = A[r * m + k];
+      for (int64_t c = 0; c < m; ++c) lam[c] += Xn[r * m + c] * a * Xn[k * m + c];
+    }
+  X.swap(Xn);
+}
+
+}  // namespace
+
+bool toeplitz_eig_split(int64_t n, double alpha, double h, int fd_order, SplitEig& s) {
+  using ld = long double;
+  const std::vector<double> g = fd_weights(alpha, n, fd_order);
+  const double scale = -std::pow(h, -alpha);
+  std::vector<double> t(n);
+  for (int64_t k = 0; k < n; ++k) t[k] = scale * g[k];
+  const int64_t m = n / 2, me = n - m, mo = m;
+  s.n = n;
+  s.me = me;
+  s.mo = mo;
+  // the blocks in long double (the sums of two doubles are exact there) and in double
+  const ld sq2 = std::sqrt((ld)2);
+  std::vector<ld> Ae(me * me), Ao(mo * mo);
+  for (int64_t i = 0; i < m; ++i)
+    for (int64_t k = 0; k < m; ++k) {
+      const ld a = t[i > k ? i - k : k - i], b = t[n - 1 - i - k];
+      Ae[i * me + k] = a + b;
+      Ao[i * mo + k] = a - b;
+    }
+  if (me > m) {  // odd n: the middle point belongs to the even block
+    for (int64_t i = 0; i < m; ++i) Ae[i * me + m] = Ae[m * me + i] = sq2 * (ld)t[m - i];
+    Ae[m * me + m] = t[0];
+  }
+  std::vector<double> De(Ae.begin(), Ae.end()), Do(Ao.begin(), Ao.end());
+  std::vector<double> Ve, le, Vo, lo;
+  if (!sym_eig(me, De, Ve, le)) return false;
+  if (mo > 0 && !sym_eig(mo, Do, Vo, lo)) return false;
+  std::vector<ld> Xe, Xo, lame, lamo;
+  sweep_block(me, Ve, Ae, Xe, lame);
+  if (mo > 0) sweep_block(mo, Vo, Ao, Xo, lamo);
+  // Q = Z diag(Xe, Xo), rounded once from long double, with the mirror entries copied so the
+  // even/odd structure holds exactly in FP64
+  const ld r2 = 1 / sq2;
+  s.Q.assign(n * n, 0.0);
+  s.lam.resize(n);
+  for (int64_t k = 0; k < me; ++k) {
+    s.lam[k] = (double)lame[k];
+    for (int64_t i = 0; i < m; ++i) s.Q[i * n + k] = s.Q[(n - 1 - i) * n + k] = (double)(r2 * Xe[i * me + k]);
+    if (me > m) s.Q[m * n + k] = (double)Xe[m * me + k];
+  }
+  for (int64_t k = 0; k < mo; ++k) {
+    s.lam[me + k] = (double)lamo[k];
+    for (int64_t i = 0; i < m; ++i) {
+      const double v = (double)(r2 * Xo[i * mo + k]);
+      s.Q[i * n + me + k] = v;
+      s.Q[(n - 1 - i) * n + me + k] = -v;
+    }
+  }
+  return true;
+}
+
 // --- bfloat16 ----------------------------------------------------------------------------
 
 uint16_t bf16_round(double x) {

@@ -21,6 +21,24 @@ bool sym_eig(int64_t n, std::vector<double>& A, std::vector<double>& Q, std::vec
 bool toeplitz_eig(int64_t n, double alpha, double h, int fd_order, std::vector<double>& Q,
                   std::vector<double>& lambda);
 
+// Even/odd splitting of the symmetric Toeplitz D = -h^{-alpha} Toeplitz(g).  D is
+// persymmetric (J D J = D, J the exchange matrix), so with m = floor(n/2) the orthogonal
+// Z whose columns are (e_k + e_{n-1-k})/sqrt(2) (k < m), e_m (odd n only), then
+// (e_k - e_{n-1-k})/sqrt(2) (k < m) block-diagonalises it: Z^T D Z = diag(De, Do), De of
+// size me = n - m, Do of size mo = m, with (i, k < m, t_k = D[0][k])
+//   De[i][k] = t_|i-k| + t_{n-1-i-k},  Do[i][k] = t_|i-k| - t_{n-1-i-k},
+//   De[i][m] = De[m][i] = sqrt(2) t_{m-i},  De[m][m] = t_0   (odd n).
+// Each block is diagonalised by sym_eig, then given one Newton-Schulz orthogonalisation
+// sweep and Rayleigh-quotient eigenvalues in long double; Q = Z diag(Ve, Vo) is rounded once
+// from long double with its mirror entries copied, so Q[n-1-i][k] = +-Q[i][k] holds exactly
+// (+ for the me even columns, - for the mo odd ones).
+struct SplitEig {
+  int64_t n = 0, me = 0, mo = 0;
+  std::vector<double> Q;    // n x n row-major, column k <-> lam[k]
+  std::vector<double> lam;  // block order: even block (ascending), then odd block (ascending)
+};
+bool toeplitz_eig_split(int64_t n, double alpha, double h, int fd_order, SplitEig& s);
+
 // Round a double to the nearest bfloat16 (ties to even); returns the bf16 bits.
 uint16_t bf16_round(double x);
 double bf16_value(uint16_t b);

@@ -354,13 +354,28 @@ struct TileCfg {
   static_assert(TM % 64 == 0, "rows per tile");
 };
 
+// Structure of a mode product.
+//  kDense:    out[a, i, b] = sum_{k<n} M[i, k] in[a, k, b]                    (M = Q^T or Q)
+//  kSplitFwd: Q^T with Q = Z diag(Ve, Vo) (the even/odd block form of a persymmetric D):
+//             a row tile lies in the even block (eigen rows [0, me)) or the odd block
+//             (rows [me, n)) and contracts only the half-length combination
+//             out[a, base + i, b] = sum_{k<K} Mblk[i, k] (in[a, k, b] +- in[a, n-1-k, b]),
+//             K = me or mo, with the 1/sqrt(2) (1/2 for the odd-n middle) folded into Mblk.
+//  kSplitBwd: Q: two half-length contractions per physical row i < me,
+//             p_i = sum_{k<me} Me[i, k] in[a, k, b], q_i = sum_{k<mo} Mo[i, k] in[a, me+k, b],
+//             then out[a, i, b] = p_i + q_i and, for i < mo, out[a, n-1-i, b] = p_i - q_i.
+// Both split forms do half the multiply-adds of kDense for the same bytes moved.
+enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2 };
+
 struct Geo {
   uint32_t A, B;      // batch (slower) and inner (faster) extents, complex elements
-  int n, npad;        // contraction length and padded leading dimension of M
-  int ntm;            // number of M tiles
+  int n, npad;        // axis length; leading dimension of M (of each block matrix when split)
+  int ntm;            // number of row tiles
   uint32_t bt;        // N loader: column tiles per batch index
   uint32_t nblocks;   // total workgroups
-  int vec_ok;         // unused by the kernels (kept for layout stability)
+  int me, mo;         // split: even and odd block sizes
+  int te;             // kSplitFwd: row tiles of the even block
+  int pad_;
 };
 
 template <class R>
@@ -392,27 +407,31 @@ struct MfmaT<double> {
 // N loader: column b of batch a (element stride B along k).  T loader: row a (k contiguous).
 // Loads are raw; the prologue is applied when the unit is written to LDS, so that the
 // global loads of the next k-tile stay in flight during the MFMA work of the current one.
+// Element k (kb <= k < kb + G) of a B unit is tensor row koff + k, or n - 1 - k when rev;
+// rows with k >= klim read as zero.
 template <class C, int G, bool TL>
 __device__ __forceinline__ void load_b_unit(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
-                                            int kb, C (&v)[G]) {
+                                            int kb, int klim, int koff, bool rev, C (&v)[G]) {
 #pragma unroll
   for (int e = 0; e < G; ++e) {
     const int k = kb + e;
-    const bool ok = TL ? (a < g.A && k < g.n) : (b < g.B && k < g.n);
-    const int64_t j = TL ? (int64_t)a * g.n + k : ((int64_t)a * g.n + k) * g.B + b;
+    const int row = rev ? g.n - 1 - k : koff + k;
+    const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
+    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
     v[e] = ok ? U[j] : C{0, 0};
   }
 }
 
 template <class C, int G, bool TL, class Pro>
-__device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b, int kb, const Pro& pro,
-                                           C (&v)[G]) {
+__device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b, int kb, int klim, int koff,
+                                           bool rev, const Pro& pro, C (&v)[G]) {
   if (Pro::kId) return;
 #pragma unroll
   for (int e = 0; e < G; ++e) {
     const int k = kb + e;
-    const bool ok = TL ? (a < g.A && k < g.n) : (b < g.B && k < g.n);
-    const int64_t j = TL ? (int64_t)a * g.n + k : ((int64_t)a * g.n + k) * g.B + b;
+    const int row = rev ? g.n - 1 - k : koff + k;
+    const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
+    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
     if (ok) v[e] = pro(j, v[e]);
   }
 }
@@ -436,9 +455,12 @@ constexpr bool kTlDirectEpilogue = true;
 constexpr bool kTlDirectEpilogue = false;
 #endif
 
-template <class R, class T, bool TL, class Epi, class Get, class RowMap>
-__device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint32_t c0, int m0, const Epi& epi,
-                                             Get get, RowMap rowmap, void* smem) {
+// Rows m0 + r of the tile (r < TM) are valid below row_end; phys(i) maps a valid row to the
+// index along the mode axis that the output element has (identity except for the mirrored
+// half of kSplitBwd).
+template <class R, class T, bool TL, class Epi, class Get, class RowMap, class Phys>
+__device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint32_t c0, int m0, int row_end,
+                                             const Epi& epi, Get get, RowMap rowmap, Phys phys, void* smem) {
   using C = typename Cx<R>::T;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
@@ -457,8 +479,9 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
         R re[4], im[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          i[r] = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
-          ok[r] = i[r] < g.n;
+          const int row = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
+          ok[r] = row < row_end;
+          i[r] = phys(row);
           j[r] = ((int64_t)a_fix * g.n + i[r]) * g.B + col;
           re[r] = get(fm, fn, 0, r);
           im[r] = get(fm, fn, 1, r);
@@ -483,8 +506,9 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
         R re[4], im[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          i[r] = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
-          ok[r] = i[r] < g.n;
+          const int row = m0 + wm * T::WTM + fm * 16 + rowmap(lane, r);
+          ok[r] = row < row_end;
+          i[r] = phys(row);
           j[r] = (int64_t)col * g.n + i[r];
           re[r] = get(fm, fn, 0, r);
           im[r] = get(fm, fn, 1, r);
@@ -523,8 +547,8 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const int row = lane + 64 * v;
-          i[v] = m0 + row;
-          ok[v] = i[v] < g.n;
+          ok[v] = m0 + row < row_end;
+          i[v] = phys(m0 + row);
           j[v] = (int64_t)col * g.n + i[v];
           const C x = Cs[cc * LDC + row];
           re[v] = x.x;
@@ -548,8 +572,9 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 // FP64 / FP32 MFMA mode product
 // ---------------------------------------------------------------------------------------
 
-// One workgroup's tile (logical block index bid) of the mode product described by g.
-template <class R, class T, bool TL, class Pro, class Epi>
+// One workgroup's tile (logical block index bid) of the mode product described by g, with
+// structure SP (kDense / kSplitFwd / kSplitBwd, see Geo).
+template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__ M,
                                              const typename Cx<R>::T* __restrict__ U, const Pro& pro,
                                              const Epi& epi, uint32_t bid) {
@@ -559,20 +584,40 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   using acc_t = typename MT::acc_t;
   constexpr int G = MT::G;
   constexpr int TM = T::TM, TNC = T::TNC, TK = T::TK;
+  constexpr int NB = (SP == kSplitBwd) ? 2 : 1;  // operand pairs (even / odd block)
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
-  constexpr size_t kAsBytes = (size_t)2 * TM * LDK * sizeof(R);
-  constexpr size_t kBsBytes = (size_t)2 * 2 * TNC * LDK * sizeof(R);
-  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? epi_lds_bytes<C, T>() : 0);
+  constexpr size_t kAsBytes = (size_t)2 * NB * TM * LDK * sizeof(R);
+  constexpr size_t kBsBytes = (size_t)2 * NB * 2 * TNC * LDK * sizeof(R);
+  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? (size_t)16 * (TM + 1) * sizeof(C) : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
-  R (*As)[TM * LDK] = reinterpret_cast<R (*)[TM * LDK]>(smem);
-  R (*Bs)[2 * TNC * LDK] = reinterpret_cast<R (*)[2 * TNC * LDK]>(smem + kAsBytes);
+  R (*As)[NB][TM * LDK] = reinterpret_cast<R (*)[NB][TM * LDK]>(smem);
+  R (*Bs)[NB][2 * TNC * LDK] = reinterpret_cast<R (*)[NB][2 * TNC * LDK]>(smem + kAsBytes);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
   const int mt = (int)(bid % (uint32_t)g.ntm);
   const uint32_t ct = bid / (uint32_t)g.ntm;
-  const int m0 = mt * TM;
+  // row tile -> block, first row, contraction length, valid rows
+  int m0, K, row_end, base = 0;
+  bool odd = false;
+  const R* Ma = M;
+  if (SP == kDense) {
+    m0 = mt * TM;
+    K = g.n;
+    row_end = g.n;
+  } else if (SP == kSplitFwd) {
+    odd = mt >= g.te;
+    m0 = (odd ? mt - g.te : mt) * TM;
+    K = odd ? g.mo : g.me;
+    row_end = K;
+    base = odd ? g.me : 0;
+    Ma = M + (odd ? (int64_t)g.npad * g.npad : 0);
+  } else {
+    m0 = mt * TM;
+    K = g.me;
+    row_end = g.me;
+  }
   uint32_t a_fix = 0, c0;
   if (TL) {
     c0 = ct * TNC;
@@ -586,9 +631,10 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   constexpr int AIT = (AU + T::THREADS - 1) / T::THREADS;
   constexpr int BU = TNC * KU;
   constexpr int BIT = (BU + T::THREADS - 1) / T::THREADS;
+  constexpr int NR = (SP == kDense) ? 1 : 2;  // B values per unit element (pair or block)
 
-  fragT ra[AIT];
-  C rb[BIT][G];
+  fragT ra[NB][AIT];
+  C rb[NR][BIT][G];
 
   auto unit_b = [&](int u, int& row, int& kq) {
     if (TL) {
@@ -602,11 +648,15 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int u = tid + it * T::THREADS;
-      if (AU % T::THREADS == 0 || u < AU) {
-        const int row = u / KU, kq = u % KU;
-        ra[it] = *(const fragT*)&M[(int64_t)(m0 + row) * g.npad + k0 + kq * G];
+    for (int h = 0; h < NB; ++h) {
+      const R* Mh = Ma + (int64_t)h * g.npad * g.npad;
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int u = tid + it * T::THREADS;
+        if (AU % T::THREADS == 0 || u < AU) {
+          const int row = u / KU, kq = u % KU;
+          ra[h][it] = *(const fragT*)&Mh[(int64_t)(m0 + row) * g.npad + k0 + kq * G];
+        }
       }
     }
 #pragma unroll
@@ -615,81 +665,114 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
         unit_b(u, row, kq);
-        if (TL)
-          load_b_unit<C, G, TL>(g, U, c0 + row, 0, k0 + kq * G, rb[it]);
-        else
-          load_b_unit<C, G, TL>(g, U, a_fix, c0 + row, k0 + kq * G, rb[it]);
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        const int kb = k0 + kq * G;
+        if (SP == kDense) {
+          load_b_unit<C, G, TL>(g, U, a, b, kb, g.n, 0, false, rb[0][it]);
+        } else if (SP == kSplitFwd) {
+          load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
+          load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+        } else {
+          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
+          load_b_unit<C, G, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
+        }
       }
     }
+  };
+  auto put_b = [&](R (*dst)[2 * TNC * LDK], int buf, int row, int kq, const C (&v)[G]) {
+    fragT re, im;
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      re[e] = v[e].x;
+      im[e] = v[e].y;
+    }
+    *(fragT*)&dst[buf][row * LDK + kq * G] = re;
+    *(fragT*)&dst[buf][(TNC + row) * LDK + kq * G] = im;
   };
   auto sstore = [&](int buf, int kt) {
     const int k0 = kt * TK;
 #pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int u = tid + it * T::THREADS;
-      if (AU % T::THREADS == 0 || u < AU) {
-        const int row = u / KU, kq = u % KU;
-        *(fragT*)&As[buf][row * LDK + kq * G] = ra[it];
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int u = tid + it * T::THREADS;
+        if (AU % T::THREADS == 0 || u < AU) {
+          const int row = u / KU, kq = u % KU;
+          *(fragT*)&As[buf][h][row * LDK + kq * G] = ra[h][it];
+        }
       }
-    }
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
         unit_b(u, row, kq);
-        if (TL)
-          pro_b_unit<C, G, TL, Pro>(g, c0 + row, 0, k0 + kq * G, pro, rb[it]);
-        else
-          pro_b_unit<C, G, TL, Pro>(g, a_fix, c0 + row, k0 + kq * G, pro, rb[it]);
-        fragT re, im;
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        const int kb = k0 + kq * G;
+        if (SP == kDense) {
+          pro_b_unit<C, G, TL, Pro>(g, a, b, kb, g.n, 0, false, pro, rb[0][it]);
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, rb[0][it]);
+        } else if (SP == kSplitFwd) {
+          pro_b_unit<C, G, TL, Pro>(g, a, b, kb, K, 0, false, pro, rb[0][it]);
+          pro_b_unit<C, G, TL, Pro>(g, a, b, kb, K, 0, true, pro, rb[NR - 1][it]);
+          C v[G];
+          const R sg = odd ? (R)-1 : (R)1;
 #pragma unroll
-        for (int e = 0; e < G; ++e) {
-          re[e] = rb[it][e].x;
-          im[e] = rb[it][e].y;
+          for (int e = 0; e < G; ++e) {
+            v[e].x = rb[0][it][e].x + sg * rb[NR - 1][it][e].x;
+            v[e].y = rb[0][it][e].y + sg * rb[NR - 1][it][e].y;
+          }
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, v);
+        } else {
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, rb[0][it]);
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB + 1, row, kq, rb[NR - 1][it]);
         }
-        *(fragT*)&Bs[buf][row * LDK + kq * G] = re;
-        *(fragT*)&Bs[buf][(TNC + row) * LDK + kq * G] = im;
       }
     }
   };
 
-  acc_t acc[T::FM][T::FNC][2];
+  acc_t acc[NB][T::FM][T::FNC][2];
 #pragma unroll
-  for (int fm = 0; fm < T::FM; ++fm)
+  for (int h = 0; h < NB; ++h)
 #pragma unroll
-    for (int fn = 0; fn < T::FNC; ++fn)
-#pragma unroll
-      for (int p = 0; p < 2; ++p)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[fm][fn][p][r] = 0;
-
-  const int lr = lane & 15, lk = (lane >> 4) * G;
-  auto compute = [&](int buf) {
-    const R* as = As[buf];
-    const R* bs = Bs[buf];
-#pragma unroll
-    for (int kg = 0; kg < TK; kg += 4 * G) {
-      fragT bf[T::FNC][2];
+    for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
       for (int fn = 0; fn < T::FNC; ++fn)
 #pragma unroll
         for (int p = 0; p < 2; ++p)
-          bf[fn][p] = *(const fragT*)&bs[(p * TNC + wn * T::WTNC + fn * 16 + lr) * LDK + kg + lk];
 #pragma unroll
-      for (int fm = 0; fm < T::FM; ++fm) {
-        const fragT af = *(const fragT*)&as[(wm * T::WTM + fm * 16 + lr) * LDK + kg + lk];
+          for (int r = 0; r < 4; ++r) acc[h][fm][fn][p][r] = 0;
+
+  const int lr = lane & 15, lk = (lane >> 4) * G;
+  auto compute = [&](int buf) {
 #pragma unroll
-        for (int s = 0; s < G; ++s)
+    for (int h = 0; h < NB; ++h) {
+      const R* as = As[buf][h];
+      const R* bs = Bs[buf][h];
 #pragma unroll
-          for (int fn = 0; fn < T::FNC; ++fn)
+      for (int kg = 0; kg < TK; kg += 4 * G) {
+        fragT bf[T::FNC][2];
 #pragma unroll
-            for (int p = 0; p < 2; ++p) acc[fm][fn][p] = MT::mma(af[s], bf[fn][p][s], acc[fm][fn][p]);
+        for (int fn = 0; fn < T::FNC; ++fn)
+#pragma unroll
+          for (int p = 0; p < 2; ++p)
+            bf[fn][p] = *(const fragT*)&bs[(p * TNC + wn * T::WTNC + fn * 16 + lr) * LDK + kg + lk];
+#pragma unroll
+        for (int fm = 0; fm < T::FM; ++fm) {
+          const fragT af = *(const fragT*)&as[(wm * T::WTM + fm * 16 + lr) * LDK + kg + lk];
+#pragma unroll
+          for (int s = 0; s < G; ++s)
+#pragma unroll
+            for (int fn = 0; fn < T::FNC; ++fn)
+#pragma unroll
+              for (int p = 0; p < 2; ++p)
+                acc[h][fm][fn][p] = MT::mma(af[s], bf[fn][p][s], acc[h][fm][fn][p]);
+        }
       }
     }
   };
 
-  const int KT = (g.n + TK - 1) / TK;
+  const int KT = (K + TK - 1) / TK;
   gload(0);
   sstore(0, 0);
   __syncthreads();
@@ -701,16 +784,30 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
     __syncthreads();
   }
 
-  run_epilogue<R, T, TL>(
-      g, a_fix, c0, m0, epi, [&](int fm, int fn, int p, int r) { return (R)acc[fm][fn][p][r]; },
-      [](int l, int r) { return MT::row(l, r); }, smem);
+  auto rowmap = [](int l, int r) { return MT::row(l, r); };
+  if (SP != kSplitBwd) {
+    run_epilogue<R, T, TL>(
+        g, a_fix, c0, base + m0, base + row_end, epi,
+        [&](int fm, int fn, int p, int r) { return (R)acc[0][fm][fn][p][r]; }, rowmap, [](int i) { return i; },
+        smem);
+  } else {
+    const int n1 = g.n - 1;
+    run_epilogue<R, T, TL>(
+        g, a_fix, c0, m0, g.me, epi,
+        [&](int fm, int fn, int p, int r) { return (R)(acc[0][fm][fn][p][r] + acc[NB - 1][fm][fn][p][r]); },
+        rowmap, [](int i) { return i; }, smem);
+    run_epilogue<R, T, TL>(
+        g, a_fix, c0, m0, g.mo, epi,
+        [&](int fm, int fn, int p, int r) { return (R)(acc[0][fm][fn][p][r] - acc[NB - 1][fm][fn][p][r]); },
+        rowmap, [n1](int i) { return n1 - i; }, smem);
+  }
 }
 
-template <class R, class T, bool TL, class Pro, class Epi>
+template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __global__ void __launch_bounds__(T::THREADS)
     mp_mfma_kernel(Geo g, const R* __restrict__ M, const typename Cx<R>::T* __restrict__ U, Pro pro,
                    Epi epi) {
-  mp_mfma_tile<R, T, TL, Pro, Epi>(g, M, U, pro, epi, xcd_remap(blockIdx.x, g.nblocks));
+  mp_mfma_tile<R, T, TL, SP, Pro, Epi>(g, M, U, pro, epi, xcd_remap(blockIdx.x, g.nblocks));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -748,8 +845,8 @@ __global__ void __launch_bounds__(T::THREADS)
   const uint32_t b = xcd_remap(blockIdx.x, nblocks);
   const int k = find_item(items, count, b);
   const GroupItem<Pro, Epi>& it = items[k];
-  mp_mfma_tile<R, T, TL, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro, it.epi,
-                                   b - it.first);
+  mp_mfma_tile<R, T, TL, kDense, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro,
+                                           it.epi, b - it.first);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -837,9 +934,9 @@ __global__ void __launch_bounds__(T::THREADS)
         int row, kq;
         unit_b(u, row, kq);
         if (TL)
-          load_b_unit<C, LG, TL>(g, U, c0 + row, 0, k0 + kq * LG, rb[it]);
+          load_b_unit<C, LG, TL>(g, U, c0 + row, 0, k0 + kq * LG, g.n, 0, false, rb[it]);
         else
-          load_b_unit<C, LG, TL>(g, U, a_fix, c0 + row, k0 + kq * LG, rb[it]);
+          load_b_unit<C, LG, TL>(g, U, a_fix, c0 + row, k0 + kq * LG, g.n, 0, false, rb[it]);
       }
     }
   };
@@ -861,9 +958,9 @@ __global__ void __launch_bounds__(T::THREADS)
         int row, kq;
         unit_b(u, row, kq);
         if (TL)
-          pro_b_unit<C, LG, TL, Pro>(g, c0 + row, 0, k0 + kq * LG, pro, rb[it]);
+          pro_b_unit<C, LG, TL, Pro>(g, c0 + row, 0, k0 + kq * LG, g.n, 0, false, pro, rb[it]);
         else
-          pro_b_unit<C, LG, TL, Pro>(g, a_fix, c0 + row, k0 + kq * LG, pro, rb[it]);
+          pro_b_unit<C, LG, TL, Pro>(g, a_fix, c0 + row, k0 + kq * LG, g.n, 0, false, pro, rb[it]);
         v4bf re[NP], im[NP];
 #pragma unroll
         for (int e = 0; e < LG; ++e) {
@@ -943,8 +1040,8 @@ __global__ void __launch_bounds__(T::THREADS)
   }
 
   run_epilogue<float, T, TL>(
-      g, a_fix, c0, m0, epi, [&](int fm, int fn, int p, int r) { return acc[fm][fn][p][r]; },
-      [](int l, int r) { return MfmaT<float>::row(l, r); }, smem);
+      g, a_fix, c0, m0, g.n, epi, [&](int fm, int fn, int p, int r) { return acc[fm][fn][p][r]; },
+      [](int l, int r) { return MfmaT<float>::row(l, r); }, [](int i) { return i; }, smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -952,13 +1049,25 @@ __global__ void __launch_bounds__(T::THREADS)
 // ---------------------------------------------------------------------------------------
 
 template <class T>
-inline Geo make_geo(const MPLaunch& L, bool tl, int vec_units) {
+inline Geo make_geo(const MPLaunch& L, bool tl, int /*vec_units*/) {
   Geo g;
   g.A = (uint32_t)L.A;
   g.B = (uint32_t)L.B;
   g.n = L.n;
   g.npad = L.npad;
-  g.ntm = (L.n + T::TM - 1) / T::TM;
+  g.me = L.me;
+  g.mo = L.mo;
+  g.pad_ = 0;
+  if (L.split == kSplitFwd) {
+    g.te = (L.me + T::TM - 1) / T::TM;
+    g.ntm = g.te + (L.mo + T::TM - 1) / T::TM;
+  } else if (L.split == kSplitBwd) {
+    g.te = 0;
+    g.ntm = (L.me + T::TM - 1) / T::TM;
+  } else {
+    g.te = 0;
+    g.ntm = (L.n + T::TM - 1) / T::TM;
+  }
   if (tl) {
     g.bt = 1;
     g.nblocks = (uint32_t)(((L.A + T::TNC - 1) / T::TNC) * g.ntm);
@@ -966,7 +1075,6 @@ inline Geo make_geo(const MPLaunch& L, bool tl, int vec_units) {
     g.bt = (uint32_t)((L.B + T::TNC - 1) / T::TNC);
     g.nblocks = (uint32_t)(L.A * g.bt * g.ntm);
   }
-  g.vec_ok = (L.n % vec_units == 0) ? 1 : 0;
   return g;
 }
 

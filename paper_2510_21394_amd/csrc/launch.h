@@ -61,6 +61,8 @@ struct EpiParams {
 struct MPLaunch {
   int prec = P_F64;
   int cfg = 0;  // tile configuration index
+  int split = 0;       // 0 dense, 1 even/odd forward (Q^T), 2 even/odd backward (Q); see kernels.hpp
+  int me = 0, mo = 0;  // split: even and odd block sizes (me + mo = n)
   int64_t A = 1;
   int n = 1;
   int npad = 1;
@@ -73,9 +75,11 @@ struct MPLaunch {
   EpiParams ep;
 };
 
-constexpr int kNumCfg = 3;  // per precision: 0 = 256-row tiles, 1 = 128, 2 = 64
-int cfg_rows(int prec, int cfg);
-int cfg_cols(int prec, int cfg);  // complex columns per tile
+constexpr int kNumCfg = 3;  // tile configurations per precision and structure
+int cfg_rows(int prec, int cfg, int split = 0);
+int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
+// True when the even/odd split kernels exist for the precision.
+bool split_supported(int prec);
 
 // True when the fused kernel exists for this (loader, prologue, epilogue) combination.
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek);

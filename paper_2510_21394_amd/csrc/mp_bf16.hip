@@ -6,7 +6,7 @@ namespace fcgle {
 template <int NP>
 struct BFK {
   using R = float;
-  template <class T, bool TL, class Pro, class Epi>
+  template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {
     const Geo g = make_geo<T>(L, TL, 4);
     hipLaunchKernelGGL((mp_bf16_kernel<T, NP, TL, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,

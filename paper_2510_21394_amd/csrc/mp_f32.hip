@@ -5,16 +5,24 @@ namespace fcgle {
 
 struct F32K {
   using R = float;
-  template <class T, bool TL, class Pro, class Epi>
+  template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {
     const Geo g = make_geo<T>(L, TL, MfmaT<float>::G);
-    hipLaunchKernelGGL((mp_mfma_kernel<float, T, TL, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
+    hipLaunchKernelGGL((mp_mfma_kernel<float, T, TL, SP, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
                        (const float*)L.M, (const float2*)L.in, Pro(L.pp), Epi(L.ep));
     return hipGetLastError();
   }
 };
 
 hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {
+  if (L.split) {
+    switch (L.cfg) {
+      case 0: return dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);
+      case 1: return dispatch_split<F32K, TileCfg<64, 64, 16, 1, 2>>(L, s);
+      case 2: return dispatch_split<F32K, TileCfg<128, 32, 16, 2, 2>>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (L.cfg) {
     case 0: return dispatch_cfg<F32K, TileCfg<256, 64, 16, 2, 2>>(L, s);
     case 1: return dispatch_cfg<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);

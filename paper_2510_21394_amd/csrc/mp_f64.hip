@@ -5,16 +5,24 @@ namespace fcgle {
 
 struct F64K {
   using R = double;
-  template <class T, bool TL, class Pro, class Epi>
+  template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {
     const Geo g = make_geo<T>(L, TL, MfmaT<double>::G);
-    hipLaunchKernelGGL((mp_mfma_kernel<double, T, TL, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
+    hipLaunchKernelGGL((mp_mfma_kernel<double, T, TL, SP, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
                        (const double*)L.M, (const double2*)L.in, Pro(L.pp), Epi(L.ep));
     return hipGetLastError();
   }
 };
 
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s) {
+  if (L.split) {
+    switch (L.cfg) {
+      case 0: return dispatch_split<F64K, TileCfg<128, 32, 8, 2, 2>>(L, s);
+      case 1: return dispatch_split<F64K, TileCfg<64, 32, 8, 1, 2>>(L, s);
+      case 2: return dispatch_split<F64K, TileCfg<64, 16, 8, 1, 1>>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   switch (L.cfg) {
     case 0: return dispatch_cfg<F64K, TileCfg<256, 32, 8, 2, 2>>(L, s);
     case 1: return dispatch_cfg<F64K, TileCfg<128, 32, 8, 2, 2>>(L, s);

@@ -102,7 +102,13 @@ struct fcgle_plan {
   int ns = 0;
   double rate[4] = {0, 0, 0, 0};
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
-  int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd]
+  int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd], for the active structure
+  // even/odd split of the mode products (persymmetric D): block sizes, leading dimension and
+  // the stacked block matrices [Fe; Fo] (forward) and [Be; Bo] (backward)
+  bool split = false;
+  int me[4] = {0, 0, 0, 0}, mo[4] = {0, 0, 0, 0}, ldsp[4] = {0, 0, 0, 0};
+  void* Mfs[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* Mbs[4] = {nullptr, nullptr, nullptr, nullptr};
   bool tuned = false;
   int fusion = 3;  // bit 0: prologue, bit 1: epilogue
   int* dflag = nullptr;

@@ -162,7 +162,8 @@ hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, co
   return hipGetLastError();
 }
 
-int cfg_rows(int prec, int cfg) { return kCfgRows[prec][cfg]; }
-int cfg_cols(int prec, int cfg) { return kCfgCols[prec][cfg]; }
+int cfg_rows(int prec, int cfg, int split) { return kCfgRows[split ? 1 : 0][prec][cfg]; }
+int cfg_cols(int prec, int cfg, int split) { return kCfgCols[split ? 1 : 0][prec][cfg]; }
+bool split_supported(int prec) { return prec == P_F64 || prec == P_F32; }
 
 }  // namespace fcgle

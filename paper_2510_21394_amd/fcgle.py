@@ -180,6 +180,10 @@ class Plan:
     def set_fusion(self, prologue: bool = True, epilogue: bool = True):
         L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)))
 
+    def set_structure(self, split: bool):
+        """True: even/odd half-size mode products (default for fp64/fp32); False: dense."""
+        L.check(self.lib.fcgle_set_structure(self.handle, int(bool(split))))
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)
         L.check(self.lib.fcgle_describe(self.handle, buf, 1024))
@@ -261,6 +265,8 @@ class BatchPlan:
 
 def decode_signature(sig: int) -> dict:
     """Inverse of the kernel signature of fcgle_timing_read."""
+    structure = sig // 512
+    sig %= 512
     ek = sig % 8
     sig //= 8
     pk = sig % 2
@@ -270,6 +276,7 @@ def decode_signature(sig: int) -> dict:
     cfg = sig % 4
     prec = sig // 4
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
+            "structure": ["dense", "even_odd_fwd", "even_odd_bwd"][structure],
             "prologue": ["none", "nonlinearity"][pk],
             "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "?", "?"][ek]}
 

@@ -256,19 +256,57 @@ def test_unfused_paths_match_oracle(F, fusion, scheme):
     assert O.rel_l2(_host(u), ref) <= 1e-12
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec,split", [("fp64", True), ("fp64", False), ("fp32", True), ("fp32", False),
+                                        ("bf16x3", False), ("bf16x6", False)])
 @pytest.mark.parametrize("cfg", [0, 1, 2])
-def test_every_tile_configuration(F, prec, cfg):
+def test_every_tile_configuration(F, prec, split, cfg):
     n = (300, 70, 129)
     alpha, h = _setup(n, 21)
     V = random_complex(n, 22)
     plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
+    plan.set_structure(split)
     for ax in range(3):
         for fwd in (0, 1):
             plan.set_tiles(ax, fwd, cfg)
     out = plan.apply_f("phi1", 1e-2, _dev(V, prec))
     ref = O.Problem(n, alpha, h, BASE_PARAMS).f("phi1", 1e-2, V)
-    assert O.rel_l2(_host(out), ref) <= TOL_OP[prec]
+    err = O.rel_l2(_host(out), ref)
+    print(f"[tiles {prec} split={split} cfg={cfg}] rel_l2 = {err:.3e}")
+    assert err <= TOL_OP[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", [(2, 3), (3, 2, 5), (7,), (33, 64), (17, 40, 31), (129, 18, 16)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_dense_and_even_odd_structures_agree_with_oracle(F, prec, n):
+    """Every kind through both mode-product structures, on odd and even axis lengths
+    (the odd-length middle point, length-2/3 axes, several row tiles)."""
+    alpha, h = _setup(n, 31)
+    params = (0.7, 0.9, 1.0, 1.0, 0.5)
+    V = random_complex(n, 32)
+    P = O.Problem(n, alpha, h, params)
+    plan = F.Plan(n, alpha, h, params, tau=1e-3, precision=prec)
+    for kind in ("inv", "exp", "phi1", "phi2"):
+        ref = P.f(kind, 2e-2, V)
+        for split in (True, False):
+            plan.set_structure(split)
+            out = plan.apply_f(kind, 2e-2, _dev(V, prec))
+            err = O.rel_l2(_host(out), ref)
+            assert err <= TOL_OP[prec], (kind, split, err)
+    plan.close()
+
+
+def test_get_eig_matches_oracle_reconstruction(F):
+    n = (37, 24)
+    alpha, h = _setup(n, 41)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3)
+    for mu in range(2):
+        Q, lam = plan.eig(mu)
+        D = O.diff_matrix(alpha[mu], n[mu], h[mu])
+        assert np.all(np.diff(lam) >= 0)
+        assert np.linalg.norm(Q @ np.diag(lam) @ Q.T - D) <= 1e-13 * np.linalg.norm(D)
+        assert np.linalg.norm(Q.T @ Q - np.eye(n[mu])) <= 1e-13
+    plan.close()
 
 
 def test_autotuned_exp_euler_matches_oracle(F):
