@@ -211,18 +211,20 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
 /* Structure of the mode products.  Every D_mu is symmetric Toeplitz, hence persymmetric
  * (J D J = D with J the exchange matrix), so Q_mu = Z diag(Ve, Vo) with Z built from
  * (e_k +- e_{n-1-k})/sqrt(2) and Ve, Vo the eigenvectors of two half-size blocks (the
- * set-up always diagonalises D_mu this way).  split = 1 (the default where available,
- * FCGLE_FP64 and FCGLE_FP32): each mode product contracts the half-length sums and
- * differences of mirrored fibre entries with the half-size blocks -- half the multiply-adds
- * of the dense product for the same bytes moved; split = 0: dense Q_mu^T / Q_mu products.
- * Results agree to rounding.  Resets the tile choice to its default (autotune again after).
- * Errors: ERR_ARG, ERR_UNSUPPORTED (split = 1 for the split-BF16 precisions). */
+ * set-up always diagonalises D_mu this way).  split = 1 (the default, every precision):
+ * each mode product contracts the half-length sums and differences of mirrored fibre
+ * entries with the half-size blocks -- half the multiply-adds of the dense product for the
+ * same bytes moved; split = 0: dense Q_mu^T / Q_mu products.  Results agree to rounding.
+ * Resets the tile choice to its default (autotune again after).  Errors: ERR_ARG. */
 int fcgle_set_structure(fcgle_plan* plan, int split);
 
 /* Fusion switches: bit 0 fuses the pointwise prologue (nonlinearity) into the first
  * mode product of a Tucker operator, bit 1 fuses the pointwise epilogue (f-scale,
  * exponential-Euler update, LBDF2 history) into the last one; a cleared bit runs that
- * map as a separate streaming kernel.  Default 3.  Errors: ERR_ARG. */
+ * map as a separate streaming kernel.  Bit 2 runs the mode products of forward (Q^T)
+ * operators from the last axis to the first (the products commute), so the epilogue lands
+ * on a product along a slow axis.  Default 3; fcgle_autotune picks all three by timing
+ * whole forward operators.  Errors: ERR_ARG. */
 int fcgle_set_fusion(fcgle_plan* plan, int flags);
 
 /* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */

@@ -108,14 +108,31 @@ int upload_split(fcgle_plan* P, int mu) {
       B[ld * ld + i * ld + k] = Q[i * n + me + k];
     }
   const int pr = precision_of(P);
+  // FP64 / FP32 as is; split-BF16 as NP pieces per block, block-major ([h][piece][ld x ld]),
+  // each entry split in FP64: q0 = bf16(q), q1 = bf16(q - q0), ...
   auto up = [&](const std::vector<double>& M, void** dst) -> int {
     if (pr == P_F64) {
       FC_TRY(plan_alloc(dst, M.size() * sizeof(double)));
       HIP_TRY(hipMemcpy(*dst, M.data(), M.size() * sizeof(double), hipMemcpyHostToDevice));
-    } else {
+    } else if (pr == P_F32) {
       std::vector<float> f(M.begin(), M.end());
       FC_TRY(plan_alloc(dst, f.size() * sizeof(float)));
       HIP_TRY(hipMemcpy(*dst, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice));
+    } else {
+      const int np = (pr == P_BF16X3) ? 2 : 3;
+      const int64_t blk = ld * ld;
+      std::vector<uint16_t> b(2 * np * blk, 0);
+      for (int h = 0; h < 2; ++h)
+        for (int64_t e = 0; e < blk; ++e) {
+          double r = M[h * blk + e];
+          for (int q = 0; q < np; ++q) {
+            const uint16_t bits = bf16_round(r);
+            b[(h * np + q) * blk + e] = bits;
+            r -= bf16_value(bits);
+          }
+        }
+      FC_TRY(plan_alloc(dst, b.size() * sizeof(uint16_t)));
+      HIP_TRY(hipMemcpy(*dst, b.data(), b.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
     }
     return FCGLE_OK;
   };
@@ -233,8 +250,12 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
     return t;
   };
   const void* cur = in;
-  for (int mu = 0; mu < P->d; ++mu) {
-    const bool first = (mu == 0), last = (mu == P->d - 1);
+  // Forward operators may run their mode products from the fastest axis to the slowest, so
+  // the epilogue (f-scale, update) lands on an N-loader product (the products commute).
+  const bool rev = fwd && P->fwd_rev;
+  for (int step = 0; step < P->d; ++step) {
+    const int mu = rev ? P->d - 1 - step : step;
+    const bool first = (step == 0), last = (step == P->d - 1);
     MPLaunch L = base_launch(P, mu, fwd);
     const bool tl = (L.B == 1);
     L.in = cur;
@@ -260,7 +281,9 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
         L.ep = EpiParams();
         L.ep.out = t;
         FC_TRY(launch_timed(P, L, mu, st));
-        HIP_TRY(launch_pointwise_epi(pr, P->N, (int)P->n[mu], t, ek, ep, st));
+        // the streaming pass views the tensor as (rows, n_d) whatever the last product was
+        ep.sep.mu = P->d - 1;
+        HIP_TRY(launch_pointwise_epi(pr, P->N, (int)P->n[P->d - 1], t, ek, ep, st));
       }
     } else {
       void* t = pick(L.in);
@@ -820,67 +843,38 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
       }
       plan->cfg[mu][dir] = best_c;
     }
-  // 2. fused or separate exponential-Euler update after the last forward mode product
-  const int last = plan->d - 1;
+  // 2. order of the forward products and fusion of the nonlinearity prologue and the
+  //    exponential-Euler epilogue: time the whole forward operator of a step for each choice
+  FC_TRY(ensure_state_buffers(plan));
+  HIP_TRY(hipMemsetAsync(plan->uprev, 0, bytes, st));
   EpiParams ep;
   ep.out = plan->s[2];
   ep.tau = plan->tau;
   FC_TRY(get_grid(plan, FCGLE_PHI1, plan->tau, st, &ep.F));
   FC_TRY(get_sep(plan, plan->tau, &ep.sep));
-  ep.sep.mu = last;
-  float unfused;
-  {
-    MPLaunch L = base_launch(plan, last, true);
-    L.in = plan->s[0];
-    L.ep.out = plan->s[1];
-    FC_TRY(time_ms(st, e0, e1, reps, [&] {
-      hipError_t e = launch_mode_product(L, st);
-      if (e != hipSuccess) return e;
-      return launch_pointwise_epi(pr, plan->N, (int)plan->n[last], plan->s[1], EpiKind::ExpEuler, ep, st);
-    }, &unfused));
-  }
-  float fused = 1e30f;
-  int fused_c = plan->cfg[last][1];
-  for (int c = 0; c < kNumCfg; ++c) {
-    MPLaunch L = base_launch(plan, last, true);
-    L.cfg = c;
-    L.in = plan->s[0];
-    L.ek = EpiKind::ExpEuler;
-    L.ep = ep;
-    float ms;
-    FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(L, st); }, &ms));
-    if (ms < fused) {
-      fused = ms;
-      fused_c = c;
+  const ProParams pp = nonlin_params(plan, 0.0);
+  float best = 1e30f;
+  int best_fusion = 3;
+  bool best_rev = false;
+  for (int rev = 0; rev < (plan->d > 1 ? 2 : 1); ++rev)
+    for (int fusion = 0; fusion < 4; ++fusion) {
+      plan->fwd_rev = (rev != 0);
+      plan->fusion = fusion;
+      float ms;
+      FC_TRY(time_ms(st, e0, e1, reps, [&] {
+        const int rc = tucker(plan, true, plan->uprev, ProKind::Nonlin, pp, EpiKind::ExpEuler, ep, plan->s[0],
+                              plan->s[1], st);
+        return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
+      }, &ms));
+      if (ms < best) {
+        best = ms;
+        best_fusion = fusion;
+        best_rev = (rev != 0);
+      }
     }
-  }
-  int fusion = 0;
-  if (fused < unfused) {
-    fusion |= 2;
-    plan->cfg[last][1] = fused_c;
-  }
-  // 3. fused or separate nonlinearity before the first forward mode product
-  if (plan->d > 1) {
-    ProParams pp = nonlin_params(plan, 0.0);
-    MPLaunch L = base_launch(plan, 0, true);
-    L.in = plan->s[0];
-    L.ep.out = plan->s[1];
-    float sep_ms, fus_ms;
-    FC_TRY(time_ms(st, e0, e1, reps, [&] {
-      hipError_t e = launch_pointwise_pro(pr, plan->N, plan->s[0], plan->s[2], pp, st);
-      if (e != hipSuccess) return e;
-      MPLaunch L2 = L;
-      L2.in = plan->s[2];
-      return launch_mode_product(L2, st);
-    }, &sep_ms));
-    MPLaunch Lf = L;
-    Lf.pk = ProKind::Nonlin;
-    Lf.pp = pp;
-    FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(Lf, st); }, &fus_ms));
-    if (fus_ms <= sep_ms) fusion |= 1;
-  } else {
-    fusion |= 1;
-  }
+  (void)pr;
+  plan->fwd_rev = best_rev;
+  const int fusion = best_fusion;
   plan->fusion = fusion;
   return FCGLE_OK;
 }
@@ -933,8 +927,9 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
 
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
-  if (flags < 0 || flags > 3) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..3");
-  plan->fusion = flags;
+  if (flags < 0 || flags > 7) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..7");
+  plan->fusion = flags & 3;
+  plan->fwd_rev = (flags & 4) != 0;
   return FCGLE_OK;
 }
 
@@ -954,6 +949,7 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   }
   s += plan->split ? " structure=even-odd" : " structure=dense";
   s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");
+  s += plan->fwd_rev ? " forward-order=reversed" : " forward-order=natural";
   s += plan->tuned ? " tuned" : " default";
   std::snprintf(buf, len, "%s", s.c_str());
   return FCGLE_OK;

@@ -10,9 +10,9 @@ namespace fcgle {
 // blocks (at most n/2 + 1 rows each) and the backward form carries two accumulator sets, so
 // their tiles are smaller.
 constexpr int kCfgRows[2][4][kNumCfg] = {{{256, 128, 64}, {256, 128, 64}, {256, 128, 64}, {128, 64, 64}},
-                                         {{128, 64, 64}, {128, 64, 128}, {128, 64, 64}, {64, 64, 64}}};
+                                         {{128, 64, 64}, {128, 64, 128}, {64, 128, 64}, {64, 64, 128}}};
 constexpr int kCfgCols[2][4][kNumCfg] = {{{32, 32, 32}, {64, 64, 64}, {64, 64, 64}, {64, 64, 32}},
-                                         {{32, 32, 16}, {64, 64, 32}, {64, 64, 32}, {64, 32, 32}}};
+                                         {{32, 32, 16}, {64, 64, 32}, {64, 32, 32}, {32, 16, 16}}};
 
 // Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
 // combinations a structure never needs are not instantiated.
@@ -21,12 +21,32 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   using R = typename K::R;
   const bool tl = (L.B == 1);
   if (!tl) {
-    if (L.ek != EpiKind::Store) return hipErrorInvalidValue;
-    if (L.pk == ProKind::Id) return K::template go<T, false, SP, ProIdF, EpiStoreF<R>>(L, s);
-    if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+    if (L.pk != ProKind::Id) {
+      if constexpr (SP != kSplitBwd)
+        if (L.ek == EpiKind::Store) return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+      return hipErrorInvalidValue;
+    }
+    switch (L.ek) {
+      case EpiKind::Store:
+        return K::template go<T, false, SP, ProIdF, EpiStoreF<R>>(L, s);
+      case EpiKind::Grid:
+        if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProIdF, EpiGridF<R>>(L, s);
+        return hipErrorInvalidValue;
+      case EpiKind::Sep:
+        if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProIdF, EpiSepF<R>>(L, s);
+        return hipErrorInvalidValue;
+      case EpiKind::ExpEuler:
+        if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProIdF, EpiExpEulerF<R>>(L, s);
+        return hipErrorInvalidValue;
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  if (L.pk != ProKind::Id) {
+    if constexpr (SP != kSplitBwd)
+      if (L.ek == EpiKind::Store) return K::template go<T, true, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
     return hipErrorInvalidValue;
   }
-  if (L.pk != ProKind::Id) return hipErrorInvalidValue;
   switch (L.ek) {
     case EpiKind::Store:
       return K::template go<T, true, SP, ProIdF, EpiStoreF<R>>(L, s);

@@ -25,6 +25,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "fz.hpp"
 #include "launch.h"
@@ -133,13 +134,17 @@ struct ProNonlinF {
 
 // ---------------------------------------------------------------------------------------
 // Epilogue functors.  col(a, b) is evaluated once per output column (a: flat index over the
-// axes slower than mu, b: over the faster ones).  apply<V>(ctx, i, j, ok, re, im) handles V
-// output elements of that column (i: mode-mu index, j: flat index, ok: inside the tensor):
-// every functor issues all of its global loads for the V elements before its first store,
-// so the loads are not serialised behind stores the compiler cannot prove independent.
+// axes slower than mu, b: over the faster ones).  Each functor works in two phases over V
+// output elements (i: mode-mu index, j: flat index, ok: inside the tensor):
+//   load<V>(i, j, ok, pre)                     issues every global load it needs,
+//   store<V>(ctx, i, j, ok, re, im, pre)       computes and stores.
+// Callers run the loads of several columns before their stores, so loads are not
+// serialised behind stores the compiler cannot prove independent (the exponential-Euler
+// update reads and writes the same array).  apply<V> is load followed by store.
 // ---------------------------------------------------------------------------------------
 
 struct NoCtx {};
+struct NoPre {};
 
 // Product over the axes other than mu of the separable per-axis factors.
 __device__ __forceinline__ zc sep_other(const SepParams& s, uint32_t a, uint32_t b) {
@@ -165,44 +170,6 @@ __device__ __forceinline__ C mkc(R re, R im) {
   return v;
 }
 
-template <class R>
-struct EpiStoreF {
-  using C = typename Cx<R>::T;
-  using Ctx = NoCtx;
-  C* out;
-  EpiStoreF() = default;
-  explicit EpiStoreF(const EpiParams& p) : out((C*)p.out) {}
-  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
-  template <int V>
-  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
-                                        const R* im) const {
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-      if (ok[v]) out[j[v]] = mkc<C>(re[v], im[v]);
-  }
-};
-
-template <class R>
-struct EpiGridF {
-  using C = typename Cx<R>::T;
-  using Ctx = NoCtx;
-  C* out;
-  const C* F;
-  EpiGridF() = default;
-  explicit EpiGridF(const EpiParams& p) : out((C*)p.out), F((const C*)p.F) {}
-  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
-  template <int V>
-  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
-                                        const R* im) const {
-    C f[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) f[v] = ok[v] ? F[j[v]] : C{0, 0};
-#pragma unroll
-    for (int v = 0; v < V; ++v)
-      if (ok[v]) out[j[v]] = mkc<C>(f[v].x * re[v] - f[v].y * im[v], f[v].x * im[v] + f[v].y * re[v]);
-  }
-};
-
 // Complex arithmetic in the state precision (float2 / double2).
 template <class C>
 __device__ __forceinline__ C cmul(C a, C b) {
@@ -212,6 +179,61 @@ __device__ __forceinline__ C cmul(C a, C b) {
   return o;
 }
 
+#define FCGLE_EPI_APPLY                                                                              \
+  template <int V>                                                                                   \
+  __device__ __forceinline__ void apply(const Ctx& ctx, const int* i, const int64_t* j, const bool* ok, \
+                                        const R* re, const R* im) const {                           \
+    Pre pre[V];                                                                                      \
+    this->template load<V>(i, j, ok, pre);                                                           \
+    this->template store<V>(ctx, i, j, ok, re, im, pre);                                             \
+  }
+
+template <class R>
+struct EpiStoreF {
+  using C = typename Cx<R>::T;
+  using Ctx = NoCtx;
+  using Pre = NoPre;
+  C* out;
+  EpiStoreF() = default;
+  explicit EpiStoreF(const EpiParams& p) : out((C*)p.out) {}
+  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
+  template <int V>
+  __device__ __forceinline__ void load(const int*, const int64_t*, const bool*, Pre*) const {}
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im, const Pre*) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = mkc<C>(re[v], im[v]);
+  }
+  FCGLE_EPI_APPLY
+};
+
+template <class R>
+struct EpiGridF {
+  using C = typename Cx<R>::T;
+  using Ctx = NoCtx;
+  using Pre = C;
+  C* out;
+  const C* F;
+  EpiGridF() = default;
+  explicit EpiGridF(const EpiParams& p) : out((C*)p.out), F((const C*)p.F) {}
+  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
+  template <int V>
+  __device__ __forceinline__ void load(const int*, const int64_t* j, const bool* ok, Pre* f) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v) f[v] = ok[v] ? F[j[v]] : C{0, 0};
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im, const Pre* f) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = mkc<C>(f[v].x * re[v] - f[v].y * im[v], f[v].x * im[v] + f[v].y * re[v]);
+  }
+  FCGLE_EPI_APPLY
+};
+
 // out[j] = E_j v with E the separable exponential (product of the per-axis FP64 factors),
 // formed and applied in FP64: E is the same every step, so a rounding of E in the state
 // precision would act as a fixed per-element bias that grows linearly over a trajectory.
@@ -219,21 +241,25 @@ template <class R>
 struct EpiSepF {
   using C = typename Cx<R>::T;
   using Ctx = zc;
+  using Pre = zc;
   C* out;
   SepParams s;
   EpiSepF() = default;
   explicit EpiSepF(const EpiParams& p) : out((C*)p.out), s(p.sep) {}
   __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
   template <int V>
-  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
-                                        const R* re, const R* im) const {
-    zc f[V];
+  __device__ __forceinline__ void load(const int* i, const int64_t*, const bool* ok, Pre* f) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx& Eo, const int*, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im, const Pre* f) const {
 #pragma unroll
     for (int v = 0; v < V; ++v)
       if (ok[v]) out[j[v]] = from_zc<C>(zmul(zmul(Eo, f[v]), zc{(double)re[v], (double)im[v]}));
   }
+  FCGLE_EPI_APPLY
 };
 
 // uhat[j] <- E_j uhat[j] + tau P1[j] v   (v = transformed nonlinearity).  E uhat is formed in
@@ -242,6 +268,10 @@ template <class R>
 struct EpiExpEulerF {
   using C = typename Cx<R>::T;
   using Ctx = zc;
+  struct Pre {
+    C u, P;
+    zc f;
+  };
   C* uhat;
   const C* P1;
   C* ghat_out;
@@ -252,25 +282,27 @@ struct EpiExpEulerF {
       : uhat((C*)p.out), P1((const C*)p.F), ghat_out((C*)p.ghat_out), s(p.sep), tau(p.tau) {}
   __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
   template <int V>
-  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
-                                        const R* re, const R* im) const {
-    C u[V], P[V];
-    zc f[V];
+  __device__ __forceinline__ void load(const int* i, const int64_t* j, const bool* ok, Pre* pre) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      u[v] = ok[v] ? uhat[j[v]] : C{0, 0};
-      P[v] = ok[v] ? P1[j[v]] : C{0, 0};
-      f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+      pre[v].u = ok[v] ? uhat[j[v]] : C{0, 0};
+      pre[v].P = ok[v] ? P1[j[v]] : C{0, 0};
+      pre[v].f = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
     }
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx& Eo, const int*, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im, const Pre* pre) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       if (!ok[v]) continue;
-      const zc eu = zmul(zmul(Eo, f[v]), to_zc(u[v]));
-      const C pg = cmul(P[v], mkc<C>(re[v], im[v]));
+      const zc eu = zmul(zmul(Eo, pre[v].f), to_zc(pre[v].u));
+      const C pg = cmul(pre[v].P, mkc<C>(re[v], im[v]));
       uhat[j[v]] = from_zc<C>(zc{eu.re + tau * (double)pg.x, eu.im + tau * (double)pg.y});
       if (ghat_out) ghat_out[j[v]] = mkc<C>(re[v], im[v]);
     }
   }
+  FCGLE_EPI_APPLY
 };
 
 // Exponential-Euler update that also records what the adjoint needs for the derivatives
@@ -281,6 +313,10 @@ template <class R>
 struct EpiExpEulerRecF {
   using C = typename Cx<R>::T;
   using Ctx = zc;
+  struct Pre {
+    C u, p1, p2;
+    zc f;
+  };
   C* uhat;
   const C* P1;
   const C* P2;
@@ -292,44 +328,49 @@ struct EpiExpEulerRecF {
       : uhat((C*)p.out), P1((const C*)p.F), P2((const C*)p.F2), X((C*)p.out2), s(p.sep), tau(p.tau) {}
   __device__ __forceinline__ Ctx col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
   template <int V>
-  __device__ __forceinline__ void apply(const Ctx& Eo, const int* i, const int64_t* j, const bool* ok,
-                                        const R* re, const R* im) const {
-    C u[V], p1[V], p2[V];
-    zc f[V];
+  __device__ __forceinline__ void load(const int* i, const int64_t* j, const bool* ok, Pre* pre) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      u[v] = ok[v] ? uhat[j[v]] : C{0, 0};
-      p1[v] = ok[v] ? P1[j[v]] : C{0, 0};
-      p2[v] = ok[v] ? P2[j[v]] : C{0, 0};
-      f[v] = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
+      pre[v].u = ok[v] ? uhat[j[v]] : C{0, 0};
+      pre[v].p1 = ok[v] ? P1[j[v]] : C{0, 0};
+      pre[v].p2 = ok[v] ? P2[j[v]] : C{0, 0};
+      pre[v].f = ok[v] ? ((const zc*)s.fac[s.mu])[i[v]] : zc{0, 0};
     }
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx& Eo, const int*, const int64_t* j, const bool* ok,
+                                        const R* re, const R* im, const Pre* pre) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       if (!ok[v]) continue;
-      const zc E = zmul(Eo, f[v]);
+      const zc E = zmul(Eo, pre[v].f);
       const zc g{(double)re[v], (double)im[v]};
-      const zc r = zadd(zmul(E, to_zc(u[v])), zscale(zmul(to_zc(p1[v]), g), tau));
+      const zc r = zadd(zmul(E, to_zc(pre[v].u)), zscale(zmul(to_zc(pre[v].p1), g), tau));
       uhat[j[v]] = from_zc<C>(r);
-      X[j[v]] = from_zc<C>(zsub(r, zscale(zmul(to_zc(p2[v]), g), tau)));
+      X[j[v]] = from_zc<C>(zsub(r, zscale(zmul(to_zc(pre[v].p2), g), tau)));
     }
   }
+  FCGLE_EPI_APPLY
 };
 
 template <class R>
 struct EpiKeepOldF {
   using C = typename Cx<R>::T;
   using Ctx = NoCtx;
+  using Pre = C;
   C* out;
   C* save;
   EpiKeepOldF() = default;
   explicit EpiKeepOldF(const EpiParams& p) : out((C*)p.out), save((C*)p.save) {}
   __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
   template <int V>
-  __device__ __forceinline__ void apply(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
-                                        const R* im) const {
-    C old[V];
+  __device__ __forceinline__ void load(const int*, const int64_t* j, const bool* ok, Pre* old) const {
 #pragma unroll
     for (int v = 0; v < V; ++v) old[v] = ok[v] ? out[j[v]] : C{0, 0};
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im, const Pre* old) const {
 #pragma unroll
     for (int v = 0; v < V; ++v)
       if (ok[v]) {
@@ -337,7 +378,10 @@ struct EpiKeepOldF {
         out[j[v]] = mkc<C>(re[v], im[v]);
       }
   }
+  FCGLE_EPI_APPLY
 };
+
+#undef FCGLE_EPI_APPLY
 
 // ---------------------------------------------------------------------------------------
 // Tile configurations and geometry
@@ -455,6 +499,22 @@ constexpr bool kTlDirectEpilogue = true;
 constexpr bool kTlDirectEpilogue = false;
 #endif
 
+// Columns whose epilogue loads are issued together in the T-loader epilogue: at most
+// kEpiGroupBytes of loaded operands per lane, and none for functors without loads (their
+// stores need no grouping and the extra live values would cost occupancy).  Measured on the
+// 256^3 workload, grouping did not speed up the exponential-Euler epilogue, so the budget
+// keeps one column at a time for it.
+constexpr size_t kEpiGroupBytes = 64;
+template <class Pre>
+constexpr int epi_column_group(int V, int cpw) {
+  if (std::is_same<Pre, NoPre>::value) return 1;
+  int cg = (int)(kEpiGroupBytes / (sizeof(Pre) * (size_t)V));
+  if (cg < 1) cg = 1;
+  if (cg > cpw) cg = cpw;
+  while (cpw % cg) --cg;
+  return cg;
+}
+
 // Rows m0 + r of the tile (r < TM) are valid below row_end; phys(i) maps a valid row to the
 // index along the mode axis that the output element has (identity except for the mirrored
 // half of kSplitBwd).
@@ -536,25 +596,42 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
           }
       }
       __syncthreads();
-      for (int cc = wave; cc < CW; cc += T::NW) {
-        const uint32_t col = c0 + q * CW + cc;
-        if (col >= g.A) continue;
-        const auto ctx = epi.col(col, 0);
-        int i[V];
-        int64_t j[V];
-        bool ok[V];
-        R re[V], im[V];
+      // each wave owns columns wave, wave + NW, ...; the loads of CG columns are issued
+      // together before their stores
+      constexpr int CPW = CW / T::NW;
+      constexpr int CG = epi_column_group<typename Epi::Pre>(V, CPW);
 #pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const int row = lane + 64 * v;
-          ok[v] = m0 + row < row_end;
-          i[v] = phys(m0 + row);
-          j[v] = (int64_t)col * g.n + i[v];
-          const C x = Cs[cc * LDC + row];
-          re[v] = x.x;
-          im[v] = x.y;
+      for (int c1 = 0; c1 < CPW; c1 += CG) {
+        int i[CG * V];
+        int64_t j[CG * V];
+        bool ok[CG * V];
+        R re[CG * V], im[CG * V];
+        typename Epi::Pre pre[CG * V];
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          const int cc = wave + (c1 + cg) * T::NW;
+          const uint32_t col = c0 + q * CW + cc;
+          const bool colok = (c1 + cg < CPW) && col < g.A;
+#pragma unroll
+          for (int v = 0; v < V; ++v) {
+            const int row = lane + 64 * v, e = cg * V + v;
+            ok[e] = colok && m0 + row < row_end;
+            i[e] = phys(m0 + row);
+            j[e] = (int64_t)col * g.n + i[e];
+            const C x = colok ? Cs[cc * LDC + row] : C{0, 0};
+            re[e] = x.x;
+            im[e] = x.y;
+          }
         }
-        epi.template apply<V>(ctx, i, j, ok, re, im);
+        epi.template load<CG * V>(i, j, ok, pre);
+#pragma unroll
+        for (int cg = 0; cg < CG; ++cg) {
+          const int cc = wave + (c1 + cg) * T::NW;
+          const uint32_t col = c0 + q * CW + cc;
+          if (!((c1 + cg < CPW) && col < g.A)) continue;
+          const auto ctx = epi.col(col, 0);
+          epi.template store<V>(ctx, i + cg * V, j + cg * V, ok + cg * V, re + cg * V, im + cg * V, pre + cg * V);
+        }
       }
       __syncthreads();
     }
@@ -867,27 +944,51 @@ __device__ __forceinline__ void split_bf16(float x, __bf16 (&p)[NP]) {
   }
 }
 
-template <class T, int NP, bool TL, class Pro, class Epi>
+// Structure SP as for the FP32/FP64 kernels (see Geo).  Block matrices of the split forms
+// are stored block-major: block h, piece q at Mp + (h * NP + q) * npad^2.
+template <class T, int NP, bool TL, int SP, class Pro, class Epi>
 __global__ void __launch_bounds__(T::THREADS)
     mp_bf16_kernel(Geo g, const __bf16* __restrict__ Mp, const float2* __restrict__ U, Pro pro, Epi epi) {
   using C = float2;
   constexpr int TM = T::TM, TNC = T::TNC, TK = T::TK;
   static_assert(TK % 32 == 0, "k tile");
+  constexpr int NB = (SP == kSplitBwd) ? 2 : 1;
+  constexpr int NR = (SP == kDense) ? 1 : 2;
   constexpr int LDK = TK + 8;  // 16-byte pad
   constexpr int LG = 4;        // B loader unit: 4 consecutive k of one column
-  constexpr size_t kAsBytes = (size_t)2 * NP * TM * LDK * sizeof(__bf16);
-  constexpr size_t kBsBytes = (size_t)2 * NP * 2 * TNC * LDK * sizeof(__bf16);
+  constexpr size_t kAsBytes = (size_t)2 * NB * NP * TM * LDK * sizeof(__bf16);
+  constexpr size_t kBsBytes = (size_t)2 * NB * NP * 2 * TNC * LDK * sizeof(__bf16);
   constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? epi_lds_bytes<C, T>() : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
-  __bf16 (*As)[NP][TM * LDK] = reinterpret_cast<__bf16 (*)[NP][TM * LDK]>(smem);
-  __bf16 (*Bs)[NP][2 * TNC * LDK] = reinterpret_cast<__bf16 (*)[NP][2 * TNC * LDK]>(smem + kAsBytes);
+  // [buffer][block][piece][...]
+  __bf16 (*As)[NB][NP][TM * LDK] = reinterpret_cast<__bf16 (*)[NB][NP][TM * LDK]>(smem);
+  __bf16 (*Bs)[NB][NP][2 * TNC * LDK] = reinterpret_cast<__bf16 (*)[NB][NP][2 * TNC * LDK]>(smem + kAsBytes);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave / T::WN, wn = wave % T::WN;
   const uint32_t bid = xcd_remap(blockIdx.x, g.nblocks);
   const int mt = (int)(bid % (uint32_t)g.ntm);
   const uint32_t ct = bid / (uint32_t)g.ntm;
-  const int m0 = mt * TM;
+  const int64_t piece = (int64_t)g.npad * g.npad;
+  int m0, K, row_end, base = 0;
+  bool odd = false;
+  const __bf16* Ma = Mp;
+  if (SP == kDense) {
+    m0 = mt * TM;
+    K = g.n;
+    row_end = g.n;
+  } else if (SP == kSplitFwd) {
+    odd = mt >= g.te;
+    m0 = (odd ? mt - g.te : mt) * TM;
+    K = odd ? g.mo : g.me;
+    row_end = K;
+    base = odd ? g.me : 0;
+    Ma = Mp + (odd ? NP * piece : 0);
+  } else {
+    m0 = mt * TM;
+    K = g.me;
+    row_end = g.me;
+  }
   uint32_t a_fix = 0, c0;
   if (TL) {
     c0 = ct * TNC;
@@ -895,7 +996,6 @@ __global__ void __launch_bounds__(T::THREADS)
     a_fix = ct / g.bt;
     c0 = (ct % g.bt) * TNC;
   }
-  const int64_t piece = (int64_t)g.npad * g.npad;
 
   constexpr int KUA = TK / 8;  // A units: 8 bf16 (16 bytes)
   constexpr int AU = TM * KUA * NP;
@@ -904,8 +1004,8 @@ __global__ void __launch_bounds__(T::THREADS)
   constexpr int BU = TNC * KUB;
   constexpr int BIT = (BU + T::THREADS - 1) / T::THREADS;
 
-  v8bf ra[AIT];
-  C rb[BIT][LG];
+  v8bf ra[NB][AIT];
+  C rb[NR][BIT][LG];
 
   auto unit_b = [&](int u, int& row, int& kq) {
     if (TL) {
@@ -919,115 +1019,148 @@ __global__ void __launch_bounds__(T::THREADS)
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int u = tid + it * T::THREADS;
-      if (AU % T::THREADS == 0 || u < AU) {
-        const int q = u / (TM * KUA), rem = u % (TM * KUA);
-        const int row = rem / KUA, kq = rem % KUA;
-        ra[it] = *(const v8bf*)&Mp[q * piece + (int64_t)(m0 + row) * g.npad + k0 + kq * 8];
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int u = tid + it * T::THREADS;
+        if (AU % T::THREADS == 0 || u < AU) {
+          const int q = u / (TM * KUA), rem = u % (TM * KUA);
+          const int row = rem / KUA, kq = rem % KUA;
+          ra[h][it] = *(const v8bf*)&Ma[(h * NP + q) * piece + (int64_t)(m0 + row) * g.npad + k0 + kq * 8];
+        }
       }
-    }
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
         unit_b(u, row, kq);
-        if (TL)
-          load_b_unit<C, LG, TL>(g, U, c0 + row, 0, k0 + kq * LG, g.n, 0, false, rb[it]);
-        else
-          load_b_unit<C, LG, TL>(g, U, a_fix, c0 + row, k0 + kq * LG, g.n, 0, false, rb[it]);
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        const int kb = k0 + kq * LG;
+        if (SP == kDense) {
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.n, 0, false, rb[0][it]);
+        } else if (SP == kSplitFwd) {
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+        } else {
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
+        }
       }
+    }
+  };
+  auto put_b = [&](int buf, int h, int row, int kq, const C (&v)[LG]) {
+    v4bf re[NP], im[NP];
+#pragma unroll
+    for (int e = 0; e < LG; ++e) {
+      __bf16 pr[NP], pi[NP];
+      split_bf16<NP>(v[e].x, pr);
+      split_bf16<NP>(v[e].y, pi);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        re[q][e] = pr[q];
+        im[q][e] = pi[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      *(v4bf*)&Bs[buf][h][q][row * LDK + kq * LG] = re[q];
+      *(v4bf*)&Bs[buf][h][q][(TNC + row) * LDK + kq * LG] = im[q];
     }
   };
   auto sstore = [&](int buf, int kt) {
     const int k0 = kt * TK;
 #pragma unroll
-    for (int it = 0; it < AIT; ++it) {
-      const int u = tid + it * T::THREADS;
-      if (AU % T::THREADS == 0 || u < AU) {
-        const int q = u / (TM * KUA), rem = u % (TM * KUA);
-        const int row = rem / KUA, kq = rem % KUA;
-        *(v8bf*)&As[buf][q][row * LDK + kq * 8] = ra[it];
+    for (int h = 0; h < NB; ++h)
+#pragma unroll
+      for (int it = 0; it < AIT; ++it) {
+        const int u = tid + it * T::THREADS;
+        if (AU % T::THREADS == 0 || u < AU) {
+          const int q = u / (TM * KUA), rem = u % (TM * KUA);
+          const int row = rem / KUA, kq = rem % KUA;
+          *(v8bf*)&As[buf][h][q][row * LDK + kq * 8] = ra[h][it];
+        }
       }
-    }
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
         unit_b(u, row, kq);
-        if (TL)
-          pro_b_unit<C, LG, TL, Pro>(g, c0 + row, 0, k0 + kq * LG, g.n, 0, false, pro, rb[it]);
-        else
-          pro_b_unit<C, LG, TL, Pro>(g, a_fix, c0 + row, k0 + kq * LG, g.n, 0, false, pro, rb[it]);
-        v4bf re[NP], im[NP];
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        const int kb = k0 + kq * LG;
+        if (SP == kDense) {
+          pro_b_unit<C, LG, TL, Pro>(g, a, b, kb, g.n, 0, false, pro, rb[0][it]);
+          put_b(buf, 0, row, kq, rb[0][it]);
+        } else if (SP == kSplitFwd) {
+          pro_b_unit<C, LG, TL, Pro>(g, a, b, kb, K, 0, false, pro, rb[0][it]);
+          pro_b_unit<C, LG, TL, Pro>(g, a, b, kb, K, 0, true, pro, rb[NR - 1][it]);
+          C v[LG];
+          const float sg = odd ? -1.0f : 1.0f;
 #pragma unroll
-        for (int e = 0; e < LG; ++e) {
-          __bf16 pr[NP], pi[NP];
-          split_bf16<NP>(rb[it][e].x, pr);
-          split_bf16<NP>(rb[it][e].y, pi);
-#pragma unroll
-          for (int q = 0; q < NP; ++q) {
-            re[q][e] = pr[q];
-            im[q][e] = pi[q];
+          for (int e = 0; e < LG; ++e) {
+            v[e].x = rb[0][it][e].x + sg * rb[NR - 1][it][e].x;
+            v[e].y = rb[0][it][e].y + sg * rb[NR - 1][it][e].y;
           }
-        }
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          *(v4bf*)&Bs[buf][q][row * LDK + kq * LG] = re[q];
-          *(v4bf*)&Bs[buf][q][(TNC + row) * LDK + kq * LG] = im[q];
+          put_b(buf, 0, row, kq, v);
+        } else {
+          put_b(buf, 0, row, kq, rb[0][it]);
+          put_b(buf, NB - 1, row, kq, rb[NR - 1][it]);
         }
       }
     }
   };
 
-  v4f acc[T::FM][T::FNC][2];
+  v4f acc[NB][T::FM][T::FNC][2];
 #pragma unroll
-  for (int fm = 0; fm < T::FM; ++fm)
+  for (int h = 0; h < NB; ++h)
 #pragma unroll
-    for (int fn = 0; fn < T::FNC; ++fn)
+    for (int fm = 0; fm < T::FM; ++fm)
 #pragma unroll
-      for (int p = 0; p < 2; ++p) acc[fm][fn][p] = v4f{0, 0, 0, 0};
+      for (int fn = 0; fn < T::FNC; ++fn)
+#pragma unroll
+        for (int p = 0; p < 2; ++p) acc[h][fm][fn][p] = v4f{0, 0, 0, 0};
 
   const int lr = lane & 15, lk = (lane >> 4) * 8;
   auto compute = [&](int buf) {
 #pragma unroll
-    for (int kg = 0; kg < TK; kg += 32) {
-      v8bf bf[T::FNC][2][NP];
+    for (int h = 0; h < NB; ++h)
 #pragma unroll
-      for (int fn = 0; fn < T::FNC; ++fn)
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-#pragma unroll
-          for (int q = 0; q < NP; ++q)
-            bf[fn][p][q] = *(const v8bf*)&Bs[buf][q][(p * TNC + wn * T::WTNC + fn * 16 + lr) * LDK + kg + lk];
-#pragma unroll
-      for (int fm = 0; fm < T::FM; ++fm) {
-        v8bf af[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) af[q] = *(const v8bf*)&As[buf][q][(wm * T::WTM + fm * 16 + lr) * LDK + kg + lk];
+      for (int kg = 0; kg < TK; kg += 32) {
+        v8bf bf[T::FNC][2][NP];
 #pragma unroll
         for (int fn = 0; fn < T::FNC; ++fn)
 #pragma unroll
-          for (int p = 0; p < 2; ++p) {
-            v4f c = acc[fm][fn][p];
-            // smallest terms first
-            if (NP == 3) {
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][NP - 1], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[fn][p][1], c, 0, 0, 0);
-              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[NP - 1], bf[fn][p][0], c, 0, 0, 0);
+          for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < NP; ++q)
+              bf[fn][p][q] = *(const v8bf*)&Bs[buf][h][q][(p * TNC + wn * T::WTNC + fn * 16 + lr) * LDK + kg + lk];
+#pragma unroll
+        for (int fm = 0; fm < T::FM; ++fm) {
+          v8bf af[NP];
+#pragma unroll
+          for (int q = 0; q < NP; ++q) af[q] = *(const v8bf*)&As[buf][h][q][(wm * T::WTM + fm * 16 + lr) * LDK + kg + lk];
+#pragma unroll
+          for (int fn = 0; fn < T::FNC; ++fn)
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+              v4f c = acc[h][fm][fn][p];
+              // smallest terms first
+              if (NP == 3) {
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][NP - 1], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[fn][p][1], c, 0, 0, 0);
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[NP - 1], bf[fn][p][0], c, 0, 0, 0);
+              }
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][1], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[fn][p][0], c, 0, 0, 0);
+              c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][0], c, 0, 0, 0);
+              acc[h][fm][fn][p] = c;
             }
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][1], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[1], bf[fn][p][0], c, 0, 0, 0);
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[0], bf[fn][p][0], c, 0, 0, 0);
-            acc[fm][fn][p] = c;
-          }
+        }
       }
-    }
   };
 
-  const int KT = (g.n + TK - 1) / TK;
+  const int KT = (K + TK - 1) / TK;
   gload(0);
   sstore(0, 0);
   __syncthreads();
@@ -1039,9 +1172,22 @@ __global__ void __launch_bounds__(T::THREADS)
     __syncthreads();
   }
 
-  run_epilogue<float, T, TL>(
-      g, a_fix, c0, m0, g.n, epi, [&](int fm, int fn, int p, int r) { return acc[fm][fn][p][r]; },
-      [](int l, int r) { return MfmaT<float>::row(l, r); }, [](int i) { return i; }, smem);
+  auto rowmap = [](int l, int r) { return MfmaT<float>::row(l, r); };
+  if (SP != kSplitBwd) {
+    run_epilogue<float, T, TL>(
+        g, a_fix, c0, base + m0, base + row_end, epi,
+        [&](int fm, int fn, int p, int r) { return acc[0][fm][fn][p][r]; }, rowmap, [](int i) { return i; }, smem);
+  } else {
+    const int n1 = g.n - 1;
+    run_epilogue<float, T, TL>(
+        g, a_fix, c0, m0, g.me, epi,
+        [&](int fm, int fn, int p, int r) { return acc[0][fm][fn][p][r] + acc[NB - 1][fm][fn][p][r]; }, rowmap,
+        [](int i) { return i; }, smem);
+    run_epilogue<float, T, TL>(
+        g, a_fix, c0, m0, g.mo, epi,
+        [&](int fm, int fn, int p, int r) { return acc[0][fm][fn][p][r] - acc[NB - 1][fm][fn][p][r]; }, rowmap,
+        [n1](int i) { return n1 - i; }, smem);
+  }
 }
 
 // ---------------------------------------------------------------------------------------

@@ -9,18 +9,35 @@ struct BFK {
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {
     const Geo g = make_geo<T>(L, TL, 4);
-    hipLaunchKernelGGL((mp_bf16_kernel<T, NP, TL, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
+    hipLaunchKernelGGL((mp_bf16_kernel<T, NP, TL, SP, Pro, Epi>), dim3(g.nblocks), dim3(T::THREADS), 0, s, g,
                        (const __bf16*)L.M, (const float2*)L.in, Pro(L.pp), Epi(L.ep));
     return hipGetLastError();
   }
 };
 
 hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
+  // Split tiles stay within the 160 KB of LDS with two operand blocks of NP pieces each.
   if (L.prec == P_BF16X3) {
+    if (L.split) {
+      switch (L.cfg) {
+        case 0: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
+        case 1: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
+        case 2: return dispatch_split<BFK<2>, TileCfg<64, 32, 32, 1, 2>>(L, s);
+        default: return hipErrorInvalidValue;
+      }
+    }
     switch (L.cfg) {
       case 0: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 2, 2>>(L, s);
       case 1: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2>>(L, s);
       case 2: return dispatch_cfg<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  if (L.split) {
+    switch (L.cfg) {
+      case 0: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
+      case 1: return dispatch_split<BFK<3>, TileCfg<64, 16, 32, 1, 1>>(L, s);
+      case 2: return dispatch_split<BFK<3>, TileCfg<128, 16, 32, 2, 1>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }

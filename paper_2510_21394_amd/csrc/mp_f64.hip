@@ -17,9 +17,9 @@ struct F64K {
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s) {
   if (L.split) {
     switch (L.cfg) {
-      case 0: return dispatch_split<F64K, TileCfg<128, 32, 8, 2, 2>>(L, s);
-      case 1: return dispatch_split<F64K, TileCfg<64, 32, 8, 1, 2>>(L, s);
-      case 2: return dispatch_split<F64K, TileCfg<64, 16, 8, 1, 1>>(L, s);
+      case 0: return dispatch_split<F64K, TileCfg<128, 32, 16, 2, 2>>(L, s);
+      case 1: return dispatch_split<F64K, TileCfg<64, 32, 16, 1, 2>>(L, s);
+      case 2: return dispatch_split<F64K, TileCfg<64, 16, 16, 1, 1>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }

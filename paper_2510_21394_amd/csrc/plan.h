@@ -111,6 +111,7 @@ struct fcgle_plan {
   void* Mbs[4] = {nullptr, nullptr, nullptr, nullptr};
   bool tuned = false;
   int fusion = 3;  // bit 0: prologue, bit 1: epilogue
+  bool fwd_rev = false;  // forward operators run their mode products from axis d to axis 1
   int* dflag = nullptr;
   // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled
   // copy, the forward-transformed adjoint source, and the recomputed segment (u_k, X_k)

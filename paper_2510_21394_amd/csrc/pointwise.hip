@@ -23,22 +23,38 @@ __global__ void __launch_bounds__(kPwThreads)
     out[j] = pro(j, in[j]);
 }
 
-// One workgroup per row of the fastest axis (the tensor viewed as (rows, nlast)): the
-// per-row context of the epilogue (the separable factor of the slower axes) is formed once
-// and no index division is needed per element.
+// The tensor viewed as (rows, nlast); each workgroup pass takes kPwChunk consecutive
+// elements, kPwUnroll per thread (loads of all of them before any store), and forms the
+// per-row context of the epilogue (the separable factor of the slower axes) per element.
+constexpr int kPwUnroll = 8;
+constexpr int kPwChunk = kPwThreads * kPwUnroll;
+
 template <class R, class Epi>
 __global__ void __launch_bounds__(kPwThreads)
     pw_epi_kernel(uint32_t rows, int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
-  for (uint32_t a = blockIdx.x; a < rows; a += gridDim.x) {
-    const auto ctx = epi.col(a, 0);
-    const int64_t base = (int64_t)a * nlast;
-    for (int i = threadIdx.x; i < nlast; i += kPwThreads) {
-      const auto x = v[base + i];
-      const int ii[1] = {i};
-      const int64_t jj[1] = {base + i};
-      const bool ok[1] = {true};
-      const R re[1] = {x.x}, im[1] = {x.y};
-      epi.template apply<1>(ctx, ii, jj, ok, re, im);
+  const int64_t N = (int64_t)rows * nlast;
+  for (int64_t e0 = (int64_t)blockIdx.x * kPwChunk; e0 < N; e0 += (int64_t)gridDim.x * kPwChunk) {
+    int ii[kPwUnroll];
+    int64_t jj[kPwUnroll];
+    bool ok[kPwUnroll];
+    R re[kPwUnroll], im[kPwUnroll];
+    typename Epi::Pre pre[kPwUnroll];
+#pragma unroll
+    for (int u = 0; u < kPwUnroll; ++u) {
+      const int64_t j = e0 + threadIdx.x + (int64_t)u * kPwThreads;
+      ok[u] = j < N;
+      jj[u] = ok[u] ? j : 0;
+      ii[u] = (int)(jj[u] % nlast);
+      const auto x = ok[u] ? v[jj[u]] : typename Cx<R>::T{0, 0};
+      re[u] = x.x;
+      im[u] = x.y;
+    }
+    epi.template load<kPwUnroll>(ii, jj, ok, pre);
+#pragma unroll
+    for (int u = 0; u < kPwUnroll; ++u) {
+      if (!ok[u]) continue;
+      const auto ctx = epi.col((uint32_t)(jj[u] / nlast), 0);
+      epi.template store<1>(ctx, ii + u, jj + u, ok + u, re + u, im + u, pre + u);
     }
   }
 }
@@ -99,8 +115,9 @@ template <class R, class Epi>
 hipError_t epi_launch(int64_t N, int nlast, const void* v, const EpiParams& p, hipStream_t s) {
   using C = typename Cx<R>::T;
   const int64_t rows = N / nlast;
-  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(rows < 65536 ? rows : 65536)), dim3(kPwThreads), 0,
-                     s, (uint32_t)rows, nlast, (const C*)v, Epi(p));
+  const int64_t chunks = (N + kPwChunk - 1) / kPwChunk;
+  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(chunks < 65536 ? chunks : 65536)), dim3(kPwThreads),
+                     0, s, (uint32_t)rows, nlast, (const C*)v, Epi(p));
   return hipGetLastError();
 }
 
@@ -120,9 +137,10 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
 }  // namespace
 
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek) {
-  if (!tloader) return ek == EpiKind::Store;
-  return pk == ProKind::Id && (ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep ||
-                               ek == EpiKind::ExpEuler || ek == EpiKind::KeepOld);
+  if (pk != ProKind::Id) return ek == EpiKind::Store;
+  if (!tloader) return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler;
+  return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler ||
+         ek == EpiKind::KeepOld;
 }
 
 hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,
@@ -164,6 +182,6 @@ hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, co
 
 int cfg_rows(int prec, int cfg, int split) { return kCfgRows[split ? 1 : 0][prec][cfg]; }
 int cfg_cols(int prec, int cfg, int split) { return kCfgCols[split ? 1 : 0][prec][cfg]; }
-bool split_supported(int prec) { return prec == P_F64 || prec == P_F32; }
+bool split_supported(int prec) { return prec >= P_F64 && prec <= P_BF16X6; }
 
 }  // namespace fcgle

@@ -177,8 +177,11 @@ class Plan:
     def set_tiles(self, axis: int, fwd: bool, cfg: int):
         L.check(self.lib.fcgle_set_tiles(self.handle, int(axis), int(bool(fwd)), int(cfg)))
 
-    def set_fusion(self, prologue: bool = True, epilogue: bool = True):
-        L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)))
+    def set_fusion(self, prologue: bool = True, epilogue: bool = True, reverse: bool = False):
+        """Fuse the nonlinearity into the first / the pointwise epilogue into the last mode
+        product; reverse: run forward operators from the last axis to the first."""
+        L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)
+                                          | (4 if reverse else 0)))
 
     def set_structure(self, split: bool):
         """True: even/odd half-size mode products (default for fp64/fp32); False: dense."""

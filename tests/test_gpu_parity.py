@@ -240,8 +240,9 @@ def test_timing_counts_mode_products(F):
     assert sig == {"exp_euler"}
 
 
-@pytest.mark.parametrize("fusion", [(False, False), (True, False), (False, True)])
-@pytest.mark.parametrize("scheme", ["exp_euler", "lbdf2"])
+@pytest.mark.parametrize("fusion", [(False, False, False), (True, False, False), (False, True, False),
+                                    (True, True, True), (False, False, True), (True, False, True)])
+@pytest.mark.parametrize("scheme", ["exp_euler", "lbdf2", "lawson"])
 def test_unfused_paths_match_oracle(F, fusion, scheme):
     n = (22, 35, 19)
     params = BASE_PARAMS
@@ -257,7 +258,7 @@ def test_unfused_paths_match_oracle(F, fusion, scheme):
 
 
 @pytest.mark.parametrize("prec,split", [("fp64", True), ("fp64", False), ("fp32", True), ("fp32", False),
-                                        ("bf16x3", False), ("bf16x6", False)])
+                                        ("bf16x3", True), ("bf16x3", False), ("bf16x6", True), ("bf16x6", False)])
 @pytest.mark.parametrize("cfg", [0, 1, 2])
 def test_every_tile_configuration(F, prec, split, cfg):
     n = (300, 70, 129)
@@ -275,7 +276,7 @@ def test_every_tile_configuration(F, prec, split, cfg):
     assert err <= TOL_OP[prec]
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("n", [(2, 3), (3, 2, 5), (7,), (33, 64), (17, 40, 31), (129, 18, 16)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_dense_and_even_odd_structures_agree_with_oracle(F, prec, n):
