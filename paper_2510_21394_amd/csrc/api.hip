@@ -173,9 +173,11 @@ int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
   for (auto& e : P->seps)
     if (e.theta == theta) {
       for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
+      sp->other_last = e.other_last;
+      sp->other_first = e.other_first;
       return FCGLE_OK;
     }
-  SepBuf e{theta, {nullptr, nullptr, nullptr, nullptr}};
+  SepBuf e{theta, {nullptr, nullptr, nullptr, nullptr}, nullptr, nullptr};
   for (int m = 0; m < P->d; ++m) {
     std::vector<double> buf(2 * P->n[m]);
     for (int64_t j = 0; j < P->n[m]; ++j) {
@@ -186,8 +188,25 @@ int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
     FC_TRY(plan_alloc(&e.fac[m], buf.size() * sizeof(double)));
     HIP_TRY(hipMemcpy(e.fac[m], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
   }
-  P->seps.push_back(e);
   for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
+  // per-column factor tables for epilogues on the last and on the first axis
+  const int64_t cl = P->N / P->n[P->d - 1], cf = P->N / P->n[0];
+  int rc = plan_alloc(&e.other_last, (size_t)cl * 2 * sizeof(double));
+  if (rc == FCGLE_OK) rc = plan_alloc(&e.other_first, (size_t)cf * 2 * sizeof(double));
+  if (rc == FCGLE_OK && launch_sep_table(*sp, P->d - 1, cl, e.other_last, nullptr) != hipSuccess)
+    rc = fail(FCGLE_ERR_HIP, "separable factor table: launch failed");
+  if (rc == FCGLE_OK && launch_sep_table(*sp, 0, cf, e.other_first, nullptr) != hipSuccess)
+    rc = fail(FCGLE_ERR_HIP, "separable factor table: launch failed");
+  if (rc == FCGLE_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(FCGLE_ERR_HIP, "separable factor table");
+  if (rc != FCGLE_OK) {
+    for (int m = 0; m < P->d; ++m) (void)hipFree(e.fac[m]);
+    if (e.other_last) (void)hipFree(e.other_last);
+    if (e.other_first) (void)hipFree(e.other_first);
+    return rc;
+  }
+  P->seps.push_back(e);
+  sp->other_last = e.other_last;
+  sp->other_first = e.other_first;
   return FCGLE_OK;
 }
 
@@ -541,8 +560,11 @@ void free_plan(fcgle_plan* P) {
     f(P->dlam[m]);
   }
   for (auto& g : P->grids) f(g.F);
-  for (auto& e : P->seps)
+  for (auto& e : P->seps) {
     for (int m = 0; m < 4; ++m) f(e.fac[m]);
+    f(e.other_last);
+    f(e.other_first);
+  }
   for (int k = 0; k < 3; ++k) f(P->s[k]);
   f(P->uhat);
   f(P->uprev);

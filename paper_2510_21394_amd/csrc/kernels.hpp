@@ -146,8 +146,9 @@ struct ProNonlinF {
 struct NoCtx {};
 struct NoPre {};
 
-// Product over the axes other than mu of the separable per-axis factors.
-__device__ __forceinline__ zc sep_other(const SepParams& s, uint32_t a, uint32_t b) {
+// Product over the axes other than mu of the separable per-axis factors (a: flat index over
+// the slower axes, b: over the faster ones).
+__device__ __forceinline__ zc sep_other_direct(const SepParams& s, uint32_t a, uint32_t b) {
   zc E{1.0, 0.0};
   for (int nu = s.d - 1; nu > s.mu; --nu) {
     const uint32_t jn = b % (uint32_t)s.n[nu];
@@ -160,6 +161,12 @@ __device__ __forceinline__ zc sep_other(const SepParams& s, uint32_t a, uint32_t
     E = zmul(E, ((const zc*)s.fac[nu])[jn]);
   }
   return E;
+}
+
+__device__ __forceinline__ zc sep_other(const SepParams& s, uint32_t a, uint32_t b) {
+  if (s.mu == s.d - 1 && s.other_last) return ((const zc*)s.other_last)[a];
+  if (s.mu == 0 && s.other_first) return ((const zc*)s.other_first)[b];
+  return sep_other_direct(s, a, b);
 }
 
 template <class C, class R>

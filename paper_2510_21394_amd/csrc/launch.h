@@ -36,12 +36,17 @@ struct ProParams {
 };
 
 // Separable per-axis complex factors (FP64): value(j) = prod_mu fac[mu][j_mu].
+// other_last / other_first (optional) hold prod over the axes other than the last / the
+// first, indexed by the flat index over the remaining axes, so an epilogue on the last
+// (first) axis gets its per-column factor with one load.
 struct SepParams {
   int d = 0;
   int mu = 0;  // axis of the mode product (its index comes from the output row)
   int n[4] = {1, 1, 1, 1};
   const void* fac[4] = {nullptr, nullptr, nullptr, nullptr};  // double2[n_mu]
   const double* lam[4] = {nullptr, nullptr, nullptr, nullptr}; // eigenvalues (adjoint)
+  const void* other_last = nullptr;   // double2[N / n_{d-1}]
+  const void* other_first = nullptr;  // double2[N / n_0]
 };
 
 struct EpiParams {
@@ -140,6 +145,9 @@ hipError_t launch_adj_hat(int prec, int64_t N, int nlast, const void* v, void* a
 // Sums `count` per-block partial rows of width `width` into acc[width] (acc += sum).
 hipError_t launch_reduce_partials(const double* partial, int64_t count, int width, double* acc,
                                   hipStream_t s);
+// other = prod over the axes != mu (mu = 0 or d-1) of the separable factors, for all
+// `count` flat indices over the remaining axes (FP64, double2).
+hipError_t launch_sep_table(const SepParams& sep, int mu, int64_t count, void* other, hipStream_t s);
 // Elementwise f-grid from separable eigenvalues: F[j] = f(theta (nu + i eta) sum lam_mu[j_mu]),
 // evaluated in FP64 on the device and stored in the state type.
 hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, const SepParams& sep,

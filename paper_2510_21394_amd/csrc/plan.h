@@ -62,7 +62,9 @@ struct GridBuf {
 
 struct SepBuf {
   double theta;
-  void* fac[4];  // double2[n_mu] each
+  void* fac[4];       // double2[n_mu] each
+  void* other_last;   // double2[N / n_{d-1}]: product over the axes before the last
+  void* other_first;  // double2[N / n_0]: product over the axes after the first
 };
 
 struct TimedLaunch {

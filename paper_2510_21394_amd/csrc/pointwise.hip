@@ -23,38 +23,37 @@ __global__ void __launch_bounds__(kPwThreads)
     out[j] = pro(j, in[j]);
 }
 
-// The tensor viewed as (rows, nlast); each workgroup pass takes kPwChunk consecutive
-// elements, kPwUnroll per thread (loads of all of them before any store), and forms the
-// per-row context of the epilogue (the separable factor of the slower axes) per element.
-constexpr int kPwUnroll = 8;
-constexpr int kPwChunk = kPwThreads * kPwUnroll;
+// The tensor viewed as (rows, nlast); each workgroup pass takes kPwRows consecutive rows,
+// a thread one element of each (loads of all of them before any store); the per-row
+// context of the epilogue (the separable factor of the slower axes) is one table load.
+constexpr int kPwRows = 8;
 
 template <class R, class Epi>
 __global__ void __launch_bounds__(kPwThreads)
     pw_epi_kernel(uint32_t rows, int nlast, const typename Cx<R>::T* __restrict__ v, Epi epi) {
-  const int64_t N = (int64_t)rows * nlast;
-  for (int64_t e0 = (int64_t)blockIdx.x * kPwChunk; e0 < N; e0 += (int64_t)gridDim.x * kPwChunk) {
-    int ii[kPwUnroll];
-    int64_t jj[kPwUnroll];
-    bool ok[kPwUnroll];
-    R re[kPwUnroll], im[kPwUnroll];
-    typename Epi::Pre pre[kPwUnroll];
+  for (uint32_t r0 = blockIdx.x * kPwRows; r0 < rows; r0 += gridDim.x * kPwRows) {
+    for (int i0 = threadIdx.x; i0 < nlast; i0 += kPwThreads) {
+      int ii[kPwRows];
+      int64_t jj[kPwRows];
+      bool ok[kPwRows];
+      R re[kPwRows], im[kPwRows];
+      typename Epi::Pre pre[kPwRows];
 #pragma unroll
-    for (int u = 0; u < kPwUnroll; ++u) {
-      const int64_t j = e0 + threadIdx.x + (int64_t)u * kPwThreads;
-      ok[u] = j < N;
-      jj[u] = ok[u] ? j : 0;
-      ii[u] = (int)(jj[u] % nlast);
-      const auto x = ok[u] ? v[jj[u]] : typename Cx<R>::T{0, 0};
-      re[u] = x.x;
-      im[u] = x.y;
-    }
-    epi.template load<kPwUnroll>(ii, jj, ok, pre);
+      for (int u = 0; u < kPwRows; ++u) {
+        ok[u] = r0 + u < rows;
+        ii[u] = i0;
+        jj[u] = (int64_t)(ok[u] ? r0 + u : r0) * nlast + i0;
+        const auto x = ok[u] ? v[jj[u]] : typename Cx<R>::T{0, 0};
+        re[u] = x.x;
+        im[u] = x.y;
+      }
+      epi.template load<kPwRows>(ii, jj, ok, pre);
 #pragma unroll
-    for (int u = 0; u < kPwUnroll; ++u) {
-      if (!ok[u]) continue;
-      const auto ctx = epi.col((uint32_t)(jj[u] / nlast), 0);
-      epi.template store<1>(ctx, ii + u, jj + u, ok + u, re + u, im + u, pre + u);
+      for (int u = 0; u < kPwRows; ++u) {
+        if (!ok[u]) continue;
+        const auto ctx = epi.col(r0 + u, 0);
+        epi.template store<1>(ctx, ii + u, jj + u, ok + u, re + u, im + u, pre + u);
+      }
     }
   }
 }
@@ -74,6 +73,13 @@ __global__ void __launch_bounds__(kPwThreads)
     const zc z{tr * ell, ti * ell};
     F[j] = from_zc<C>(fz_eval(kind, z));
   }
+}
+
+__global__ void __launch_bounds__(kPwThreads)
+    sep_table_kernel(SepParams s, int mu, int64_t count, zc* __restrict__ out) {
+  s.mu = mu;
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < count; j += (int64_t)gridDim.x * kPwThreads)
+    out[j] = (mu == 0) ? sep_other_direct(s, 0, (uint32_t)j) : sep_other_direct(s, (uint32_t)j, 0);
 }
 
 template <class C>
@@ -115,8 +121,8 @@ template <class R, class Epi>
 hipError_t epi_launch(int64_t N, int nlast, const void* v, const EpiParams& p, hipStream_t s) {
   using C = typename Cx<R>::T;
   const int64_t rows = N / nlast;
-  const int64_t chunks = (N + kPwChunk - 1) / kPwChunk;
-  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(chunks < 65536 ? chunks : 65536)), dim3(kPwThreads),
+  const int64_t groups = (rows + kPwRows - 1) / kPwRows;
+  hipLaunchKernelGGL((pw_epi_kernel<R, Epi>), dim3((unsigned)(groups < 65536 ? groups : 65536)), dim3(kPwThreads),
                      0, s, (uint32_t)rows, nlast, (const C*)v, Epi(p));
   return hipGetLastError();
 }
@@ -151,6 +157,11 @@ hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, 
 hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,
                                 const EpiParams& p, hipStream_t s) {
   return prec == P_F64 ? epi_impl<double>(N, n_last, v, ek, p, s) : epi_impl<float>(N, n_last, v, ek, p, s);
+}
+
+hipError_t launch_sep_table(const SepParams& sep, int mu, int64_t count, void* other, hipStream_t s) {
+  hipLaunchKernelGGL(sep_table_kernel, dim3(pw_blocks(count)), dim3(kPwThreads), 0, s, sep, mu, count, (zc*)other);
+  return hipGetLastError();
 }
 
 hipError_t launch_check_finite(int prec, int64_t N, const void* u, int* flag, hipStream_t s) {
