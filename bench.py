@@ -180,7 +180,13 @@ def batch_timing(steps=500):
     plan.run(us, 0.0, steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    flop = sum(8.0 * i.n[0] * i.n[1] * (i.n[0] + i.n[1]) for i in insts)
+    # even/odd mode products: per axis 4 (me^2 + mo^2) N / n flop, forward and backward
+    flop = 0.0
+    for i in insts:
+        N = i.n[0] * i.n[1]
+        for m in i.n:
+            me, mo = m - m // 2, m // 2
+            flop += 2 * 4.0 * (me * me + mo * mo) * N / m
     out = {"workload": "2d_batch64_expeuler", "instances": len(insts), "steps": steps,
            "steps_per_s": steps / el, "ms_per_step": 1e3 * el / steps,
            "mode_product_tflops": flop * steps / el / 1e12, "tiles": plan.describe()}

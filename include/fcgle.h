@@ -203,7 +203,7 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
  * plan's scratch and cached eigenspace state.  Synchronous.  Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
-/* Choose the tile configuration (0..2; rows x columns per tile depend on the precision and
+/* Choose the tile configuration (0..4; rows x columns per tile depend on the precision and
  * structure, see fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
  * Results do not depend on it beyond rounding order.  Errors: ERR_ARG. */
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
@@ -240,7 +240,7 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * record.  For launch i < *count (at most cap): axis[i] = mode axis (0-based),
  * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
  * its duration, sig[i] = the kernel instantiation it ran:
- *   sig = structure * 512 + (((prec * 4 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
+ *   sig = structure * 1024 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
  * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q; prec 0..3 as fcgle_precision;
  * t_loader 1 for the fastest axis; prologue 0 none,
  * 1 nonlinearity; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,

@@ -87,26 +87,13 @@ int upload_matrix(fcgle_plan* P, const std::vector<double>& M, int64_t n, int64_
   return FCGLE_OK;
 }
 
-// Upload the stacked split block matrices of one axis, forward [Fe; Fo] and backward
-// [Be; Bo], each block ld x ld zero padded, in the plan's precision.  They are read off the
-// plan's Q (exact even/odd structure, Q = Z diag(Ve, Vo)), so the split products round like
-// the dense ones (i, k < me resp. mo; m = n/2):
-//   Fe[i][k] = Q[k][i] (k < m), Q[m][i]/2 (k = m, odd n);   Fo[i][k] = Q[k][me + i]
-//   Be[i][k] = Q[i][k];                                       Bo[i][k] = Q[i][me + k]
+// Upload the stacked split block matrices of one axis (split_block_matrices: forward
+// [Fe; Fo], backward [Be; Bo], read off the plan's Q), each block ld x ld, in the plan's
+// precision.
 int upload_split(fcgle_plan* P, int mu) {
-  const int64_t n = P->n[mu], me = P->me[mu], mo = P->mo[mu], m = n / 2, ld = P->ldsp[mu];
-  const std::vector<double>& Q = P->Q[mu];
-  std::vector<double> F(2 * ld * ld, 0.0), B(2 * ld * ld, 0.0);
-  for (int64_t i = 0; i < me; ++i)
-    for (int64_t k = 0; k < me; ++k) {
-      F[i * ld + k] = (k < m) ? Q[k * n + i] : 0.5 * Q[m * n + i];
-      B[i * ld + k] = Q[i * n + k];
-    }
-  for (int64_t i = 0; i < mo; ++i)
-    for (int64_t k = 0; k < mo; ++k) {
-      F[ld * ld + i * ld + k] = Q[k * n + me + i];
-      B[ld * ld + i * ld + k] = Q[i * n + me + k];
-    }
+  const int64_t ld = P->ldsp[mu];
+  std::vector<double> F, B;
+  split_block_matrices(P->n[mu], P->me[mu], P->mo[mu], P->Q[mu], ld, F, B);
   const int pr = precision_of(P);
   // FP64 / FP32 as is; split-BF16 as NP pieces per block, block-major ([h][piece][ld x ld]),
   // each entry split in FP64: q0 = bf16(q), q1 = bf16(q - q0), ...
@@ -218,7 +205,7 @@ int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
     tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
     tl.axis = axis;
     tl.fwd = L.split ? (L.split == 1 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
-    tl.sig = L.split * 512 + ((((L.prec * 4 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
+    tl.sig = L.split * 1024 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
     HIP_TRY(hipEventRecord(tl.e0, st));
   }
   HIP_TRY(launch_mode_product(L, st));

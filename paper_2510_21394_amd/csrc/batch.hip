@@ -31,13 +31,14 @@ enum PhaseId { PH_T0 = 0, PH_T1, PH_F0, PH_F1, PH_B0, PH_B1, PH_COUNT };
 
 struct BatchInst {
   int64_t n[2] = {0, 0};
-  int npad[2] = {0, 0};
+  int npad[2] = {0, 0};   // leading dimension of each block matrix (>= me)
+  int me[2] = {0, 0}, mo[2] = {0, 0};  // even / odd block sizes per axis
   double alpha[2] = {0, 0}, h[2] = {0, 0};
   fcgle_params p{};
   int64_t N = 0;
   std::vector<double> Q[2], lam[2];
-  float* Mf[2] = {nullptr, nullptr};
-  float* Mb[2] = {nullptr, nullptr};
+  float* Mf[2] = {nullptr, nullptr};  // [Fe; Fo] per axis (forward, even/odd blocks)
+  float* Mb[2] = {nullptr, nullptr};  // [Be; Bo] per axis (backward)
   double* dlam[2] = {nullptr, nullptr};
   double* fac[2] = {nullptr, nullptr};  // exp(tau (nu + i eta) lambda), complex FP64
   float2* P1 = nullptr;
@@ -108,6 +109,9 @@ MPLaunch inst_launch(const BatchData* B, const BatchInst& I, int phase, const vo
   L.B = axis1 ? 1 : I.n[1];
   L.n = (int)I.n[mu];
   L.npad = I.npad[mu];
+  L.split = fwd ? 1 : 2;
+  L.me = I.me[mu];
+  L.mo = I.mo[mu];
   L.M = fwd ? (const void*)I.Mf[mu] : (const void*)I.Mb[mu];
   L.pk = ph.pk;
   L.ek = ph.ek;
@@ -214,7 +218,8 @@ int build_items(BatchData* B, const void* const* u) {
 
 int launch_phase(const BatchData* B, int p, hipStream_t st) {
   const Phase& ph = B->ph[p];
-  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, ph.items, B->count, ph.nblocks, st));
+  const bool fwd = (p == PH_T0 || p == PH_T1 || p == PH_F0 || p == PH_F1);
+  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, fwd, ph.items, B->count, ph.nblocks, st));
   return FCGLE_OK;
 }
 
@@ -254,6 +259,7 @@ int get_graph(BatchData* B, int64_t steps, hipGraphExec_t* out) {
 }
 
 constexpr int64_t kGraphChunk = 500;  // steps per captured graph (longer runs replay it)
+constexpr int kGroupCfg = 3;          // tile configurations of the grouped kernels (group_f32.hip)
 
 int batch_run_impl(fcgle_plan* P, void* const* u, int64_t nsteps, hipStream_t st) {
   BatchData* B = P->batch;
@@ -301,7 +307,7 @@ int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEve
   for (int p : order) {
     float best = 1e30f;
     int best_c = B->ph[p].cfg;
-    for (int c = 0; c < kNumCfg; ++c) {
+    for (int c = 0; c < kGroupCfg; ++c) {
       B->ph[p].cfg = c;
       FC_TRY(build_items(B, scratch.data()));
       float ms;
@@ -318,7 +324,7 @@ int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEve
   int best_c = 1;
   bool best_fuse = true;
   for (int f = 0; f < 2; ++f)
-    for (int c = 0; c < kNumCfg; ++c) {
+    for (int c = 0; c < kGroupCfg; ++c) {
       B->fuse = (f == 0);
       B->ph[PH_F1].cfg = c;
       FC_TRY(build_items(B, scratch.data()));
@@ -364,13 +370,14 @@ int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
   for (const auto& I : B->inst) {
     nmin = std::min({nmin, I.n[0], I.n[1]});
     nmax = std::max({nmax, I.n[0], I.n[1]});
-    flop += 8.0 * (double)I.N * (double)(I.n[0] + I.n[1]);
+    for (int m = 0; m < 2; ++m)
+      flop += 2.0 * 4.0 * (double)(I.me[m] * I.me[m] + I.mo[m] * I.mo[m]) * (double)I.N / (double)I.n[m];
   }
   static const char* names[] = {"t0", "t1", "f0", "f1", "b0", "b1"};
   std::string s = "batch count=" + std::to_string(B->count) + " n in [" + std::to_string(nmin) + "," +
-                  std::to_string(nmax) + "] precision=fp32 tiles(rows)=";
+                  std::to_string(nmax) + "] precision=fp32 structure=even-odd tiles(rows)=";
   for (int p = 0; p < PH_COUNT; ++p)
-    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg)) + (p + 1 < PH_COUNT ? "," : "");
+    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg, 1)) + (p + 1 < PH_COUNT ? "," : "");
   s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
   char tail[96];
   std::snprintf(tail, sizeof(tail), " flop/step=%.4g%s", flop, B->tuned ? " tuned" : " default");
@@ -439,7 +446,9 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
       I.n[m] = n[2 * i + m];
       I.alpha[m] = alpha[2 * i + m];
       I.h[m] = h[2 * i + m];
-      I.npad[m] = (int)round_up(I.n[m], 256);
+      I.me[m] = (int)(I.n[m] - I.n[m] / 2);
+      I.mo[m] = (int)(I.n[m] / 2);
+      I.npad[m] = (int)round_up(I.me[m], 128);
     }
     I.N = I.n[0] * I.n[1];
   }
@@ -454,7 +463,12 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
         for (int j = (int)w; j < jobs; j += (int)hw) {
           BatchInst& I = B->inst[j / 2];
           const int m = j % 2;
-          ok[j] = toeplitz_eig(I.n[m], I.alpha[m], I.h[m], 2, I.Q[m], I.lam[m]);
+          SplitEig se;
+          ok[j] = toeplitz_eig_split(I.n[m], I.alpha[m], I.h[m], 2, se);
+          if (ok[j]) {
+            I.Q[m].swap(se.Q);
+            I.lam[m].swap(se.lam);
+          }
         }
       });
     for (auto& t : th) t.join();
@@ -466,7 +480,7 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
   size_t total = 0;
   for (const auto& I : B->inst) {
     for (int m = 0; m < 2; ++m)
-      total += 2 * al((size_t)I.npad[m] * I.npad[m] * sizeof(float)) + al(I.n[m] * sizeof(double)) +
+      total += 2 * al((size_t)2 * I.npad[m] * I.npad[m] * sizeof(float)) + al(I.n[m] * sizeof(double)) +
                al(2 * I.n[m] * sizeof(double));
     total += 4 * al((size_t)I.N * 8);
   }
@@ -481,7 +495,7 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
     };
     for (auto& I : B->inst) {
       for (int m = 0; m < 2; ++m) {
-        const size_t mb = (size_t)I.npad[m] * I.npad[m] * sizeof(float);
+        const size_t mb = (size_t)2 * I.npad[m] * I.npad[m] * sizeof(float);
         I.Mf[m] = (float*)take(mb);
         I.Mb[m] = (float*)take(mb);
         I.dlam[m] = (double*)take(I.n[m] * sizeof(double));
@@ -493,17 +507,14 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
       I.tmp2 = (float2*)take((size_t)I.N * 8);
     }
   }
-  // uploads: Q^T and Q (FP32, zero padded), eigenvalues, separable exponential factors
+  // uploads: the even/odd block matrices (FP32), eigenvalues, separable exponential factors
   for (int i = 0; i < count; ++i) {
     BatchInst& I = B->inst[i];
     for (int m = 0; m < 2; ++m) {
-      const int64_t nm = I.n[m], np = I.npad[m];
-      std::vector<float> qt(np * np, 0.0f), q(np * np, 0.0f);
-      for (int64_t r = 0; r < nm; ++r)
-        for (int64_t k = 0; k < nm; ++k) {
-          q[r * np + k] = (float)I.Q[m][r * nm + k];
-          qt[r * np + k] = (float)I.Q[m][k * nm + r];
-        }
+      const int64_t nm = I.n[m];
+      std::vector<double> Fd, Bd;
+      split_block_matrices(nm, I.me[m], I.mo[m], I.Q[m], I.npad[m], Fd, Bd);
+      const std::vector<float> qt(Fd.begin(), Fd.end()), q(Bd.begin(), Bd.end());
       std::vector<double> fac(2 * nm);
       for (int64_t j = 0; j < nm; ++j) {
         const zc z = fz_eval(1, zc{tau * I.p.nu * I.lam[m][j], tau * I.p.eta * I.lam[m][j]});

@@ -9,10 +9,12 @@ namespace fcgle {
 // precision; index [split ? 1 : 0][prec][cfg].  The even/odd split kernels contract half-size
 // blocks (at most n/2 + 1 rows each) and the backward form carries two accumulator sets, so
 // their tiles are smaller.
-constexpr int kCfgRows[2][4][kNumCfg] = {{{256, 128, 64}, {256, 128, 64}, {256, 128, 64}, {128, 64, 64}},
-                                         {{128, 64, 64}, {128, 64, 128}, {64, 128, 64}, {64, 64, 128}}};
-constexpr int kCfgCols[2][4][kNumCfg] = {{{32, 32, 32}, {64, 64, 64}, {64, 64, 64}, {64, 64, 32}},
-                                         {{32, 32, 16}, {64, 64, 32}, {64, 32, 32}, {32, 16, 16}}};
+constexpr int kCfgRows[2][4][kNumCfg] = {
+    {{256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}, {128, 64, 64, 64, 128}},
+    {{128, 64, 64, 128, 128}, {128, 64, 128, 128, 128}, {64, 128, 64, 64, 128}, {64, 64, 128, 64, 64}}};
+constexpr int kCfgCols[2][4][kNumCfg] = {
+    {{32, 32, 32, 32, 32}, {64, 64, 64, 64, 64}, {64, 64, 64, 64, 64}, {64, 64, 32, 64, 64}},
+    {{32, 32, 16, 32, 64}, {64, 64, 32, 64, 128}, {64, 32, 32, 64, 32}, {32, 16, 16, 32, 16}}};
 
 // Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
 // combinations a structure never needs are not instantiated.

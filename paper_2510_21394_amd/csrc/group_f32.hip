@@ -8,43 +8,53 @@ namespace fcgle {
 
 namespace {
 
-template <bool TL, class Pro, class Epi>
+template <bool TL, int SP, class Pro, class Epi>
 struct Combo {
   static constexpr bool tl = TL;
+  static constexpr int sp = SP;
   using P = Pro;
   using E = Epi;
 };
 
-// Calls f(Combo<...>{}) for the supported (loader, prologue, epilogue) combination.
+// Calls f(Combo<...>{}) for the supported (loader, prologue, epilogue) combination; forward
+// products (Q^T) use the even/odd forward form, backward ones (Q) the backward form.
 template <class F>
-bool with_combo(bool tl, ProKind pk, EpiKind ek, F&& f) {
+bool with_combo(bool tl, ProKind pk, EpiKind ek, bool fwd, F&& f) {
   using R = float;
-  if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
-    f(Combo<false, ProNonlinF<R>, EpiStoreF<R>>{});
-    return true;
+  if (fwd) {
+    if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
+      f(Combo<false, kSplitFwd, ProNonlinF<R>, EpiStoreF<R>>{});
+      return true;
+    }
+    if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
+      f(Combo<false, kSplitFwd, ProIdF, EpiStoreF<R>>{});
+      return true;
+    }
+    if (tl && pk == ProKind::Id && ek == EpiKind::Store) {
+      f(Combo<true, kSplitFwd, ProIdF, EpiStoreF<R>>{});
+      return true;
+    }
+    if (tl && pk == ProKind::Id && ek == EpiKind::ExpEuler) {
+      f(Combo<true, kSplitFwd, ProIdF, EpiExpEulerF<R>>{});
+      return true;
+    }
+    return false;
   }
-  if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
-    f(Combo<false, ProIdF, EpiStoreF<R>>{});
-    return true;
-  }
-  if (tl && pk == ProKind::Id && ek == EpiKind::Store) {
-    f(Combo<true, ProIdF, EpiStoreF<R>>{});
-    return true;
-  }
-  if (tl && pk == ProKind::Id && ek == EpiKind::ExpEuler) {
-    f(Combo<true, ProIdF, EpiExpEulerF<R>>{});
-    return true;
-  }
-  return false;
+  if (pk != ProKind::Id || ek != EpiKind::Store) return false;
+  if (tl)
+    f(Combo<true, kSplitBwd, ProIdF, EpiStoreF<R>>{});
+  else
+    f(Combo<false, kSplitBwd, ProIdF, EpiStoreF<R>>{});
+  return true;
 }
 
-// The FP32 tile configurations (same as the single-problem FP32 kernels).
+// The FP32 tile configurations of the even/odd kernels.
 template <class F>
 bool with_cfg(int cfg, F&& f) {
   switch (cfg) {
-    case 0: f(TileCfg<256, 64, 16, 2, 2>{}); return true;
-    case 1: f(TileCfg<128, 64, 16, 2, 2>{}); return true;
-    case 2: f(TileCfg<64, 64, 16, 1, 2>{}); return true;
+    case 0: f(TileCfg<128, 64, 16, 2, 2>{}); return true;
+    case 1: f(TileCfg<64, 64, 16, 1, 2>{}); return true;
+    case 2: f(TileCfg<128, 32, 16, 2, 2>{}); return true;
     default: return false;
   }
 }
@@ -81,26 +91,28 @@ __global__ void __launch_bounds__(256)
 
 }  // namespace
 
-bool group_supported(bool tloader, ProKind pk, EpiKind ek) {
-  return with_combo(tloader, pk, ek, [](auto) {});
+bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd) {
+  return with_combo(tloader, pk, ek, fwd, [](auto) {});
 }
 
 size_t group_item_bytes(ProKind pk, EpiKind ek) {
   size_t b = 0;
   for (int tl = 0; tl < 2; ++tl)
-    with_combo(tl != 0, pk, ek, [&](auto c) {
-      using Cb = decltype(c);
-      b = sizeof(GroupItem<typename Cb::P, typename Cb::E>);
-    });
+    for (int fwd = 0; fwd < 2; ++fwd)
+      with_combo(tl != 0, pk, ek, fwd != 0, [&](auto c) {
+        using Cb = decltype(c);
+        b = sizeof(GroupItem<typename Cb::P, typename Cb::E>);
+      });
   return b;
 }
 
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host) {
   uint32_t total = 0;
+  const bool fwd = count > 0 && L[0].split == kSplitFwd;
   with_cfg(cfg, [&](auto t) {
     using T = decltype(t);
-    with_combo(tloader, pk, ek, [&](auto c) {
+    with_combo(tloader, pk, ek, fwd, [&](auto c) {
       using Cb = decltype(c);
       using Item = GroupItem<typename Cb::P, typename Cb::E>;
       unsigned char* dst = (unsigned char*)items_host;
@@ -120,17 +132,17 @@ uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MP
   return total;
 }
 
-hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const void* items_dev, int count,
-                            uint32_t nblocks, hipStream_t s) {
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, bool fwd, const void* items_dev,
+                            int count, uint32_t nblocks, hipStream_t s) {
   hipError_t err = hipErrorInvalidValue;
   if (count < 1 || nblocks == 0) return err;
   with_cfg(cfg, [&](auto t) {
     using T = decltype(t);
-    with_combo(tloader, pk, ek, [&](auto c) {
+    with_combo(tloader, pk, ek, fwd, [&](auto c) {
       using Cb = decltype(c);
       using Item = GroupItem<typename Cb::P, typename Cb::E>;
-      hipLaunchKernelGGL((mp_group_kernel<float, T, Cb::tl, typename Cb::P, typename Cb::E>), dim3(nblocks),
-                         dim3(T::THREADS), 0, s, (const Item*)items_dev, count, nblocks);
+      hipLaunchKernelGGL((mp_group_kernel<float, T, Cb::tl, Cb::sp, typename Cb::P, typename Cb::E>),
+                         dim3(nblocks), dim3(T::THREADS), 0, s, (const Item*)items_dev, count, nblocks);
       err = hipGetLastError();
     });
   });

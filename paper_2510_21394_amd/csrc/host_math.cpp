@@ -350,6 +350,23 @@ bool toeplitz_eig_split(int64_t n, double alpha, double h, int fd_order, SplitEi
   return true;
 }
 
+void split_block_matrices(int64_t n, int64_t me, int64_t mo, const std::vector<double>& Q, int64_t ld,
+                          std::vector<double>& F, std::vector<double>& B) {
+  const int64_t m = n / 2;
+  F.assign(2 * ld * ld, 0.0);
+  B.assign(2 * ld * ld, 0.0);
+  for (int64_t i = 0; i < me; ++i)
+    for (int64_t k = 0; k < me; ++k) {
+      F[i * ld + k] = (k < m) ? Q[k * n + i] : 0.5 * Q[m * n + i];
+      B[i * ld + k] = Q[i * n + k];
+    }
+  for (int64_t i = 0; i < mo; ++i)
+    for (int64_t k = 0; k < mo; ++k) {
+      F[ld * ld + i * ld + k] = Q[k * n + me + i];
+      B[ld * ld + i * ld + k] = Q[i * n + me + k];
+    }
+}
+
 // --- bfloat16 ----------------------------------------------------------------------------
 
 uint16_t bf16_round(double x) {

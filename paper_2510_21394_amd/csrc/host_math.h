@@ -39,6 +39,15 @@ struct SplitEig {
 };
 bool toeplitz_eig_split(int64_t n, double alpha, double h, int fd_order, SplitEig& s);
 
+// The stacked even/odd block matrices of the split mode products, read off Q (n x n,
+// exact even/odd structure, block order), each block ld x ld zero padded (ld >= me):
+//   F = [Fe; Fo] (forward, Q^T):  Fe[i][k] = Q[k][i] (k < m), Q[m][i]/2 (k = m, odd n);
+//                                 Fo[i][k] = Q[k][me + i]
+//   B = [Be; Bo] (backward, Q):   Be[i][k] = Q[i][k];  Bo[i][k] = Q[i][me + k]
+// so that the split products are the dense ones with the same Q, summed in another order.
+void split_block_matrices(int64_t n, int64_t me, int64_t mo, const std::vector<double>& Q, int64_t ld,
+                          std::vector<double>& F, std::vector<double>& B);
+
 // Round a double to the nearest bfloat16 (ties to even); returns the bf16 bits.
 uint16_t bf16_round(double x);
 double bf16_value(uint16_t b);

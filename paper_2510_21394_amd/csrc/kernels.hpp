@@ -923,14 +923,14 @@ __device__ __forceinline__ int find_item(const Item* __restrict__ items, int cou
   return lo;
 }
 
-template <class R, class T, bool TL, class Pro, class Epi>
+template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __global__ void __launch_bounds__(T::THREADS)
     mp_group_kernel(const GroupItem<Pro, Epi>* __restrict__ items, int count, uint32_t nblocks) {
   const uint32_t b = xcd_remap(blockIdx.x, nblocks);
   const int k = find_item(items, count, b);
   const GroupItem<Pro, Epi>& it = items[k];
-  mp_mfma_tile<R, T, TL, kDense, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro,
-                                           it.epi, b - it.first);
+  mp_mfma_tile<R, T, TL, SP, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro, it.epi,
+                                       b - it.first);
 }
 
 // ---------------------------------------------------------------------------------------

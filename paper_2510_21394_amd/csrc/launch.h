@@ -80,7 +80,7 @@ struct MPLaunch {
   EpiParams ep;
 };
 
-constexpr int kNumCfg = 3;  // tile configurations per precision and structure
+constexpr int kNumCfg = 5;  // tile configurations per precision and structure
 int cfg_rows(int prec, int cfg, int split = 0);
 int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
 // True when the even/odd split kernels exist for the precision.
@@ -98,18 +98,19 @@ inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
   return launch_mp_bf16(L, s);
 }
 
-// Grouped FP32 mode products: the same mode product (same loader, prologue and epilogue
-// kinds, tile configuration `cfg`) of `count` independent problems in one launch.
-// group_build_f32 writes the item array for the per-problem descriptions L[0..count) into
-// host memory (group_item_bytes(pk, ek) bytes per item) and returns the total number of
-// workgroups; the array must then be copied to the device and passed to launch_group_f32.
-// Supported: (N loader, Nonlin or Id, Store), (T loader, Id, Store or ExpEuler).
-bool group_supported(bool tloader, ProKind pk, EpiKind ek);
+// Grouped FP32 even/odd mode products: the same mode product (same loader, prologue and
+// epilogue kinds, direction, tile configuration `cfg`) of `count` independent problems in
+// one launch.  group_build_f32 writes the item array for the per-problem descriptions
+// L[0..count) (split = 1 forward or 2 backward) into host memory (group_item_bytes(pk, ek)
+// bytes per item) and returns the total number of workgroups; the array must then be copied
+// to the device and passed to launch_group_f32.  Supported: forward (N loader, Nonlin or Id,
+// Store), (T loader, Id, Store or ExpEuler); backward (either loader, Id, Store).
+bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd);
 size_t group_item_bytes(ProKind pk, EpiKind ek);
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host);
-hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const void* items_dev, int count,
-                            uint32_t nblocks, hipStream_t s);
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, bool fwd, const void* items_dev,
+                            int count, uint32_t nblocks, hipStream_t s);
 // Grouped streaming epilogue (FP32): item k applies `ek` (ExpEuler) to v[k] viewed as
 // (rows[k], nlast[k]) with parameters ep[k]; returns the total number of rows.
 size_t pw_group_item_bytes(EpiKind ek);

@@ -23,6 +23,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
         case 0: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
         case 1: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
         case 2: return dispatch_split<BFK<2>, TileCfg<64, 32, 32, 1, 2>>(L, s);
+        case 3: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
+        case 4: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
         default: return hipErrorInvalidValue;
       }
     }
@@ -30,6 +32,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
       case 0: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 2, 2>>(L, s);
       case 1: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2>>(L, s);
       case 2: return dispatch_cfg<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
+      case 3: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2>>(L, s);
+      case 4: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 2, 2>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -38,6 +42,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
       case 0: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
       case 1: return dispatch_split<BFK<3>, TileCfg<64, 16, 32, 1, 1>>(L, s);
       case 2: return dispatch_split<BFK<3>, TileCfg<128, 16, 32, 2, 1>>(L, s);
+      case 3: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
+      case 4: return dispatch_split<BFK<3>, TileCfg<64, 16, 32, 1, 1>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -45,6 +51,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
     case 0: return dispatch_cfg<BFK<3>, TileCfg<128, 64, 32, 2, 2>>(L, s);
     case 1: return dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 1, 2>>(L, s);
     case 2: return dispatch_cfg<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
+    case 3: return dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 1, 2>>(L, s);
+    case 4: return dispatch_cfg<BFK<3>, TileCfg<128, 64, 32, 2, 2>>(L, s);
     default: return hipErrorInvalidValue;
   }
 }

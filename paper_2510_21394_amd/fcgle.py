@@ -268,16 +268,16 @@ class BatchPlan:
 
 def decode_signature(sig: int) -> dict:
     """Inverse of the kernel signature of fcgle_timing_read."""
-    structure = sig // 512
-    sig %= 512
+    structure = sig // 1024
+    sig %= 1024
     ek = sig % 8
     sig //= 8
     pk = sig % 2
     sig //= 2
     tl = sig % 2
     sig //= 2
-    cfg = sig % 4
-    prec = sig // 4
+    cfg = sig % 8
+    prec = sig // 8
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
             "structure": ["dense", "even_odd_fwd", "even_odd_bwd"][structure],
             "prologue": ["none", "nonlinearity"][pk],

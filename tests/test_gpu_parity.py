@@ -259,7 +259,7 @@ def test_unfused_paths_match_oracle(F, fusion, scheme):
 
 @pytest.mark.parametrize("prec,split", [("fp64", True), ("fp64", False), ("fp32", True), ("fp32", False),
                                         ("bf16x3", True), ("bf16x3", False), ("bf16x6", True), ("bf16x6", False)])
-@pytest.mark.parametrize("cfg", [0, 1, 2])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 def test_every_tile_configuration(F, prec, split, cfg):
     n = (300, 70, 129)
     alpha, h = _setup(n, 21)
