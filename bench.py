@@ -75,6 +75,9 @@ def parse():
                     help="first copy MIB MiB device-to-device once (a plain copy kernel of known size, "
                          "to scale hardware byte counters)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and adjoint context timings")
+    ap.add_argument("--tile-sweep", action="store_true",
+                    help="after the timed steps, run one step in every tile configuration and forward order "
+                         "(so that a counter run sees every kernel the autotuner may pick)")
     return ap.parse_args()
 
 
@@ -92,7 +95,7 @@ def mode_product_flop(n, structure):
     return 4.0 * (me * me + mo * mo) * N / m + 2.0 * N
 
 
-def time_precision(prec, w, U0, steps, warmup, autotune, golden):
+def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=False):
     import torch
     from paper_2510_21394_amd import Plan
     from paper_2510_21394_amd.fcgle import decode_signature
@@ -123,6 +126,18 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden):
         got = v.reshape(-1)[torch.from_numpy(golden["idx"]).cuda()].cpu().numpy().astype(np.complex128)
         ref = golden["val"]
         err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    if tile_sweep:
+        from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
+        v = u0.clone()
+        for reverse in (False, True):
+            plan.set_fusion(True, True, reverse)
+            for cfg in range(NUM_TILE_CONFIGS):
+                for axis in range(len(w.n)):
+                    for fwd in (False, True):
+                        plan.set_tiles(axis, fwd, cfg)
+                plan.set_state(v)
+                plan.run("exp_euler", v, 0.0, 1)
+        torch.cuda.synchronize()
     # per-kernel aggregation (kernel instantiation = signature)
     per = {}
     for axis, fwd, sig, ms in rec:
@@ -268,7 +283,8 @@ def main():
     variants = {}
     order = [a.precision] + [p for p in a.variants.split(",") if p and p != a.precision]
     for prec in order:
-        variants[prec] = time_precision(prec, w, U0, a.steps, a.warmup, not a.no_autotune, golden)
+        variants[prec] = time_precision(prec, w, U0, a.steps, a.warmup, not a.no_autotune, golden,
+                                        a.tile_sweep and prec == a.precision)
         print(f"# {prec}: {variants[prec]['steps_per_s']:.1f} steps/s, "
               f"{variants[prec]['ms_per_step']:.3f} ms/step, err {variants[prec]['rel_l2_vs_fp64_oracle_at_T']}",
               file=sys.stderr, flush=True)

@@ -15,6 +15,7 @@ from . import _lib as L
 
 STATE_DTYPE = {"fp64": torch.complex128, "fp32": torch.complex64, "bf16x3": torch.complex64,
                "bf16x6": torch.complex64}
+NUM_TILE_CONFIGS = 5  # tile configurations accepted by fcgle_set_tiles (0 .. 4)
 
 
 def _stream():
