@@ -95,6 +95,35 @@ def mode_product_flop(n, structure):
     return 4.0 * (me * me + mo * mo) * N / m + 2.0 * N
 
 
+def mode_product_bytes(n, kernel, elem):
+    """Algorithmic HBM bytes of one mode-product launch on a complex tensor of N elements of
+    `elem` bytes (the workload has no source term): read the input and write the output,
+    2 e N; with the fused exponential-Euler epilogue the output is not stored but uhat and
+    the P1 grid are read and uhat written, 4 e N; with the update prologue (the update of
+    the state applied by the first backward product) ghat, uhat and P1 are read and the new
+    state and the product written, 5 e N.  The per-axis factor tables are negligible."""
+    N = float(np.prod(n))
+    if kernel["prologue"] == "exp_euler_update":
+        return 5.0 * elem * N
+    if kernel["epilogue"] == "exp_euler":
+        return 4.0 * elem * N
+    return 2.0 * elem * N
+
+
+def roofline_of(kernel, flop, nbytes, avg_ms, prec):
+    """Which roofline bounds the kernel (the larger of its MFMA and HBM time at peak) and the
+    fraction of that bound it reaches."""
+    t_mfma = flop / (PEAK_TFLOPS[prec] * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    sec = avg_ms * 1e-3
+    if t_hbm > t_mfma:
+        ach = nbytes / sec / 1e9
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS}
+    ach = flop / sec / 1e12
+    return {"bound": "mfma", "achieved": ach, "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+            "frac": ach / PEAK_TFLOPS[prec]}
+
+
 def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=False):
     import torch
     from paper_2510_21394_amd import Plan
@@ -129,8 +158,8 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
     if tile_sweep:
         from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
         v = u0.clone()
-        for reverse in (False, True):
-            plan.set_fusion(True, True, reverse)
+        for reverse, upd in ((False, False), (True, False), (False, True), (True, True)):
+            plan.set_fusion(True, True, reverse, update_in_backward=upd)
             for cfg in range(NUM_TILE_CONFIGS):
                 for axis in range(len(w.n)):
                     for fwd in (False, True):
@@ -151,15 +180,22 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
     dom_sig = max(per, key=lambda s: per[s]["ms"])
     dom = per[dom_sig]
     avg_ms = dom["ms"] / dom["count"]
-    dom_flop = mode_product_flop(w.n, decode_signature(dom_sig)["structure"])
+    elem = 16 if prec == "fp64" else 8
+    dom_kernel = decode_signature(dom_sig)
+    dom_flop = mode_product_flop(w.n, dom_kernel["structure"])
+    dom_bytes = mode_product_bytes(w.n, dom_kernel, elem)
     achieved = dom_flop / (avg_ms * 1e-3) / 1e12
     kernels = []
     for sig, d in sorted(per.items(), key=lambda kv: -kv[1]["ms"]):
         a = d["ms"] / d["count"]
-        fl = mode_product_flop(w.n, decode_signature(sig)["structure"])
-        kernels.append({"kernel": decode_signature(sig), "signature": sig, "launches_per_step": d["count"] / steps,
-                        "avg_us": round(a * 1e3, 2), "flop_per_launch": fl,
-                        "tflops": round(fl / (a * 1e-3) / 1e12, 2),
+        kd = decode_signature(sig)
+        fl = mode_product_flop(w.n, kd["structure"])
+        nb = mode_product_bytes(w.n, kd, elem)
+        rl = roofline_of(kd, fl, nb, a, prec)
+        kernels.append({"kernel": kd, "signature": sig, "launches_per_step": d["count"] / steps,
+                        "avg_us": round(a * 1e3, 2), "flop_per_launch": fl, "bytes_per_launch": nb,
+                        "tflops": round(fl / (a * 1e-3) / 1e12, 2), "gbs": round(nb / (a * 1e-3) / 1e9, 1),
+                        "bound": rl["bound"], "frac": round(rl["frac"], 3),
                         "axes_dirs": sorted(d["launches"])})
     out = {
         "precision": prec,
@@ -169,8 +205,10 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
         "mode_product_tflops_avg": total_flop / (total_mp_ms * 1e-3) / 1e12,
         "rel_l2_vs_fp64_oracle_at_T": err,
         "tiles": plan.describe(),
-        "dominant": {"signature": dom_sig, "kernel": decode_signature(dom_sig), "avg_ms": avg_ms,
-                     "flop_per_launch": dom_flop, "achieved_tflops": achieved, "count": dom["count"]},
+        "dominant": {"signature": dom_sig, "kernel": dom_kernel, "avg_ms": avg_ms,
+                     "flop_per_launch": dom_flop, "bytes_per_launch": dom_bytes, "achieved_tflops": achieved,
+                     "achieved_gbs": dom_bytes / (avg_ms * 1e-3) / 1e9, "count": dom["count"],
+                     "roofline": roofline_of(dom_kernel, dom_flop, dom_bytes, avg_ms, prec)},
         "kernels": kernels,
     }
     plan.close()
@@ -308,17 +346,15 @@ def main():
                    "params": list(w.params), "tau": w.tau, "scheme": "exp_euler", "precision": a.precision,
                    "rel_l2_steps": int(golden["steps"]) if golden is not None else None},
         "rel_l2_vs_fp64_oracle_at_T": head["rel_l2_vs_fp64_oracle_at_T"],
-        "roofline": {
-            "bound": "mfma",
-            "kernel": dom["kernel"],
-            "achieved": dom["achieved_tflops"],
-            "peak": peak,
-            "unit": "TFLOP/s",
-            "frac": dom["achieved_tflops"] / peak,
+        "roofline": dict(dom["roofline"], **{
             "traffic": stored_traffic(dom["kernel"]),
+            "kernel": dom["kernel"],
             "per_launch_flop": dom["flop_per_launch"],
+            "per_launch_bytes": dom["bytes_per_launch"],
             "avg_launch_ms": dom["avg_ms"],
-        },
+            "mfma_frac": dom["achieved_tflops"] / peak,
+            "hbm_frac": dom["achieved_gbs"] / HBM_PEAK_GBS,
+        }),
         "variants": {p: {k: v for k, v in d.items() if k != "kernels"} for p, d in variants.items()},
         "kernels": head["kernels"],
     }

@@ -223,8 +223,11 @@ int fcgle_set_structure(fcgle_plan* plan, int split);
  * exponential-Euler update, LBDF2 history) into the last one; a cleared bit runs that
  * map as a separate streaming kernel.  Bit 2 runs the mode products of forward (Q^T)
  * operators from the last axis to the first (the products commute), so the epilogue lands
- * on a product along a slow axis.  Default 3; fcgle_autotune picks all three by timing
- * whole forward operators.  Errors: ERR_ARG. */
+ * on a product along a slow axis.  Bit 3 moves the exponential-Euler update
+ * uhat <- E uhat + tau P1 ghat out of the forward operator into the first backward product,
+ * which applies it to ghat while loading its tile, stores the new state and contracts it
+ * (even/odd FP64 / FP32 plans with d >= 2; otherwise bit 3 is ignored).  Default 3;
+ * fcgle_autotune picks all four by timing whole exponential-Euler steps.  Errors: ERR_ARG. */
 int fcgle_set_fusion(fcgle_plan* plan, int flags);
 
 /* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */
@@ -240,10 +243,10 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * record.  For launch i < *count (at most cap): axis[i] = mode axis (0-based),
  * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
  * its duration, sig[i] = the kernel instantiation it ran:
- *   sig = structure * 1024 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 2 + prologue) * 8 + epilogue
+ *   sig = structure * 2048 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 4 + prologue) * 8 + epilogue
  * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q; prec 0..3 as fcgle_precision;
- * t_loader 1 for the fastest axis; prologue 0 none,
- * 1 nonlinearity; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
+ * t_loader 1 for the fastest axis; prologue 0 none, 1 nonlinearity, 2 exponential-Euler
+ * update; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
  * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */
 int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
                       int64_t* count);

@@ -205,7 +205,7 @@ int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
     tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
     tl.axis = axis;
     tl.fwd = L.split ? (L.split == 1 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
-    tl.sig = L.split * 1024 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 2 + (int)L.pk) * 8) + (int)L.ek;
+    tl.sig = L.split * 2048 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 4 + (int)L.pk) * 8) + (int)L.ek;
     HIP_TRY(hipEventRecord(tl.e0, st));
   }
   HIP_TRY(launch_mode_product(L, st));
@@ -266,7 +266,13 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
     const bool tl = (L.B == 1);
     L.in = cur;
     if (first && pk != ProKind::Id) {
-      if ((P->fusion & 1) && mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
+      if (pk == ProKind::Update) {
+        // no streaming form: callers check update_prologue_ok first
+        L.pk = pk;
+        L.pp = pp;
+        L.pp.sep.mu = mu;
+        if (P->cfg_upd >= 0) L.cfg = P->cfg_upd;
+      } else if ((P->fusion & 1) && mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
         L.pk = pk;
         L.pp = pp;
       } else {
@@ -338,6 +344,52 @@ int default_cfg(int pr, int64_t n, bool split) {
   return best;
 }
 
+// The exponential-Euler update can run in the loads of the first backward product (axis 0,
+// N loader) when that product is an even/odd FP64 / FP32 one.
+bool update_prologue_ok(const fcgle_plan* P) {
+  const int pr = precision_of(P);
+  return P->split && P->d > 1 && (pr == P_F64 || pr == P_F32) && mp_supported(false, ProKind::Update, EpiKind::Store);
+}
+
+// One exponential-Euler step on the eigenspace state uhat (Section 4, eq. for the scheme):
+// ghat = Q^T g(t, u_n), uhat <- E uhat + tau P1 ghat, u <- Q uhat.  With fusion bit 3 the
+// update is applied by the first backward product while it loads ghat (the new state goes to
+// the second buffer, which then becomes the state); otherwise by the epilogue of the last
+// forward product (bit 1) or a streaming pass.
+int expeuler_body(fcgle_plan* P, void* u, double t, hipStream_t st) {
+  const double tau = P->tau;
+  const void* P1;
+  FC_TRY(get_grid(P, FCGLE_PHI1, tau, st, &P1));
+  SepParams sep;
+  FC_TRY(get_sep(P, tau, &sep));
+  const ProParams pp = nonlin_params(P, t);  // g(t_n, u_n)
+  EpiParams eb;
+  eb.out = u;
+  if ((P->fusion & 8) && update_prologue_ok(P)) {
+    if (!P->uhat2) FC_TRY(plan_alloc(&P->uhat2, (size_t)P->N * P->elem));
+    EpiParams eg;
+    eg.out = P->s[2];
+    FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, EpiKind::Store, eg, P->s[0], P->s[1], st));
+    ProParams up;
+    up.uhat = P->uhat;
+    up.F = P1;
+    up.uhat_out = P->uhat2;
+    up.sep = sep;
+    up.tau = tau;
+    FC_TRY(tucker(P, false, P->s[2], ProKind::Update, up, EpiKind::Store, eb, P->s[0], P->s[1], st));
+    std::swap(P->uhat, P->uhat2);
+    return FCGLE_OK;
+  }
+  EpiParams ep;
+  ep.out = P->uhat;
+  ep.F = P1;
+  ep.tau = tau;
+  ep.sep = sep;
+  FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, EpiKind::ExpEuler, ep, P->s[0], P->s[1], st));
+  FC_TRY(tucker(P, false, P->uhat, ProKind::Id, ProParams(), EpiKind::Store, eb, P->s[0], P->s[1], st));
+  return FCGLE_OK;
+}
+
 int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
   FC_TRY(ensure_state_buffers(P));
   const double tau = P->tau;
@@ -347,18 +399,7 @@ int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
       ep.out = P->uhat;
       FC_TRY(tucker(P, true, u, ProKind::Id, ProParams(), EpiKind::Store, ep, P->s[0], P->s[1], st));
     }
-    const void* P1;
-    FC_TRY(get_grid(P, FCGLE_PHI1, tau, st, &P1));
-    EpiParams ep;
-    ep.out = P->uhat;
-    ep.F = P1;
-    ep.tau = tau;
-    FC_TRY(get_sep(P, tau, &ep.sep));
-    ProParams pp = nonlin_params(P, t);  // g(t_n, u_n)
-    FC_TRY(tucker(P, true, u, ProKind::Nonlin, pp, EpiKind::ExpEuler, ep, P->s[0], P->s[1], st));
-    EpiParams eb;
-    eb.out = u;
-    FC_TRY(tucker(P, false, P->uhat, ProKind::Id, ProParams(), EpiKind::Store, eb, P->s[0], P->s[1], st));
+    FC_TRY(expeuler_body(P, u, t, st));
     P->uhat_valid = true;
     P->uhat_src = u;
     P->hist_valid = false;
@@ -554,6 +595,7 @@ void free_plan(fcgle_plan* P) {
   }
   for (int k = 0; k < 3; ++k) f(P->s[k]);
   f(P->uhat);
+  f(P->uhat2);
   f(P->uprev);
   f(P->dflag);
   for (int k = 0; k < 3; ++k) f(P->adj[k]);
@@ -852,39 +894,48 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
       }
       plan->cfg[mu][dir] = best_c;
     }
-  // 2. order of the forward products and fusion of the nonlinearity prologue and the
-  //    exponential-Euler epilogue: time the whole forward operator of a step for each choice
+  // 2. order of the forward products and where the nonlinearity and the exponential-Euler
+  //    update run (fused prologue / epilogue, streaming passes, or the update in the first
+  //    backward product): time a whole exponential-Euler step for each choice, on zero data
   FC_TRY(ensure_state_buffers(plan));
   HIP_TRY(hipMemsetAsync(plan->uprev, 0, bytes, st));
-  EpiParams ep;
-  ep.out = plan->s[2];
-  ep.tau = plan->tau;
-  FC_TRY(get_grid(plan, FCGLE_PHI1, plan->tau, st, &ep.F));
-  FC_TRY(get_sep(plan, plan->tau, &ep.sep));
-  const ProParams pp = nonlin_params(plan, 0.0);
+  HIP_TRY(hipMemsetAsync(plan->uhat, 0, bytes, st));
+  if (update_prologue_ok(plan)) {
+    if (!plan->uhat2) FC_TRY(plan_alloc(&plan->uhat2, bytes));
+    HIP_TRY(hipMemsetAsync(plan->uhat2, 0, bytes, st));
+  }
+  // with the update in the first backward product that product is timed in every tile
+  // configuration again (its loads differ from the plain product's)
+  static const int kFusions[] = {0, 1, 2, 3, 8, 9};
+  const int nfus = update_prologue_ok(plan) ? 6 : 4;
   float best = 1e30f;
-  int best_fusion = 3;
+  int best_fusion = 3, best_cfg_upd = -1;
   bool best_rev = false;
   for (int rev = 0; rev < (plan->d > 1 ? 2 : 1); ++rev)
-    for (int fusion = 0; fusion < 4; ++fusion) {
-      plan->fwd_rev = (rev != 0);
-      plan->fusion = fusion;
-      float ms;
-      FC_TRY(time_ms(st, e0, e1, reps, [&] {
-        const int rc = tucker(plan, true, plan->uprev, ProKind::Nonlin, pp, EpiKind::ExpEuler, ep, plan->s[0],
-                              plan->s[1], st);
-        return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
-      }, &ms));
-      if (ms < best) {
-        best = ms;
-        best_fusion = fusion;
-        best_rev = (rev != 0);
+    for (int fi = 0; fi < nfus; ++fi) {
+      const int fusion = kFusions[fi];
+      const bool upd = (fusion & 8) != 0;
+      for (int c = upd ? 0 : -1; c < (upd ? kNumCfg : 0); ++c) {
+        plan->fwd_rev = (rev != 0);
+        plan->fusion = fusion;
+        plan->cfg_upd = c;
+        float ms;
+        FC_TRY(time_ms(st, e0, e1, reps, [&] {
+          const int rc = expeuler_body(plan, plan->uprev, 0.0, st);
+          return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
+        }, &ms));
+        if (ms < best) {
+          best = ms;
+          best_fusion = fusion;
+          best_rev = (rev != 0);
+          best_cfg_upd = c;
+        }
       }
     }
   (void)pr;
   plan->fwd_rev = best_rev;
-  const int fusion = best_fusion;
-  plan->fusion = fusion;
+  plan->fusion = best_fusion;
+  plan->cfg_upd = best_cfg_upd;
   return FCGLE_OK;
 }
 
@@ -917,6 +968,7 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
   if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= kNumCfg)
     return fail(FCGLE_ERR_ARG, "set_tiles: bad argument");
   plan->cfg[axis][fwd] = cfg;
+  if (axis == 0 && fwd == 0) plan->cfg_upd = -1;  // the update-prologue product follows it again
   return FCGLE_OK;
 }
 
@@ -929,6 +981,7 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
     plan->split = (split != 0);
     for (int m = 0; m < plan->d; ++m)
       plan->cfg[m][0] = plan->cfg[m][1] = default_cfg(precision_of(plan), plan->n[m], plan->split);
+    plan->cfg_upd = -1;
     plan->tuned = false;
   }
   return FCGLE_OK;
@@ -936,8 +989,8 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
 
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
-  if (flags < 0 || flags > 7) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..7");
-  plan->fusion = flags & 3;
+  if (flags < 0 || flags > 15) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15");
+  plan->fusion = flags & 11;
   plan->fwd_rev = (flags & 4) != 0;
   return FCGLE_OK;
 }
@@ -958,6 +1011,14 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   }
   s += plan->split ? " structure=even-odd" : " structure=dense";
   s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");
+  if (plan->fusion & 8) {
+    if (update_prologue_ok(plan)) {
+      const int c = plan->cfg_upd >= 0 ? plan->cfg_upd : plan->cfg[0][0];
+      s += " update=backward-prologue(" + std::to_string(cfg_rows(pr, c, 1)) + "x" + std::to_string(cfg_cols(pr, c, 1)) + ")";
+    } else {
+      s += " update=backward-prologue(unsupported:epilogue)";
+    }
+  }
   s += plan->fwd_rev ? " forward-order=reversed" : " forward-order=natural";
   s += plan->tuned ? " tuned" : " default";
   std::snprintf(buf, len, "%s", s.c_str());

@@ -22,6 +22,11 @@ template <class K, class T, int SP>
 hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   using R = typename K::R;
   const bool tl = (L.B == 1);
+  if (L.pk == ProKind::Update) {
+    if constexpr (SP == kSplitBwd && K::kUpdate)
+      if (!tl && L.ek == EpiKind::Store) return K::template go<T, false, SP, ProUpdateF<R>, EpiStoreF<R>>(L, s);
+    return hipErrorInvalidValue;
+  }
   if (!tl) {
     if (L.pk != ProKind::Id) {
       if constexpr (SP != kSplitBwd)

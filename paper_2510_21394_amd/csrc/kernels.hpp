@@ -77,6 +77,8 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t w, uint32_t nblocks) {
 
 struct ProIdF {
   static constexpr bool kId = true;
+  static constexpr bool kUpdate = false;  // see ProUpdateF
+  struct Pre {};
   ProIdF() = default;
   explicit ProIdF(const ProParams&) {}
   template <class C>
@@ -90,6 +92,8 @@ struct ProIdF {
 template <class R>
 struct ProNonlinF {
   static constexpr bool kId = false;
+  static constexpr bool kUpdate = false;
+  struct Pre {};
   using C = typename Cx<R>::T;
   const C* up;
   const C* S[4];
@@ -390,6 +394,45 @@ struct EpiKeepOldF {
 
 #undef FCGLE_EPI_APPLY
 
+// Exponential-Euler update applied while the first backward product loads its input
+// (instead of in the epilogue of the last forward product):
+//   uhat_out[j] = E_j uhat[j] + tau P1[j] ghat[j],
+// where ghat (the transformed nonlinearity) is the tensor the product reads; the product
+// then contracts uhat_out.  Same arithmetic as EpiExpEulerF: E uhat in FP64 from the
+// separable factors, tau P1 ghat in the state precision.  The operands uhat[j] and P1[j]
+// are loaded together with the tile (load), the update is applied when the tile is
+// written to LDS (update); the per-column factor of the axes other than mu comes from
+// col() once per loader unit.  uhat_out must not alias uhat: with several row tiles per
+// column the other row tiles still read uhat after the first has written uhat_out.
+template <class R>
+struct ProUpdateF {
+  static constexpr bool kId = false;
+  static constexpr bool kUpdate = true;
+  using C = typename Cx<R>::T;
+  struct Pre {
+    C u, P;
+    zc f;  // factor of axis mu for the element's row
+  };
+  const C* uhat;
+  const C* P1;
+  C* uhat_out;
+  const zc* fac;  // factors of axis mu
+  SepParams s;
+  double tau;
+  ProUpdateF() = default;
+  explicit ProUpdateF(const ProParams& p)
+      : uhat((const C*)p.uhat), P1((const C*)p.F), uhat_out((C*)p.uhat_out), fac((const zc*)p.sep.fac[p.sep.mu]),
+        s(p.sep), tau(p.tau) {}
+  __device__ __forceinline__ zc col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
+  __device__ __forceinline__ Pre load(int64_t j, int i) const { return Pre{uhat[j], P1[j], fac[i]}; }
+  __device__ __forceinline__ C update(const zc& Eo, C g, const Pre& pre) const {
+    const zc eu = zmul(zmul(Eo, pre.f), to_zc(pre.u));
+    const C pg = cmul(pre.P, g);
+    return from_zc<C>(zc{eu.re + tau * (double)pg.x, eu.im + tau * (double)pg.y});
+  }
+  __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
+};
+
 // ---------------------------------------------------------------------------------------
 // Tile configurations and geometry
 // ---------------------------------------------------------------------------------------
@@ -476,14 +519,62 @@ __device__ __forceinline__ void load_b_unit(const Geo& g, const C* __restrict__ 
 template <class C, int G, bool TL, class Pro>
 __device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b, int kb, int klim, int koff,
                                            bool rev, const Pro& pro, C (&v)[G]) {
-  if (Pro::kId) return;
+  if constexpr (!Pro::kId && !Pro::kUpdate) {  // the update prologue has its own path
+#pragma unroll
+    for (int e = 0; e < G; ++e) {
+      const int k = kb + e;
+      const int row = rev ? g.n - 1 - k : koff + k;
+      const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
+      const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
+      if (ok) v[e] = pro(j, v[e]);
+    }
+  }
+}
+
+// Loads of the update-prologue kernels (ProUpdateF): the tensor element, and the update's
+// operands, of each element of one B unit (same element mapping as load_b_unit).  Every
+// load is issued unconditionally from a clamped index (element 0 / row 0 when outside the
+// tensor) so that the loads of a k-tile stay in flight together; upd_b_unit zeroes the
+// elements outside the tensor when the tile is written to LDS.
+template <class C, int G, bool TL>
+__device__ __forceinline__ void load_b_unit_clamped(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
+                                                    int kb, int klim, int koff, C (&v)[G]) {
 #pragma unroll
   for (int e = 0; e < G; ++e) {
     const int k = kb + e;
-    const int row = rev ? g.n - 1 - k : koff + k;
+    const int row = koff + k;
     const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
     const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
-    if (ok) v[e] = pro(j, v[e]);
+    v[e] = U[ok ? j : 0];
+  }
+}
+
+template <class C, int G, bool TL, class Pro>
+__device__ __forceinline__ void pre_b_unit(const Geo& g, const Pro& pro, uint32_t a, uint32_t b, int kb, int klim,
+                                           int koff, typename Pro::Pre (&p)[G]) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const int k = kb + e;
+    const int row = koff + k;
+    const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
+    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
+    p[e] = pro.load(ok ? j : 0, ok ? row : 0);
+  }
+}
+
+template <class C, int G, bool TL, class Pro>
+__device__ __forceinline__ void upd_b_unit(const Geo& g, const Pro& pro, uint32_t a, uint32_t b, int kb, int klim,
+                                           int koff, const zc& Eo, const typename Pro::Pre (&p)[G], bool write,
+                                           C (&v)[G]) {
+  const bool colok = TL ? a < g.A : b < g.B;
+#pragma unroll
+  for (int e = 0; e < G; ++e) v[e] = (colok && kb + e < klim) ? pro.update(Eo, v[e], p[e]) : C{0, 0};
+  if (!write) return;
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const int row = koff + kb + e;
+    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
+    if (colok && kb + e < klim) pro.save(j, v[e]);
   }
 }
 
@@ -719,6 +810,12 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
 
   fragT ra[NB][AIT];
   C rb[NR][BIT][G];
+  // update prologue (ProUpdateF, backward split products only): operands loaded with the
+  // tile, and the per-unit factor of the other axes (a unit keeps its column for all k)
+  constexpr bool UPD = Pro::kUpdate;
+  static_assert(!UPD || SP == kSplitBwd, "the update prologue runs on backward even/odd products");
+  typename Pro::Pre rp[UPD ? NR : 1][UPD ? BIT : 1][G];
+  zc eo[UPD ? BIT : 1];
 
   auto unit_b = [&](int u, int& row, int& kq) {
     if (TL) {
@@ -756,6 +853,11 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         } else if (SP == kSplitFwd) {
           load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
           load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+        } else if constexpr (UPD) {
+          load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.me, 0, rb[0][it]);
+          load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.mo, g.me, rb[NR - 1][it]);
+          pre_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, rp[0][it]);
+          pre_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, rp[NR - 1][it]);
         } else {
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
@@ -808,6 +910,11 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
           }
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, v);
         } else {
+          if constexpr (UPD) {
+            // the first row tile writes the updated state; every row tile contracts it
+            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rb[0][it]);
+            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rb[NR - 1][it]);
+          }
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, rb[0][it]);
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB + 1, row, kq, rb[NR - 1][it]);
         }
@@ -856,6 +963,19 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
     }
   };
 
+  if constexpr (UPD) {
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+      const int u = tid + it * T::THREADS;
+      eo[it] = zc{0.0, 0.0};
+      if (BU % T::THREADS == 0 || u < BU) {
+        int row, kq;
+        unit_b(u, row, kq);
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        if (TL ? a < g.A : b < g.B) eo[it] = pro.col(a, b);
+      }
+    }
+  }
   const int KT = (K + TK - 1) / TK;
   gload(0);
   sstore(0, 0);

@@ -11,7 +11,9 @@ namespace fcgle {
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
 
 // Pointwise map applied to the input of a mode product while its tile is loaded.
-enum class ProKind : int { Id = 0, Nonlin = 1 };
+//  Update: the exponential-Euler update uhat_out = E uhat + tau P1 v of the input v (the
+//  transformed nonlinearity), contracted and also stored (first backward even/odd product).
+enum class ProKind : int { Id = 0, Nonlin = 1, Update = 2 };
 // What the last stage of a mode product does with each output element.
 enum class EpiKind : int {
   Store = 0,     // out[j] = v
@@ -22,17 +24,6 @@ enum class EpiKind : int {
   ExpEulerRec = 5,  // as ExpEuler, and X[j] = uhat_new[j] - tau P2[j] v  (adjoint recompute;
                     //   streaming pass only)
   Count = 6
-};
-
-// g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with e = eu u + ep up;
-// output = cu u + cp up + cg g.
-struct ProParams {
-  const void* up = nullptr;
-  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
-  double sc[4] = {0, 0, 0, 0};
-  int ns = 0;
-  double gamma = 0, kappa = 0, zeta = 0;
-  double eu = 1, ep = 0, cu = 0, cp = 0, cg = 1;
 };
 
 // Separable per-axis complex factors (FP64): value(j) = prod_mu fac[mu][j_mu].
@@ -47,6 +38,23 @@ struct SepParams {
   const double* lam[4] = {nullptr, nullptr, nullptr, nullptr}; // eigenvalues (adjoint)
   const void* other_last = nullptr;   // double2[N / n_{d-1}]
   const void* other_first = nullptr;  // double2[N / n_0]
+};
+
+// Nonlin: g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with
+// e = eu u + ep up; output = cu u + cp up + cg g.
+// Update: uhat_out[j] = E_j uhat[j] + tau F[j] v[j] (E from sep, F = the phi_1 grid).
+struct ProParams {
+  const void* up = nullptr;
+  const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
+  double sc[4] = {0, 0, 0, 0};
+  int ns = 0;
+  double gamma = 0, kappa = 0, zeta = 0;
+  double eu = 1, ep = 0, cu = 0, cp = 0, cg = 1;
+  const void* uhat = nullptr;
+  const void* F = nullptr;
+  void* uhat_out = nullptr;
+  SepParams sep;
+  double tau = 0;
 };
 
 struct EpiParams {
@@ -86,7 +94,8 @@ int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
 // True when the even/odd split kernels exist for the precision.
 bool split_supported(int prec);
 
-// True when the fused kernel exists for this (loader, prologue, epilogue) combination.
+// True when the fused kernel exists for this (loader, prologue, epilogue) combination
+// (ProKind::Update: backward even/odd FP64 / FP32 products with the N loader only).
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek);
 
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s);

@@ -4,6 +4,7 @@
 namespace fcgle {
 
 struct F32K {
+  static constexpr bool kUpdate = true;  // ProUpdateF instantiated
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {

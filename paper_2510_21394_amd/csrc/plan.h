@@ -96,6 +96,7 @@ struct fcgle_plan {
   std::vector<fcgle::SepBuf> seps;
   void* s[3] = {nullptr, nullptr, nullptr};  // scratch tensors
   void* uhat = nullptr;
+  void* uhat2 = nullptr;  // second eigenspace state (update prologue writes here, then swapped)
   bool uhat_valid = false;
   const void* uhat_src = nullptr;
   void* uprev = nullptr;
@@ -105,6 +106,7 @@ struct fcgle_plan {
   double rate[4] = {0, 0, 0, 0};
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
   int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd], for the active structure
+  int cfg_upd = -1;  // tiles of the axis-0 backward product with the update prologue (-1: cfg[0][0])
   // even/odd split of the mode products (persymmetric D): block sizes, leading dimension and
   // the stacked block matrices [Fe; Fo] (forward) and [Be; Bo] (backward)
   bool split = false;
@@ -112,7 +114,9 @@ struct fcgle_plan {
   void* Mfs[4] = {nullptr, nullptr, nullptr, nullptr};
   void* Mbs[4] = {nullptr, nullptr, nullptr, nullptr};
   bool tuned = false;
-  int fusion = 3;  // bit 0: prologue, bit 1: epilogue
+  // bit 0: nonlinearity prologue, bit 1: epilogue of the last forward product, bit 3:
+  // exponential-Euler update in the prologue of the first backward product (when supported)
+  int fusion = 3;
   bool fwd_rev = false;  // forward operators run their mode products from axis d to axis 1
   int* dflag = nullptr;
   // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled

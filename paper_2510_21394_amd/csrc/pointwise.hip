@@ -143,6 +143,7 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
 }  // namespace
 
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek) {
+  if (pk == ProKind::Update) return !tloader && ek == EpiKind::Store;
   if (pk != ProKind::Id) return ek == EpiKind::Store;
   if (!tloader) return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler;
   return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler ||

@@ -178,11 +178,14 @@ class Plan:
     def set_tiles(self, axis: int, fwd: bool, cfg: int):
         L.check(self.lib.fcgle_set_tiles(self.handle, int(axis), int(bool(fwd)), int(cfg)))
 
-    def set_fusion(self, prologue: bool = True, epilogue: bool = True, reverse: bool = False):
+    def set_fusion(self, prologue: bool = True, epilogue: bool = True, reverse: bool = False,
+                   update_in_backward: bool = False):
         """Fuse the nonlinearity into the first / the pointwise epilogue into the last mode
-        product; reverse: run forward operators from the last axis to the first."""
+        product; reverse: run forward operators from the last axis to the first;
+        update_in_backward: apply the exponential-Euler update in the loads of the first
+        backward product instead (even/odd fp64 / fp32 plans, d >= 2)."""
         L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)
-                                          | (4 if reverse else 0)))
+                                          | (4 if reverse else 0) | (8 if update_in_backward else 0)))
 
     def set_structure(self, split: bool):
         """True: even/odd half-size mode products (default for fp64/fp32); False: dense."""
@@ -269,19 +272,19 @@ class BatchPlan:
 
 def decode_signature(sig: int) -> dict:
     """Inverse of the kernel signature of fcgle_timing_read."""
-    structure = sig // 1024
-    sig %= 1024
+    structure = sig // 2048
+    sig %= 2048
     ek = sig % 8
     sig //= 8
-    pk = sig % 2
-    sig //= 2
+    pk = sig % 4
+    sig //= 4
     tl = sig % 2
     sig //= 2
     cfg = sig % 8
     prec = sig // 8
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
             "structure": ["dense", "even_odd_fwd", "even_odd_bwd"][structure],
-            "prologue": ["none", "nonlinearity"][pk],
+            "prologue": ["none", "nonlinearity", "exp_euler_update", "?"][pk],
             "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "?", "?"][ek]}
 
 

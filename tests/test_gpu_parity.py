@@ -241,7 +241,8 @@ def test_timing_counts_mode_products(F):
 
 
 @pytest.mark.parametrize("fusion", [(False, False, False), (True, False, False), (False, True, False),
-                                    (True, True, True), (False, False, True), (True, False, True)])
+                                    (True, True, True), (False, False, True), (True, False, True),
+                                    (True, True, False, True), (False, False, True, True)])
 @pytest.mark.parametrize("scheme", ["exp_euler", "lbdf2", "lawson"])
 def test_unfused_paths_match_oracle(F, fusion, scheme):
     n = (22, 35, 19)
@@ -323,3 +324,80 @@ def test_autotuned_exp_euler_matches_oracle(F):
         plan.run("exp_euler", u, 0.0, steps)
         print(plan.describe())
         assert O.rel_l2(_host(u), ref) <= tol
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("n", [(150, 21, 26), (37, 30, 19), (131, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_update_in_backward_prologue(F, prec, cfg, n):
+    """Exponential-Euler update applied by the first backward product while it loads its tile
+    (fusion bit 3), in every tile configuration of that product: odd and even axis lengths,
+    ragged column tiles, and two row tiles per column (n0 = 150 and 131 with 64-row tiles), where
+    only the first row tile stores the new state.  Against the oracle trajectory, and the timing
+    record shows the update prologue on the axis-0 backward product."""
+    alpha, h = _setup(n, 31)
+    params = (0.9, -0.4, 0.8, 1.1, 0.6)
+    tau, steps = 2e-3, 6
+    U0 = 1.5 * sech_product(grid_axes(n, ((-9.0, 9.0),) * len(n)), [0.7] + [0.2] * (len(n) - 1), 0.3)
+    ref = O.run(O.Problem(n, alpha, h, params), "exp_euler", U0, tau, steps)
+    plan = F.Plan(n, alpha, h, params, tau=tau, precision=prec)
+    plan.set_fusion(True, True, False, update_in_backward=True)
+    plan.set_tiles(0, 0, cfg)
+    desc = plan.describe()
+    assert "update=backward-prologue" in desc and "unsupported" not in desc
+    u = _dev(U0, prec)
+    plan.step("exp_euler", u, 0.0)
+    plan.timing_enable(64)
+    plan.run("exp_euler", u, tau, steps - 1)
+    rec = plan.timing_read()
+    err = O.rel_l2(_host(u), ref)
+    print(f"[update prologue {prec} cfg{cfg} {n}] rel_l2 = {err:.3e}")
+    assert err <= TOL_OP[prec]
+    pro = {F.fcgle.decode_signature(r[2])["prologue"] for r in rec if r[0] == 0 and r[1] == 0}
+    assert pro == {"exp_euler_update"}
+    epi = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[1] == 1}
+    assert epi == {"store"}
+    plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_update_modes_interleave(F, prec):
+    """Switching between the update in the backward prologue (which alternates the two
+    eigenspace buffers) and the fused epilogue in the middle of a trajectory keeps the state."""
+    n = (40, 33, 28)
+    alpha, h = _setup(n, 41)
+    params = BASE_PARAMS
+    tau = 2e-3
+    U0 = sech_product(grid_axes(n, ((-8.0, 8.0),) * 3), [1.0, 0.0, 0.0])
+    ref = O.run(O.Problem(n, alpha, h, params), "exp_euler", U0, tau, 9)
+    plan = F.Plan(n, alpha, h, params, tau=tau, precision=prec)
+    u = _dev(U0, prec)
+    t = 0.0
+    for k, upd in enumerate([True, True, True, False, False, True, False, True, True]):
+        plan.set_fusion(True, True, k % 2 == 1, update_in_backward=upd)
+        plan.step("exp_euler", u, t)
+        t += tau
+    err = O.rel_l2(_host(u), ref)
+    print(f"[interleaved update modes {prec}] rel_l2 = {err:.3e}")
+    assert err <= TOL_OP[prec]
+    plan.close()
+
+
+def test_update_in_backward_ignored_where_unsupported(F):
+    """1-D plans (no N-loader backward product) and dense / split-BF16 plans keep the
+    epilogue form when bit 3 is set; results still match the oracle."""
+    cases = [((300,), "fp64", True), ((24, 30), "fp32", False), ((24, 30), "bf16x6", True)]
+    for n, prec, split in cases:
+        alpha, h = _setup(n, 51)
+        tau = 2e-3
+        U0 = random_complex(n, 52) * 0.3
+        ref = O.run(O.Problem(n, alpha, h, BASE_PARAMS), "exp_euler", U0, tau, 4)
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=tau, precision=prec)
+        plan.set_structure(split)
+        plan.set_fusion(True, True, False, update_in_backward=True)
+        assert "unsupported" in plan.describe()
+        u = _dev(U0, prec)
+        plan.run("exp_euler", u, 0.0, 4)
+        tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16x6": 1e-5}[prec]
+        assert O.rel_l2(_host(u), ref) <= tol
+        plan.close()
