@@ -137,6 +137,22 @@ int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const voi
 int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, void* out_dev,
                   void* stream);
 
+/* The inverse of the linearly implicit steps, x = (I - theta (nu + i eta) K)^{-1} v (Section 3,
+ * the resolvent R = 1/(1 - z) on the eigenvalue grid), refined to FP64 accuracy for plans of
+ * any precision by classical iterative refinement: x_0 = R o v is formed with the plan's
+ * precision (Q^T, the R-grid, Q); then `sweeps` times the residual
+ * r = v - (I - theta (nu + i eta) K) x is formed in FP64 with FP64 MFMA mode products by the
+ * Toeplitz matrices D_mu themselves (K u = sum_mu (nu + i eta) U x_mu D_mu, eq. kronsumv), and
+ * x += R o r again with the plan's precision.
+ * v_dev, x_dev: complex128 device tensors of N elements in C order, not aliased; v is read
+ * only.  sweeps: 0..8.  rnorm (host, optional): sweeps + 1 values
+ * ||v - (I - theta (nu + i eta) K) x_k||_2 / ||v||_2, k = 0..sweeps, from FP64 wavefront
+ * reductions (one more residual; the call then synchronises the stream).  The first call
+ * uploads D_mu in FP64 (npad^2 doubles per axis) and allocates two N-element work tensors.
+ * Errors: ERR_ARG, ERR_NOMEM, ERR_HIP. */
+int fcgle_apply_inv_refined(fcgle_plan* plan, double theta, const void* v_dev, void* x_dev, int sweeps,
+                            double* rnorm, void* stream);
+
 /* Forget the cached eigenspace state and the LBDF2 history, then (if u_prev_dev
  * is not NULL) record u_prev_dev as u_{n-1} for the next FCGLE_LBDF2 step on
  * u_dev.  Call it whenever the caller writes u_dev between steps.  Errors: ERR_ARG. */

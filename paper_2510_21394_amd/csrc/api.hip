@@ -594,6 +594,10 @@ void free_plan(fcgle_plan* P) {
     f(e.other_first);
   }
   for (int k = 0; k < 3; ++k) f(P->s[k]);
+  for (int m = 0; m < 4; ++m) f(P->Md[m]);
+  f(P->rf_r);
+  f(P->rf_y);
+  f(P->rf_part);
   f(P->uhat);
   f(P->uhat2);
   f(P->uprev);
@@ -603,6 +607,66 @@ void free_plan(fcgle_plan* P) {
   for (void* q : P->traj_x) f(q);
   f(P->partial);
   for (auto e : P->ev_pool) (void)hipEventDestroy(e);
+}
+
+// --- refinement sweep of the inverse ------------------------------------------------
+
+int ensure_refine(fcgle_plan* P) {
+  if (!P->Md[0]) {
+    for (int m = 0; m < P->d; ++m) {
+      // D_mu = -h^{-alpha} Toep(g), g the fractional centred-difference weights
+      const int64_t n = P->n[m], np = P->npad[m];
+      const std::vector<double> g = fd_weights(P->alpha[m], n, P->fd_order);
+      const double scale = -std::pow(P->h[m], -P->alpha[m]);
+      std::vector<double> buf(np * np, 0.0);
+      for (int64_t i = 0; i < n; ++i)
+        for (int64_t k = 0; k < n; ++k) buf[i * np + k] = scale * g[i > k ? i - k : k - i];
+      FC_TRY(plan_alloc(&P->Md[m], buf.size() * sizeof(double)));
+      HIP_TRY(hipMemcpy(P->Md[m], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+  }
+  if (!P->rf_r) FC_TRY(plan_alloc(&P->rf_r, (size_t)P->N * 16));
+  if (!P->rf_y) FC_TRY(plan_alloc(&P->rf_y, (size_t)P->N * P->elem));
+  if (!P->rf_part) FC_TRY(plan_alloc((void**)&P->rf_part, (size_t)(rf_norm_parts() + 16) * sizeof(double)));
+  return FCGLE_OK;
+}
+
+// rf_r = v - (I - theta (nu + i eta) K) x = v - x + theta (nu + i eta) sum_mu D_mu x_mu x, all in FP64
+// (dense FP64 MFMA products with the Toeplitz D_mu accumulating into rf_r).
+int refine_residual(fcgle_plan* P, double theta, const void* v, const void* x, hipStream_t st) {
+  HIP_TRY(launch_rf_sub(P->N, v, x, P->rf_r, st));
+  for (int mu = 0; mu < P->d; ++mu) {
+    MPLaunch L;
+    L.prec = P_F64;
+    L.cfg = default_cfg(P_F64, P->n[mu], false);
+    int64_t A = 1, B = 1;
+    for (int m = 0; m < mu; ++m) A *= P->n[m];
+    for (int m = mu + 1; m < P->d; ++m) B *= P->n[m];
+    L.A = A;
+    L.B = B;
+    L.n = (int)P->n[mu];
+    L.npad = P->npad[mu];
+    L.M = P->Md[mu];
+    L.in = x;
+    L.ek = EpiKind::Axpy;
+    L.ep.out = P->rf_r;
+    L.ep.cre = theta * P->p.nu;
+    L.ep.cim = theta * P->p.eta;
+    HIP_TRY(launch_mode_product(L, st));
+  }
+  return FCGLE_OK;
+}
+
+// rf_y <- R o rf_y = (I - theta (nu + i eta) K)^{-1} rf_y with the plan's precision
+int refine_inverse(fcgle_plan* P, double theta, hipStream_t st) {
+  EpiParams ep;
+  ep.out = P->s[2];
+  FC_TRY(get_grid(P, FCGLE_INV, theta, st, &ep.F));
+  FC_TRY(tucker(P, true, P->rf_y, ProKind::Id, ProParams(), EpiKind::Grid, ep, P->s[0], P->s[1], st));
+  EpiParams eb;
+  eb.out = P->rf_y;
+  FC_TRY(tucker(P, false, P->s[2], ProKind::Id, ProParams(), EpiKind::Store, eb, P->s[0], P->s[1], st));
+  return FCGLE_OK;
 }
 
 }  // namespace
@@ -792,6 +856,44 @@ int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, v
   eb.out = out_dev;
   FC_TRY(tucker(plan, false, plan->s[2], ProKind::Id, ProParams(), EpiKind::Store, eb, plan->s[0], plan->s[1], st));
   if (out_dev == plan->uhat_src) plan->uhat_valid = false;
+  return FCGLE_OK;
+}
+
+int fcgle_apply_inv_refined(fcgle_plan* plan, double theta, const void* v_dev, void* x_dev, int sweeps,
+                            double* rnorm, void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!v_dev || !x_dev) return fail(FCGLE_ERR_ARG, "NULL tensor");
+  if (v_dev == x_dev) return fail(FCGLE_ERR_ARG, "apply_inv_refined: x must not alias v");
+  if (sweeps < 0 || sweeps > 8) return fail(FCGLE_ERR_ARG, "apply_inv_refined: sweeps must be 0..8");
+  if (!std::isfinite(theta)) return fail(FCGLE_ERR_ARG, "theta not finite");
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  FC_TRY(ensure_refine(plan));
+  const int pr = precision_of(plan);
+  const int parts = rf_norm_parts();
+  double* nrm = plan->rf_part + parts;  // [0] = |v|^2, [1 + k] = |r_k|^2
+  if (rnorm) HIP_TRY(launch_rf_norm2(plan->N, v_dev, plan->rf_part, nrm, st));
+  // x_0 = R o v in the plan's precision
+  HIP_TRY(launch_rf_to_state(pr, plan->N, v_dev, plan->rf_y, st));
+  FC_TRY(refine_inverse(plan, theta, st));
+  HIP_TRY(launch_rf_set(pr, plan->N, x_dev, plan->rf_y, st));
+  for (int k = 0; k <= sweeps; ++k) {
+    if (k == sweeps && !rnorm) break;
+    FC_TRY(refine_residual(plan, theta, v_dev, x_dev, st));
+    if (rnorm) HIP_TRY(launch_rf_norm2(plan->N, plan->rf_r, plan->rf_part, nrm + 1 + k, st));
+    if (k == sweeps) break;
+    HIP_TRY(launch_rf_to_state(pr, plan->N, plan->rf_r, plan->rf_y, st));
+    FC_TRY(refine_inverse(plan, theta, st));
+    HIP_TRY(launch_rf_add(pr, plan->N, x_dev, plan->rf_y, st));
+  }
+  if (rnorm) {
+    double h[10];
+    HIP_TRY(hipMemcpyAsync(h, nrm, (size_t)(sweeps + 2) * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double vn = std::sqrt(h[0]);
+    for (int k = 0; k <= sweeps; ++k) rnorm[k] = vn > 0.0 ? std::sqrt(h[1 + k]) / vn : std::sqrt(h[1 + k]);
+  }
+  if (x_dev == plan->uhat_src) plan->uhat_valid = false;
   return FCGLE_OK;
 }
 

@@ -45,6 +45,10 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
       case EpiKind::ExpEuler:
         if constexpr (SP != kSplitBwd) return K::template go<T, false, SP, ProIdF, EpiExpEulerF<R>>(L, s);
         return hipErrorInvalidValue;
+      case EpiKind::Axpy:
+        if constexpr (SP == kDense && std::is_same<R, double>::value)
+          return K::template go<T, false, SP, ProIdF, EpiAxpyF<R>>(L, s);
+        return hipErrorInvalidValue;
       default:
         return hipErrorInvalidValue;
     }
@@ -68,6 +72,10 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
       return hipErrorInvalidValue;
     case EpiKind::KeepOld:
       if constexpr (SP != kSplitFwd) return K::template go<T, true, SP, ProIdF, EpiKeepOldF<R>>(L, s);
+      return hipErrorInvalidValue;
+    case EpiKind::Axpy:
+      if constexpr (SP == kDense && std::is_same<R, double>::value)
+        return K::template go<T, true, SP, ProIdF, EpiAxpyF<R>>(L, s);
       return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;

@@ -392,6 +392,34 @@ struct EpiKeepOldF {
   FCGLE_EPI_APPLY
 };
 
+// out[j] += c v with a complex coefficient c (the FP64 residual r += theta (nu + i eta) D_mu x_mu
+// of the refinement sweep): each output element is read and written by the one thread that
+// computes it.
+template <class R>
+struct EpiAxpyF {
+  using C = typename Cx<R>::T;
+  using Ctx = NoCtx;
+  using Pre = C;
+  C* out;
+  R cre, cim;
+  EpiAxpyF() = default;
+  explicit EpiAxpyF(const EpiParams& p) : out((C*)p.out), cre((R)p.cre), cim((R)p.cim) {}
+  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
+  template <int V>
+  __device__ __forceinline__ void load(const int*, const int64_t* j, const bool* ok, Pre* old) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v) old[v] = ok[v] ? out[j[v]] : C{0, 0};
+  }
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im, const Pre* old) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = mkc<C>(old[v].x + (cre * re[v] - cim * im[v]), old[v].y + (cre * im[v] + cim * re[v]));
+  }
+  FCGLE_EPI_APPLY
+};
+
 #undef FCGLE_EPI_APPLY
 
 // Exponential-Euler update applied while the first backward product loads its input

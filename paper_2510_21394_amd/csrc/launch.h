@@ -23,7 +23,9 @@ enum class EpiKind : int {
   KeepOld = 4,   // save[j] = out[j]; out[j] = v           (LBDF2 history)
   ExpEulerRec = 5,  // as ExpEuler, and X[j] = uhat_new[j] - tau P2[j] v  (adjoint recompute;
                     //   streaming pass only)
-  Count = 6
+  Axpy = 6,         // out[j] += c v, c complex            (FP64 residual of the refinement sweep;
+                    //   dense FP64 products only)
+  Count = 7
 };
 
 // Separable per-axis complex factors (FP64): value(j) = prod_mu fac[mu][j_mu].
@@ -66,6 +68,7 @@ struct EpiParams {
   void* ghat_out = nullptr;  // ExpEuler: optional copy of the transformed nonlinearity
   const void* F2 = nullptr;  // ExpEulerRec: phi_2 grid
   void* out2 = nullptr;      // ExpEulerRec: X
+  double cre = 0, cim = 0;   // Axpy: c
 };
 
 // One mode product out[a, i, b] = sum_k M[i, k] in[a, k, b] on a complex tensor
@@ -151,6 +154,16 @@ hipError_t launch_adj_phys(int prec, int64_t N, int nlast, void* wq, const void*
 // partial[r][0] += Re S, partial[r][1] += -Im S   (E, ell from the separable factors / eigenvalues)
 hipError_t launch_adj_hat(int prec, int64_t N, int nlast, const void* v, void* ahat, void* p, const void* X,
                           const void* P1, const SepParams& sep, double tau, double* partial, hipStream_t s);
+
+// Refinement sweep of the inverse (refine.hip).  v, x, r: complex128 tensors of N elements;
+// y: the state type of `prec` (complex64, or complex128 for FP64).
+hipError_t launch_rf_sub(int64_t N, const void* v, const void* x, void* r, hipStream_t s);  // r = v - x
+hipError_t launch_rf_to_state(int prec, int64_t N, const void* r, void* y, hipStream_t s);  // y = (state) r
+hipError_t launch_rf_set(int prec, int64_t N, void* x, const void* y, hipStream_t s);       // x = y
+hipError_t launch_rf_add(int prec, int64_t N, void* x, const void* y, hipStream_t s);       // x += y
+// out[0] = sum |r_j|^2 in FP64; partial holds rf_norm_parts() doubles of scratch.
+int rf_norm_parts();
+hipError_t launch_rf_norm2(int64_t N, const void* r, double* partial, double* out, hipStream_t s);
 
 // Sums `count` per-block partial rows of width `width` into acc[width] (acc += sum).
 hipError_t launch_reduce_partials(const double* partial, int64_t count, int width, double* acc,

@@ -119,6 +119,12 @@ struct fcgle_plan {
   int fusion = 3;
   bool fwd_rev = false;  // forward operators run their mode products from axis d to axis 1
   int* dflag = nullptr;
+  // refinement sweep of the inverse (allocated on first use): FP64 Toeplitz D_mu (npad x npad),
+  // the FP64 residual, a state-type work tensor, and norm partials + results
+  void* Md[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* rf_r = nullptr;
+  void* rf_y = nullptr;
+  double* rf_part = nullptr;
   // adjoint work buffers (allocated on first use): eigenspace adjoint state, its P1-scaled
   // copy, the forward-transformed adjoint source, and the recomputed segment (u_k, X_k)
   void* adj[3] = {nullptr, nullptr, nullptr};

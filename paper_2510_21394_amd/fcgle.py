@@ -101,6 +101,23 @@ class Plan:
         L.check(self.lib.fcgle_apply_f(self.handle, L.KINDS[kind], float(theta), _ptr(u), _ptr(out), _stream()))
         return out
 
+    def apply_inv_refined(self, theta: float, v: torch.Tensor, sweeps: int = 1,
+                          out: Optional[torch.Tensor] = None, residuals: bool = False):
+        """x = (I - theta (nu + i eta) K)^{-1} v to FP64 accuracy: the plan's precision for the
+        inverse, `sweeps` refinement sweeps with the residual formed in FP64 (fcgle_apply_inv_refined).
+        v and out are complex128 tensors of the plan's shape.  With residuals=True also returns the
+        relative residual norms ||v - (I - theta (nu + i eta) K) x_k|| / ||v||, k = 0..sweeps."""
+        for t, name in ((v, "v"),) + (((out, "out"),) if out is not None else ()):
+            if t.dtype != torch.complex128 or t.device != self.device or tuple(t.shape) != self.n \
+                    or not t.is_contiguous():
+                raise ValueError(f"{name} must be a contiguous complex128 tensor of shape {self.n} on {self.device}")
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.complex128, device=self.device)
+        rn = (ctypes.c_double * (sweeps + 1))() if residuals else None
+        L.check(self.lib.fcgle_apply_inv_refined(self.handle, float(theta), _ptr(v), _ptr(out), int(sweeps),
+                                                 ctypes.cast(rn, L.P_dbl) if rn is not None else None, _stream()))
+        return (out, list(rn)) if residuals else out
+
     def set_source(self, rates: Sequence[float], tensors: Sequence[torch.Tensor]):
         for S in tensors:
             self._check_tensor(S, "S")
