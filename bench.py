@@ -276,6 +276,39 @@ def adjoint_timing():
     return res
 
 
+def refine_timing(w, U0, reps=5):
+    """Context: the inverse (I - tau (nu + i eta) K)^{-1} v on the 256^3 workload (v = u0, complex128):
+    FP32 MFMA inverse + 2 FP64-residual refinement sweeps vs the FP64 MFMA inverse; wall time
+    per call and the relative L2 difference of the two results."""
+    import torch
+    from paper_2510_21394_amd import Plan
+    v = torch.from_numpy(U0).cuda()
+    out = {"workload": w.name, "theta": w.tau, "sweeps": 2}
+    p32 = Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision="fp32")
+    x32, rn = p32.apply_inv_refined(w.tau, v, sweeps=2, residuals=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p32.apply_inv_refined(w.tau, v, sweeps=2, out=x32)
+    torch.cuda.synchronize()
+    out["fp32_refined_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+    out["relative_residuals"] = rn
+    p32.close()
+    p64 = Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision="fp64")
+    x64 = p64.apply_f("inv", w.tau, v)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        p64.apply_f("inv", w.tau, v, x64)
+    torch.cuda.synchronize()
+    out["fp64_ms"] = 1e3 * (time.perf_counter() - t0) / reps
+    out["rel_l2_refined_vs_fp64"] = float(torch.linalg.vector_norm(x32 - x64) / torch.linalg.vector_norm(x64))
+    p64.close()
+    del v, x32, x64
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
     """The FP64 oracle as it stands, timed on the host cores (bounded sample of the workload)."""
     from oracle import fcgle_oracle as O
@@ -359,7 +392,7 @@ def main():
         "kernels": head["kernels"],
     }
     if not a.no_extras:
-        line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing()}
+        line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing(), "refine": refine_timing(w, U0)}
         print(f"# batch: {line['context']['batch']['steps_per_s']:.1f} steps/s; adjoint backward/forward = "
               f"{line['context']['adjoint']['backward_over_forward']:.2f}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
