@@ -332,7 +332,7 @@ def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "one GPU only: multi-GPU execution is not implemented",
                           "n_gpus": a.gpus}))
         sys.exit(2)
     import torch

@@ -50,7 +50,7 @@ typedef struct {
 typedef enum {
   FCGLE_OK = 0,
   FCGLE_ERR_ARG = -1,         /* invalid argument (sizes, orders, NULL, tau mismatch ...) */
-  FCGLE_ERR_UNSUPPORTED = -2, /* valid request this build does not implement            */
+  FCGLE_ERR_UNSUPPORTED = -2, /* valid request that is not implemented                  */
   FCGLE_ERR_NOMEM = -3,       /* device or host allocation failed                       */
   FCGLE_ERR_HIP = -4,         /* a HIP runtime call failed                              */
   FCGLE_ERR_NONFINITE = -5,   /* NaN/Inf found by fcgle_check_finite                    */
