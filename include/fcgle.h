@@ -213,10 +213,12 @@ int fcgle_check_finite(fcgle_plan* plan, const void* u_dev, void* stream);
 int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
 
 /* Time every candidate tile configuration of each mode product on `stream`
- * (scratch inputs, `reps` launches each) and keep the fastest per axis and
- * direction, and whether the pointwise prologue/epilogue are fused or streamed.
- * For a batch plan: the same per grouped phase over all instances.  Overwrites the
- * plan's scratch and cached eigenspace state.  Synchronous.  Errors: ERR_HIP. */
+ * (scratch inputs, max(3 reps, 10) launches each) and keep the fastest per axis and
+ * direction; then time whole exponential-Euler steps (as many) for every placement of
+ * the nonlinearity and of the update (fcgle_set_fusion) and keep the fastest.
+ * For a batch plan: the same per grouped phase over all instances (`reps` launches).
+ * Overwrites the plan's scratch and cached eigenspace state.  Synchronous.
+ * Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
 /* Choose the tile configuration (0..4; rows x columns per tile depend on the precision and

@@ -988,7 +988,7 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
         L.in = plan->s[0];
         L.ep.out = plan->s[1];
         float ms;
-        FC_TRY(time_ms(st, e0, e1, reps, [&] { return launch_mode_product(L, st); }, &ms));
+        FC_TRY(time_ms(st, e0, e1, reps * 3 > 10 ? reps * 3 : 10, [&] { return launch_mode_product(L, st); }, &ms));
         if (ms < best) {
           best = ms;
           best_c = c;
@@ -1010,6 +1010,8 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
   // configuration again (its loads differ from the plain product's)
   static const int kFusions[] = {0, 1, 2, 3, 8, 9};
   const int nfus = update_prologue_ok(plan) ? 6 : 4;
+  // whole steps differ by a few percent between the best choices: time more of them
+  const int reps2 = reps * 3 > 10 ? reps * 3 : 10;
   float best = 1e30f;
   int best_fusion = 3, best_cfg_upd = -1;
   bool best_rev = false;
@@ -1022,7 +1024,7 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
         plan->fusion = fusion;
         plan->cfg_upd = c;
         float ms;
-        FC_TRY(time_ms(st, e0, e1, reps, [&] {
+        FC_TRY(time_ms(st, e0, e1, reps2, [&] {
           const int rc = expeuler_body(plan, plan->uprev, 0.0, st);
           return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
         }, &ms));
