@@ -223,7 +223,10 @@ int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
 /* Choose the tile configuration (0..4; rows x columns per tile depend on the precision and
  * structure, see fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
- * Results do not depend on it beyond rounding order.  Errors: ERR_ARG. */
+ * For a forward product of an even/odd FP64 / FP32 plan, cfg 5..9 selects configuration
+ * cfg - 5 in the form that computes both blocks in one tile (one load of each mirrored pair,
+ * marked F by fcgle_describe).  Results do not depend on it beyond rounding order.
+ * Errors: ERR_ARG, ERR_UNSUPPORTED (cfg >= 5 on another plan). */
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
 
 /* Structure of the mode products.  Every D_mu is symmetric Toeplitz, hence persymmetric
@@ -262,7 +265,8 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
  * its duration, sig[i] = the kernel instantiation it ran:
  *   sig = structure * 2048 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 4 + prologue) * 8 + epilogue
- * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q; prec 0..3 as fcgle_precision;
+ * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q, 3 even/odd Q^T with both blocks per tile;
+ * prec 0..3 as fcgle_precision;
  * t_loader 1 for the fastest axis; prologue 0 none, 1 nonlinearity, 2 exponential-Euler
  * update; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
  * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */

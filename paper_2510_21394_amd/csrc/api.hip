@@ -204,7 +204,7 @@ int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
     tl.e0 = P->ev_pool[2 * P->timed.size()];
     tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
     tl.axis = axis;
-    tl.fwd = L.split ? (L.split == 1 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
+    tl.fwd = L.split ? (L.split != 2 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
     tl.sig = L.split * 2048 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 4 + (int)L.pk) * 8) + (int)L.ek;
     HIP_TRY(hipEventRecord(tl.e0, st));
   }
@@ -227,7 +227,7 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
   L.B = B;
   L.n = (int)P->n[mu];
   if (P->split) {
-    L.split = fwd ? 1 : 2;
+    L.split = fwd ? (P->fwd2[mu] ? 3 : 1) : 2;
     L.me = P->me[mu];
     L.mo = P->mo[mu];
     L.npad = P->ldsp[mu];
@@ -982,19 +982,26 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
     for (int dir = 0; dir < 2; ++dir) {
       float best = 1e30f;
       int best_c = plan->cfg[mu][dir];
-      for (int c = 0; c < kNumCfg; ++c) {
-        MPLaunch L = base_launch(plan, mu, dir == 1);
-        L.cfg = c;
-        L.in = plan->s[0];
-        L.ep.out = plan->s[1];
-        float ms;
-        FC_TRY(time_ms(st, e0, e1, reps * 3 > 10 ? reps * 3 : 10, [&] { return launch_mode_product(L, st); }, &ms));
-        if (ms < best) {
-          best = ms;
-          best_c = c;
+      // forward even/odd products: also the form with both blocks in one tile
+      const int nform = (dir == 1 && plan->split && (pr == P_F64 || pr == P_F32)) ? 2 : 1;
+      bool best_f2 = false;
+      for (int form = 0; form < nform; ++form)
+        for (int c = 0; c < kNumCfg; ++c) {
+          plan->fwd2[mu] = (form == 1);
+          MPLaunch L = base_launch(plan, mu, dir == 1);
+          L.cfg = c;
+          L.in = plan->s[0];
+          L.ep.out = plan->s[1];
+          float ms;
+          FC_TRY(time_ms(st, e0, e1, reps * 3 > 10 ? reps * 3 : 10, [&] { return launch_mode_product(L, st); }, &ms));
+          if (ms < best) {
+            best = ms;
+            best_c = c;
+            best_f2 = (form == 1);
+          }
         }
-      }
       plan->cfg[mu][dir] = best_c;
+      if (dir == 1) plan->fwd2[mu] = best_f2;
     }
   // 2. order of the forward products and where the nonlinearity and the exponential-Euler
   //    update run (fused prologue / epilogue, streaming passes, or the update in the first
@@ -1069,9 +1076,14 @@ extern "C" {
 
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
   FC_TRY(check_plan(plan));
-  if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= kNumCfg)
+  const int pr = precision_of(plan);
+  const bool f2 = fwd == 1 && cfg >= kNumCfg;
+  if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= (fwd ? 2 * kNumCfg : kNumCfg))
     return fail(FCGLE_ERR_ARG, "set_tiles: bad argument");
-  plan->cfg[axis][fwd] = cfg;
+  if (f2 && !(plan->split && (pr == P_F64 || pr == P_F32)))
+    return fail(FCGLE_ERR_UNSUPPORTED, "set_tiles: fused forward tiles need an even/odd FP64 / FP32 plan");
+  if (fwd == 1) plan->fwd2[axis] = f2;
+  plan->cfg[axis][fwd] = f2 ? cfg - kNumCfg : cfg;
   if (axis == 0 && fwd == 0) plan->cfg_upd = -1;  // the update-prologue product follows it again
   return FCGLE_OK;
 }
@@ -1083,8 +1095,10 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
     return fail(FCGLE_ERR_UNSUPPORTED, "set_structure: no even/odd kernels for this precision");
   if ((bool)split != plan->split) {
     plan->split = (split != 0);
-    for (int m = 0; m < plan->d; ++m)
+    for (int m = 0; m < plan->d; ++m) {
       plan->cfg[m][0] = plan->cfg[m][1] = default_cfg(precision_of(plan), plan->n[m], plan->split);
+      plan->fwd2[m] = false;
+    }
     plan->cfg_upd = -1;
     plan->tuned = false;
   }
@@ -1111,7 +1125,8 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   const int sp = plan->split ? 1 : 0;
   for (int m = 0; m < plan->d; ++m) {
     s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0], sp)) +
-         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1], sp)) + "]";
+         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1], sp)) +
+         (plan->split && plan->fwd2[m] ? "F" : "") + "]";
   }
   s += plan->split ? " structure=even-odd" : " structure=dense";
   s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");

@@ -71,7 +71,7 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
       if constexpr (SP != kSplitBwd) return K::template go<T, true, SP, ProIdF, EpiExpEulerF<R>>(L, s);
       return hipErrorInvalidValue;
     case EpiKind::KeepOld:
-      if constexpr (SP != kSplitFwd) return K::template go<T, true, SP, ProIdF, EpiKeepOldF<R>>(L, s);
+      if constexpr (SP != kSplitFwd && SP != kSplitFwd2) return K::template go<T, true, SP, ProIdF, EpiKeepOldF<R>>(L, s);
       return hipErrorInvalidValue;
     case EpiKind::Axpy:
       if constexpr (SP == kDense && std::is_same<R, double>::value)
@@ -91,6 +91,8 @@ template <class K, class T>
 hipError_t dispatch_split(const MPLaunch& L, hipStream_t s) {
   if (L.split == kSplitFwd) return dispatch_combo<K, T, kSplitFwd>(L, s);
   if (L.split == kSplitBwd) return dispatch_combo<K, T, kSplitBwd>(L, s);
+  if constexpr (K::kFwd2)
+    if (L.split == kSplitFwd2) return dispatch_combo<K, T, kSplitFwd2>(L, s);
   return hipErrorInvalidValue;
 }
 

@@ -487,7 +487,12 @@ struct TileCfg {
 //             p_i = sum_{k<me} Me[i, k] in[a, k, b], q_i = sum_{k<mo} Mo[i, k] in[a, me+k, b],
 //             then out[a, i, b] = p_i + q_i and, for i < mo, out[a, n-1-i, b] = p_i - q_i.
 // Both split forms do half the multiply-adds of kDense for the same bytes moved.
-enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2 };
+//  kSplitFwd2: Q^T as kSplitFwd, with both blocks in one tile: each workgroup loads the pair
+//             in[a, k, b], in[a, n-1-k, b] once (k < me), forms the sum and the difference,
+//             contracts the sum with Fe and the difference with Fo (two accumulator sets) and
+//             writes rows base 0 and base me; half the loads and prologue work of kSplitFwd
+//             for the same multiply-adds (the odd-n middle difference is exactly zero).
+enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2, kSplitFwd2 = 3 };
 
 struct Geo {
   uint32_t A, B;      // batch (slower) and inner (faster) extents, complex elements
@@ -787,7 +792,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   using acc_t = typename MT::acc_t;
   constexpr int G = MT::G;
   constexpr int TM = T::TM, TNC = T::TNC, TK = T::TK;
-  constexpr int NB = (SP == kSplitBwd) ? 2 : 1;  // operand pairs (even / odd block)
+  constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;  // operand pairs (even / odd block)
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
   constexpr size_t kAsBytes = (size_t)2 * NB * TM * LDK * sizeof(R);
@@ -816,7 +821,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
     row_end = K;
     base = odd ? g.me : 0;
     Ma = M + (odd ? (int64_t)g.npad * g.npad : 0);
-  } else {
+  } else {  // kSplitBwd, kSplitFwd2: both blocks, contraction over the even length
     m0 = mt * TM;
     K = g.me;
     row_end = g.me;
@@ -881,6 +886,9 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         } else if (SP == kSplitFwd) {
           load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
           load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+        } else if (SP == kSplitFwd2) {
+          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
+          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else if constexpr (UPD) {
           load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.me, 0, rb[0][it]);
           load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.mo, g.me, rb[NR - 1][it]);
@@ -937,6 +945,19 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
             v[e].y = rb[0][it][e].y + sg * rb[NR - 1][it][e].y;
           }
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, v);
+        } else if (SP == kSplitFwd2) {
+          pro_b_unit<C, G, TL, Pro>(g, a, b, kb, g.me, 0, false, pro, rb[0][it]);
+          pro_b_unit<C, G, TL, Pro>(g, a, b, kb, g.me, 0, true, pro, rb[NR - 1][it]);
+          C sv[G], dv[G];
+#pragma unroll
+          for (int e = 0; e < G; ++e) {
+            sv[e].x = rb[0][it][e].x + rb[NR - 1][it][e].x;
+            sv[e].y = rb[0][it][e].y + rb[NR - 1][it][e].y;
+            dv[e].x = rb[0][it][e].x - rb[NR - 1][it][e].x;
+            dv[e].y = rb[0][it][e].y - rb[NR - 1][it][e].y;
+          }
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, sv);
+          put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB + 1, row, kq, dv);
         } else {
           if constexpr (UPD) {
             // the first row tile writes the updated state; every row tile contracts it
@@ -1017,7 +1038,15 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   }
 
   auto rowmap = [](int l, int r) { return MT::row(l, r); };
-  if (SP != kSplitBwd) {
+  if (SP == kSplitFwd2) {
+    run_epilogue<R, T, TL>(
+        g, a_fix, c0, m0, g.me, epi, [&](int fm, int fn, int p, int r) { return (R)acc[0][fm][fn][p][r]; },
+        rowmap, [](int i) { return i; }, smem);
+    run_epilogue<R, T, TL>(
+        g, a_fix, c0, g.me + m0, g.me + g.mo, epi,
+        [&](int fm, int fn, int p, int r) { return (R)acc[NB - 1][fm][fn][p][r]; }, rowmap,
+        [](int i) { return i; }, smem);
+  } else if (SP != kSplitBwd) {
     run_epilogue<R, T, TL>(
         g, a_fix, c0, base + m0, base + row_end, epi,
         [&](int fm, int fn, int p, int r) { return (R)acc[0][fm][fn][p][r]; }, rowmap, [](int i) { return i; },
@@ -1362,7 +1391,7 @@ inline Geo make_geo(const MPLaunch& L, bool tl, int /*vec_units*/) {
   if (L.split == kSplitFwd) {
     g.te = (L.me + T::TM - 1) / T::TM;
     g.ntm = g.te + (L.mo + T::TM - 1) / T::TM;
-  } else if (L.split == kSplitBwd) {
+  } else if (L.split == kSplitBwd || L.split == kSplitFwd2) {
     g.te = 0;
     g.ntm = (L.me + T::TM - 1) / T::TM;
   } else {

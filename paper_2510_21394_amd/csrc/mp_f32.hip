@@ -5,6 +5,7 @@ namespace fcgle {
 
 struct F32K {
   static constexpr bool kUpdate = true;  // ProUpdateF instantiated
+  static constexpr bool kFwd2 = true;    // fused even/odd forward tiles instantiated
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {

@@ -107,6 +107,7 @@ struct fcgle_plan {
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
   int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd], for the active structure
   int cfg_upd = -1;  // tiles of the axis-0 backward product with the update prologue (-1: cfg[0][0])
+  bool fwd2[4] = {false, false, false, false};  // forward even/odd products with both blocks per tile
   // even/odd split of the mode products (persymmetric D): block sizes, leading dimension and
   // the stacked block matrices [Fe; Fo] (forward) and [Be; Bo] (backward)
   bool split = false;

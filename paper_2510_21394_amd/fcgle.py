@@ -300,7 +300,7 @@ def decode_signature(sig: int) -> dict:
     cfg = sig % 8
     prec = sig // 8
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
-            "structure": ["dense", "even_odd_fwd", "even_odd_bwd"][structure],
+            "structure": ["dense", "even_odd_fwd", "even_odd_bwd", "even_odd_fwd_fused"][structure],
             "prologue": ["none", "nonlinearity", "exp_euler_update", "?"][pk],
             "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "?", "?"][ek]}
 

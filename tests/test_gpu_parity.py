@@ -401,3 +401,50 @@ def test_update_in_backward_ignored_where_unsupported(F):
         tol = {"fp64": 1e-12, "fp32": 1e-5, "bf16x6": 1e-5}[prec]
         assert O.rel_l2(_host(u), ref) <= tol
         plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("n", [(300, 70, 129), (37, 30, 19), (131, 64)], ids=lambda s: "x".join(map(str, s)))
+def test_fused_forward_tiles(F, prec, cfg, n):
+    """Forward even/odd products with both blocks per tile (tile configuration cfg + 5) on
+    every axis: the f-grid epilogue (phi1), the separable exponential, and exponential-Euler
+    / LBDF2 steps (nonlinearity prologue, update epilogue) against the oracle; odd and even
+    lengths (the odd-n middle difference is zero), ragged row and column tiles."""
+    alpha, h = _setup(n, 71)
+    params = (0.9, -0.4, 0.8, 1.1, 0.6)
+    V = random_complex(n, 72)
+    P = O.Problem(n, alpha, h, params)
+    plan = F.Plan(n, alpha, h, params, tau=2e-3, precision=prec)
+    for ax in range(len(n)):
+        plan.set_tiles(ax, 1, cfg + 5)
+    assert "F]" in plan.describe()
+    for kind in ("phi1", "exp"):
+        out = plan.apply_f(kind, 1e-2, _dev(V, prec))
+        assert O.rel_l2(_host(out), P.f(kind, 1e-2, V)) <= TOL_OP[prec]
+    U0 = 1.5 * sech_product(grid_axes(n, ((-9.0, 9.0),) * len(n)), [0.7] + [0.2] * (len(n) - 1), 0.3)
+    for scheme in ("exp_euler", "lbdf2"):
+        ref = O.run(P, scheme, U0, 2e-3, 4)
+        u = _dev(U0, prec)
+        plan.set_state(u)
+        plan.timing_enable(64)
+        plan.run(scheme, u, 0.0, 4)
+        rec = plan.timing_read()
+        err = O.rel_l2(_host(u), ref)
+        print(f"[fused forward {prec} cfg{cfg} {n} {scheme}] rel_l2 = {err:.3e}")
+        assert err <= TOL_OP[prec]
+        assert {F.fcgle.decode_signature(r[2])["structure"] for r in rec if r[1] == 1} == {"even_odd_fwd_fused"}
+    plan.close()
+
+
+def test_fused_forward_tiles_rejected_where_unsupported(F):
+    n = (24, 30)
+    alpha, h = _setup(n, 73)
+    for prec, split in (("bf16x3", True), ("fp32", False)):
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
+        plan.set_structure(split)
+        with pytest.raises(F.FcgleError):
+            plan.set_tiles(0, 1, 5)
+        with pytest.raises(F.FcgleError):
+            plan.set_tiles(0, 0, 5)  # backward products have no fused form
+        plan.close()
