@@ -49,6 +49,7 @@ struct BatchInst {
 
 struct Phase {
   int cfg = 1;
+  int sp = 1;  // even/odd form: kSplitFwd or kSplitFwd2 (forward phases), kSplitBwd
   bool tl = false;
   ProKind pk = ProKind::Id;
   EpiKind ek = EpiKind::Store;
@@ -109,7 +110,7 @@ MPLaunch inst_launch(const BatchData* B, const BatchInst& I, int phase, const vo
   L.B = axis1 ? 1 : I.n[1];
   L.n = (int)I.n[mu];
   L.npad = I.npad[mu];
-  L.split = fwd ? 1 : 2;
+  L.split = fwd ? ph.sp : kSplitBwd;
   L.me = I.me[mu];
   L.mo = I.mo[mu];
   L.M = fwd ? (const void*)I.Mf[mu] : (const void*)I.Mb[mu];
@@ -219,7 +220,7 @@ int build_items(BatchData* B, const void* const* u) {
 int launch_phase(const BatchData* B, int p, hipStream_t st) {
   const Phase& ph = B->ph[p];
   const bool fwd = (p == PH_T0 || p == PH_T1 || p == PH_F0 || p == PH_F1);
-  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, fwd, ph.items, B->count, ph.nblocks, st));
+  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, fwd ? ph.sp : kSplitBwd, ph.items, B->count, ph.nblocks, st));
   return FCGLE_OK;
 }
 
@@ -303,30 +304,39 @@ int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEve
     HIP_TRY(hipMemsetAsync(B->inst[i].tmp, 0, (size_t)B->inst[i].N * 8, st));
     HIP_TRY(hipMemsetAsync(B->inst[i].uhat, 0, (size_t)B->inst[i].N * 8, st));
   }
+  // per phase: tile configuration, and for forward phases the even/odd form (two row
+  // tiles, or both blocks in one tile)
   const int order[] = {PH_F0, PH_B0, PH_B1};
   for (int p : order) {
     float best = 1e30f;
-    int best_c = B->ph[p].cfg;
-    for (int c = 0; c < kGroupCfg; ++c) {
-      B->ph[p].cfg = c;
-      FC_TRY(build_items(B, scratch.data()));
-      float ms;
-      FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_phase(B, p, st); }, &ms));
-      if (ms < best) {
-        best = ms;
-        best_c = c;
+    int best_c = B->ph[p].cfg, best_sp = B->ph[p].sp;
+    const int nsp = (p == PH_F0) ? 2 : 1;
+    for (int f2 = 0; f2 < nsp; ++f2)
+      for (int c = 0; c < kGroupCfg; ++c) {
+        B->ph[p].cfg = c;
+        if (p == PH_F0) B->ph[p].sp = f2 ? kSplitFwd2 : kSplitFwd;
+        FC_TRY(build_items(B, scratch.data()));
+        float ms;
+        FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_phase(B, p, st); }, &ms));
+        if (ms < best) {
+          best = ms;
+          best_c = c;
+          best_sp = B->ph[p].sp;
+        }
       }
-    }
     B->ph[p].cfg = best_c;
+    B->ph[p].sp = best_sp;
   }
-  // F1: fused update (each tile configuration) against Store + streaming pass
+  // F1: fused update (each tile configuration and form) against Store + streaming pass
   float best = 1e30f;
-  int best_c = 1;
+  int best_c = 1, best_sp = kSplitFwd;
   bool best_fuse = true;
   for (int f = 0; f < 2; ++f)
+    for (int f2 = 0; f2 < 2; ++f2)
     for (int c = 0; c < kGroupCfg; ++c) {
       B->fuse = (f == 0);
       B->ph[PH_F1].cfg = c;
+      B->ph[PH_F1].sp = f2 ? kSplitFwd2 : kSplitFwd;
       FC_TRY(build_items(B, scratch.data()));
       float ms;
       FC_TRY(time_phase(st, e0, e1, reps, [&]() -> int {
@@ -337,12 +347,15 @@ int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEve
       if (ms < best) {
         best = ms;
         best_c = c;
+        best_sp = B->ph[PH_F1].sp;
         best_fuse = B->fuse;
       }
     }
   B->fuse = best_fuse;
   B->ph[PH_F1].cfg = best_c;
+  B->ph[PH_F1].sp = best_sp;
   B->ph[PH_T0].cfg = B->ph[PH_F0].cfg;
+  B->ph[PH_T0].sp = B->ph[PH_F0].sp;
   B->ph[PH_T1].cfg = B->ph[PH_B1].cfg;
   B->items_valid = false;
   clear_graphs(B);
@@ -377,7 +390,8 @@ int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
   std::string s = "batch count=" + std::to_string(B->count) + " n in [" + std::to_string(nmin) + "," +
                   std::to_string(nmax) + "] precision=fp32 structure=even-odd tiles(rows)=";
   for (int p = 0; p < PH_COUNT; ++p)
-    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg, 1)) + (p + 1 < PH_COUNT ? "," : "");
+    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg, 1)) +
+         (B->ph[p].sp == kSplitFwd2 ? "F" : "") + (p + 1 < PH_COUNT ? "," : "");
   s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
   char tail[96];
   std::snprintf(tail, sizeof(tail), " flop/step=%.4g%s", flop, B->tuned ? " tuned" : " default");

@@ -16,31 +16,37 @@ struct Combo {
   using E = Epi;
 };
 
-// Calls f(Combo<...>{}) for the supported (loader, prologue, epilogue) combination; forward
-// products (Q^T) use the even/odd forward form, backward ones (Q) the backward form.
-template <class F>
-bool with_combo(bool tl, ProKind pk, EpiKind ek, bool fwd, F&& f) {
+// Forward (Q^T) combinations of the even/odd form SP (kSplitFwd or kSplitFwd2).
+template <int SP, class F>
+bool with_fwd_combo(bool tl, ProKind pk, EpiKind ek, F&& f) {
   using R = float;
-  if (fwd) {
-    if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
-      f(Combo<false, kSplitFwd, ProNonlinF<R>, EpiStoreF<R>>{});
-      return true;
-    }
-    if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
-      f(Combo<false, kSplitFwd, ProIdF, EpiStoreF<R>>{});
-      return true;
-    }
-    if (tl && pk == ProKind::Id && ek == EpiKind::Store) {
-      f(Combo<true, kSplitFwd, ProIdF, EpiStoreF<R>>{});
-      return true;
-    }
-    if (tl && pk == ProKind::Id && ek == EpiKind::ExpEuler) {
-      f(Combo<true, kSplitFwd, ProIdF, EpiExpEulerF<R>>{});
-      return true;
-    }
-    return false;
+  if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
+    f(Combo<false, SP, ProNonlinF<R>, EpiStoreF<R>>{});
+    return true;
   }
-  if (pk != ProKind::Id || ek != EpiKind::Store) return false;
+  if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
+    f(Combo<false, SP, ProIdF, EpiStoreF<R>>{});
+    return true;
+  }
+  if (tl && pk == ProKind::Id && ek == EpiKind::Store) {
+    f(Combo<true, SP, ProIdF, EpiStoreF<R>>{});
+    return true;
+  }
+  if (tl && pk == ProKind::Id && ek == EpiKind::ExpEuler) {
+    f(Combo<true, SP, ProIdF, EpiExpEulerF<R>>{});
+    return true;
+  }
+  return false;
+}
+
+// Calls f(Combo<...>{}) for the supported (loader, prologue, epilogue) combination of the
+// even/odd form sp: kSplitFwd or kSplitFwd2 (Q^T), kSplitBwd (Q).
+template <class F>
+bool with_combo(bool tl, ProKind pk, EpiKind ek, int sp, F&& f) {
+  using R = float;
+  if (sp == kSplitFwd) return with_fwd_combo<kSplitFwd>(tl, pk, ek, f);
+  if (sp == kSplitFwd2) return with_fwd_combo<kSplitFwd2>(tl, pk, ek, f);
+  if (sp != kSplitBwd || pk != ProKind::Id || ek != EpiKind::Store) return false;
   if (tl)
     f(Combo<true, kSplitBwd, ProIdF, EpiStoreF<R>>{});
   else
@@ -92,14 +98,14 @@ __global__ void __launch_bounds__(256)
 }  // namespace
 
 bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd) {
-  return with_combo(tloader, pk, ek, fwd, [](auto) {});
+  return with_combo(tloader, pk, ek, fwd ? kSplitFwd : kSplitBwd, [](auto) {});
 }
 
 size_t group_item_bytes(ProKind pk, EpiKind ek) {
   size_t b = 0;
   for (int tl = 0; tl < 2; ++tl)
-    for (int fwd = 0; fwd < 2; ++fwd)
-      with_combo(tl != 0, pk, ek, fwd != 0, [&](auto c) {
+    for (int sp = kSplitFwd; sp <= kSplitFwd2; ++sp)
+      with_combo(tl != 0, pk, ek, sp, [&](auto c) {
         using Cb = decltype(c);
         b = sizeof(GroupItem<typename Cb::P, typename Cb::E>);
       });
@@ -109,10 +115,10 @@ size_t group_item_bytes(ProKind pk, EpiKind ek) {
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host) {
   uint32_t total = 0;
-  const bool fwd = count > 0 && L[0].split == kSplitFwd;
+  const int sp = count > 0 ? L[0].split : 0;
   with_cfg(cfg, [&](auto t) {
     using T = decltype(t);
-    with_combo(tloader, pk, ek, fwd, [&](auto c) {
+    with_combo(tloader, pk, ek, sp, [&](auto c) {
       using Cb = decltype(c);
       using Item = GroupItem<typename Cb::P, typename Cb::E>;
       unsigned char* dst = (unsigned char*)items_host;
@@ -132,13 +138,13 @@ uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MP
   return total;
 }
 
-hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, bool fwd, const void* items_dev,
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, int sp, const void* items_dev,
                             int count, uint32_t nblocks, hipStream_t s) {
   hipError_t err = hipErrorInvalidValue;
   if (count < 1 || nblocks == 0) return err;
   with_cfg(cfg, [&](auto t) {
     using T = decltype(t);
-    with_combo(tloader, pk, ek, fwd, [&](auto c) {
+    with_combo(tloader, pk, ek, sp, [&](auto c) {
       using Cb = decltype(c);
       using Item = GroupItem<typename Cb::P, typename Cb::E>;
       hipLaunchKernelGGL((mp_group_kernel<float, T, Cb::tl, Cb::sp, typename Cb::P, typename Cb::E>),

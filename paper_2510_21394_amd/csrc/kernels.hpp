@@ -492,7 +492,7 @@ struct TileCfg {
 //             contracts the sum with Fe and the difference with Fo (two accumulator sets) and
 //             writes rows base 0 and base me; half the loads and prologue work of kSplitFwd
 //             for the same multiply-adds (the odd-n middle difference is exactly zero).
-enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2, kSplitFwd2 = 3 };
+// (the values kDense, kSplitFwd, kSplitBwd, kSplitFwd2 are declared in launch.h: MPLaunch::split)
 
 struct Geo {
   uint32_t A, B;      // batch (slower) and inner (faster) extents, complex elements

@@ -10,6 +10,9 @@ namespace fcgle {
 
 enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16X3 = 2, P_BF16X6 = 3 };
 
+// Structure of a mode product (MPLaunch::split; the forms are described in kernels.hpp).
+enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2, kSplitFwd2 = 3 };
+
 // Pointwise map applied to the input of a mode product while its tile is loaded.
 //  Update: the exponential-Euler update uhat_out = E uhat + tau P1 v of the input v (the
 //  transformed nonlinearity), contracted and also stored (first backward even/odd product).
@@ -115,13 +118,14 @@ inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
 // one launch.  group_build_f32 writes the item array for the per-problem descriptions
 // L[0..count) (split = 1 forward or 2 backward) into host memory (group_item_bytes(pk, ek)
 // bytes per item) and returns the total number of workgroups; the array must then be copied
-// to the device and passed to launch_group_f32.  Supported: forward (N loader, Nonlin or Id,
-// Store), (T loader, Id, Store or ExpEuler); backward (either loader, Id, Store).
+// to the device and passed to launch_group_f32 with the same split (1 or 3 forward, 2
+// backward).  Supported: forward (N loader, Nonlin or Id, Store), (T loader, Id, Store or
+// ExpEuler); backward (either loader, Id, Store).
 bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd);
 size_t group_item_bytes(ProKind pk, EpiKind ek);
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host);
-hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, bool fwd, const void* items_dev,
+hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, int split, const void* items_dev,
                             int count, uint32_t nblocks, hipStream_t s);
 // Grouped streaming epilogue (FP32): item k applies `ek` (ExpEuler) to v[k] viewed as
 // (rows[k], nlast[k]) with parameters ep[k]; returns the total number of rows.
