@@ -101,10 +101,13 @@ def mode_product_bytes(n, kernel, elem):
     2 e N; with the fused exponential-Euler epilogue the output is not stored but uhat and
     the P1 grid are read and uhat written, 4 e N; with the update prologue (the update of
     the state applied by the first backward product) ghat, uhat and P1 are read and the new
-    state and the product written, 5 e N.  The per-axis factor tables are negligible."""
+    state and the product written, 5 e N (4 e N when phi_1 is formed on the fly).  The per-axis
+    factor tables are negligible."""
     N = float(np.prod(n))
     if kernel["prologue"] == "exp_euler_update":
         return 5.0 * elem * N
+    if kernel["prologue"] == "exp_euler_update_otf":  # no P1 grid read
+        return 4.0 * elem * N
     if kernel["epilogue"] == "exp_euler":
         return 4.0 * elem * N
     return 2.0 * elem * N

@@ -247,8 +247,11 @@ int fcgle_set_structure(fcgle_plan* plan, int split);
  * on a product along a slow axis.  Bit 3 moves the exponential-Euler update
  * uhat <- E uhat + tau P1 ghat out of the forward operator into the first backward product,
  * which applies it to ghat while loading its tile, stores the new state and contracts it
- * (even/odd FP64 / FP32 plans with d >= 2; otherwise bit 3 is ignored).  Default 3;
- * fcgle_autotune picks all four by timing whole exponential-Euler steps.  Errors: ERR_ARG. */
+ * (even/odd FP64 / FP32 plans with d >= 2; otherwise bit 3 is ignored).  Bit 5 (32), with
+ * bit 3: that update forms P1 = phi_1(z) = (e^z - 1)/z in FP64 from separable tables (e^z - 1
+ * accumulated from the per-axis expm1 without cancellation) instead of reading the stored P1
+ * grid (n_1 <= 512; otherwise ignored).  Bit 4 is reserved.  Default 3; fcgle_autotune picks
+ * them by timing whole exponential-Euler steps.  Errors: ERR_ARG. */
 int fcgle_set_fusion(fcgle_plan* plan, int flags);
 
 /* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */
@@ -268,7 +271,7 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q, 3 even/odd Q^T with both blocks per tile;
  * prec 0..3 as fcgle_precision;
  * t_loader 1 for the fastest axis; prologue 0 none, 1 nonlinearity, 2 exponential-Euler
- * update; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
+ * update, 3 the same with phi_1 on the fly; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
  * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */
 int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
                       int64_t* count);

@@ -155,45 +155,79 @@ int get_grid(fcgle_plan* P, int kind, double theta, hipStream_t st, const void**
 }
 
 // Separable exponential factors exp(theta (nu + i eta) lambda_mu[j]) per axis, FP64 on the host.
+// e^z - 1 for z = x + i y without cancellation: (expm1(x) cos y - 2 sin^2(y/2)) + i e^x sin y.
+zc expm1_c(double x, double y) {
+  const double s = std::sin(0.5 * y);
+  return zc{std::expm1(x) * std::cos(y) - 2.0 * s * s, std::exp(x) * std::sin(y)};
+}
+
+void fill_sep(const SepBuf& e, const fcgle_plan* P, SepParams* sp) {
+  for (int m = 0; m < P->d; ++m) {
+    sp->fac[m] = e.fac[m];
+    sp->facm1[m] = e.facm1[m];
+  }
+  sp->other_last = e.other_last;
+  sp->other_first = e.other_first;
+  sp->first_m1 = e.first_m1;
+  sp->first_lam = e.first_lam;
+  sp->zre = e.theta * P->p.nu;
+  sp->zim = e.theta * P->p.eta;
+}
+
 int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
   *sp = sep_base(P);
   for (auto& e : P->seps)
     if (e.theta == theta) {
-      for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
-      sp->other_last = e.other_last;
-      sp->other_first = e.other_first;
+      fill_sep(e, P, sp);
       return FCGLE_OK;
     }
-  SepBuf e{theta, {nullptr, nullptr, nullptr, nullptr}, nullptr, nullptr};
-  for (int m = 0; m < P->d; ++m) {
-    std::vector<double> buf(2 * P->n[m]);
+  SepBuf e{};
+  e.theta = theta;
+  int rc = FCGLE_OK;
+  for (int m = 0; m < P->d && rc == FCGLE_OK; ++m) {
+    std::vector<double> buf(2 * P->n[m]), bm1(2 * P->n[m]);
     for (int64_t j = 0; j < P->n[m]; ++j) {
-      const zc z = fz_eval(1, zc{theta * P->p.nu * P->lam[m][j], theta * P->p.eta * P->lam[m][j]});
+      const double x = theta * P->p.nu * P->lam[m][j], y = theta * P->p.eta * P->lam[m][j];
+      const zc z = fz_eval(1, zc{x, y});
       buf[2 * j] = z.re;
       buf[2 * j + 1] = z.im;
+      const zc w = expm1_c(x, y);
+      bm1[2 * j] = w.re;
+      bm1[2 * j + 1] = w.im;
     }
-    FC_TRY(plan_alloc(&e.fac[m], buf.size() * sizeof(double)));
-    HIP_TRY(hipMemcpy(e.fac[m], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice));
+    rc = plan_alloc(&e.fac[m], buf.size() * sizeof(double));
+    if (rc == FCGLE_OK) rc = plan_alloc(&e.facm1[m], bm1.size() * sizeof(double));
+    if (rc == FCGLE_OK && (hipMemcpy(e.fac[m], buf.data(), buf.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+                           hipMemcpy(e.facm1[m], bm1.data(), bm1.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess))
+      rc = fail(FCGLE_ERR_HIP, "separable factor upload failed");
   }
-  for (int m = 0; m < P->d; ++m) sp->fac[m] = e.fac[m];
-  // per-column factor tables for epilogues on the last and on the first axis
+  // per-column tables for epilogues on the last and on the first axis, and for phi_1 on the
+  // fly on the first axis
   const int64_t cl = P->N / P->n[P->d - 1], cf = P->N / P->n[0];
-  int rc = plan_alloc(&e.other_last, (size_t)cl * 2 * sizeof(double));
+  if (rc == FCGLE_OK) rc = plan_alloc(&e.other_last, (size_t)cl * 2 * sizeof(double));
   if (rc == FCGLE_OK) rc = plan_alloc(&e.other_first, (size_t)cf * 2 * sizeof(double));
-  if (rc == FCGLE_OK && launch_sep_table(*sp, P->d - 1, cl, e.other_last, nullptr) != hipSuccess)
-    rc = fail(FCGLE_ERR_HIP, "separable factor table: launch failed");
-  if (rc == FCGLE_OK && launch_sep_table(*sp, 0, cf, e.other_first, nullptr) != hipSuccess)
-    rc = fail(FCGLE_ERR_HIP, "separable factor table: launch failed");
+  if (rc == FCGLE_OK) rc = plan_alloc(&e.first_m1, (size_t)cf * 2 * sizeof(double));
+  if (rc == FCGLE_OK) rc = plan_alloc((void**)&e.first_lam, (size_t)cf * sizeof(double));
+  if (rc == FCGLE_OK) {
+    fill_sep(e, P, sp);
+    if (launch_sep_table(*sp, P->d - 1, cl, e.other_last, nullptr) != hipSuccess ||
+        launch_sep_table(*sp, 0, cf, e.other_first, nullptr) != hipSuccess ||
+        launch_sep_table_m1(*sp, cf, e.first_m1, e.first_lam, nullptr) != hipSuccess)
+      rc = fail(FCGLE_ERR_HIP, "separable factor table: launch failed");
+  }
   if (rc == FCGLE_OK && hipDeviceSynchronize() != hipSuccess) rc = fail(FCGLE_ERR_HIP, "separable factor table");
   if (rc != FCGLE_OK) {
-    for (int m = 0; m < P->d; ++m) (void)hipFree(e.fac[m]);
+    for (int m = 0; m < 4; ++m) {
+      if (e.fac[m]) (void)hipFree(e.fac[m]);
+      if (e.facm1[m]) (void)hipFree(e.facm1[m]);
+    }
     if (e.other_last) (void)hipFree(e.other_last);
     if (e.other_first) (void)hipFree(e.other_first);
+    if (e.first_m1) (void)hipFree(e.first_m1);
+    if (e.first_lam) (void)hipFree(e.first_lam);
     return rc;
   }
   P->seps.push_back(e);
-  sp->other_last = e.other_last;
-  sp->other_first = e.other_first;
   return FCGLE_OK;
 }
 
@@ -239,6 +273,15 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
   return L;
 }
 
+// Whether the backward even/odd tile configuration cfg leaves LDS for the staged rows of the
+// on-the-fly update (the same budget the kernels are instantiated under: operand tiles with
+// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows 48-byte rows).
+bool otf_fits(int pr, int cfg) {
+  const size_t r = (pr == P_F64) ? 8 : 4, ldk = 16 + (pr == P_F64 ? 2 : 4);
+  const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
+  return 2 * 2 * tm * ldk * r + 2 * 2 * 2 * tnc * ldk * r + (size_t)kOtfMaxRows * 48 <= 163840;
+}
+
 // One Tucker operator: out = epi( pro(in) x_1 M_1 ... x_d M_d ) with M = Q^T (fwd) or Q.
 // tmp0/tmp1 are scratch tensors distinct from in and from the epilogue's buffers.
 int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams& pp, EpiKind ek,
@@ -266,12 +309,13 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
     const bool tl = (L.B == 1);
     L.in = cur;
     if (first && pk != ProKind::Id) {
-      if (pk == ProKind::Update) {
+      if (pk == ProKind::Update || pk == ProKind::UpdateOtf) {
         // no streaming form: callers check update_prologue_ok first
         L.pk = pk;
         L.pp = pp;
         L.pp.sep.mu = mu;
         if (P->cfg_upd >= 0) L.cfg = P->cfg_upd;
+        if (pk == ProKind::UpdateOtf && !otf_fits(L.prec, L.cfg)) L.pk = ProKind::Update;  // reads the P1 grid
       } else if ((P->fusion & 1) && mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
         L.pk = pk;
         L.pp = pp;
@@ -351,6 +395,10 @@ bool update_prologue_ok(const fcgle_plan* P) {
   return P->split && P->d > 1 && (pr == P_F64 || pr == P_F32) && mp_supported(false, ProKind::Update, EpiKind::Store);
 }
 
+// ... and with phi_1 formed on the fly (rows of axis 0 staged in LDS)
+bool update_otf_ok(const fcgle_plan* P) { return update_prologue_ok(P) && P->n[0] <= kOtfMaxRows; }
+
+
 // One exponential-Euler step on the eigenspace state uhat (Section 4, eq. for the scheme):
 // ghat = Q^T g(t, u_n), uhat <- E uhat + tau P1 ghat, u <- Q uhat.  With fusion bit 3 the
 // update is applied by the first backward product while it loads ghat (the new state goes to
@@ -376,7 +424,8 @@ int expeuler_body(fcgle_plan* P, void* u, double t, hipStream_t st) {
     up.uhat_out = P->uhat2;
     up.sep = sep;
     up.tau = tau;
-    FC_TRY(tucker(P, false, P->s[2], ProKind::Update, up, EpiKind::Store, eb, P->s[0], P->s[1], st));
+    const ProKind pk = ((P->fusion & 32) && update_otf_ok(P)) ? ProKind::UpdateOtf : ProKind::Update;
+    FC_TRY(tucker(P, false, P->s[2], pk, up, EpiKind::Store, eb, P->s[0], P->s[1], st));
     std::swap(P->uhat, P->uhat2);
     return FCGLE_OK;
   }
@@ -589,9 +638,14 @@ void free_plan(fcgle_plan* P) {
   }
   for (auto& g : P->grids) f(g.F);
   for (auto& e : P->seps) {
-    for (int m = 0; m < 4; ++m) f(e.fac[m]);
+    for (int m = 0; m < 4; ++m) {
+      f(e.fac[m]);
+      f(e.facm1[m]);
+    }
     f(e.other_last);
     f(e.other_first);
+    f(e.first_m1);
+    f(e.first_lam);
   }
   for (int k = 0; k < 3; ++k) f(P->s[k]);
   for (int m = 0; m < 4; ++m) f(P->Md[m]);
@@ -1015,8 +1069,8 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
   }
   // with the update in the first backward product that product is timed in every tile
   // configuration again (its loads differ from the plain product's)
-  static const int kFusions[] = {0, 1, 2, 3, 8, 9};
-  const int nfus = update_prologue_ok(plan) ? 6 : 4;
+  static const int kFusions[] = {0, 1, 2, 3, 8, 9, 40, 41};
+  const int nfus = update_otf_ok(plan) ? 8 : update_prologue_ok(plan) ? 6 : 4;
   // whole steps differ by a few percent between the best choices: time more of them
   const int reps2 = reps * 3 > 10 ? reps * 3 : 10;
   float best = 1e30f;
@@ -1107,8 +1161,9 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
 
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
-  if (flags < 0 || flags > 15) return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15");
-  plan->fusion = flags & 11;
+  if (flags < 0 || flags > 47 || (flags & 16))
+    return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15, optionally with bit 5 (32)");
+  plan->fusion = flags & 43;
   plan->fwd_rev = (flags & 4) != 0;
   return FCGLE_OK;
 }
@@ -1133,7 +1188,8 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   if (plan->fusion & 8) {
     if (update_prologue_ok(plan)) {
       const int c = plan->cfg_upd >= 0 ? plan->cfg_upd : plan->cfg[0][0];
-      s += " update=backward-prologue(" + std::to_string(cfg_rows(pr, c, 1)) + "x" + std::to_string(cfg_cols(pr, c, 1)) + ")";
+      s += " update=backward-prologue(" + std::to_string(cfg_rows(pr, c, 1)) + "x" + std::to_string(cfg_cols(pr, c, 1)) +
+           ((plan->fusion & 32) && update_otf_ok(plan) ? ",phi1-on-the-fly" : "") + ")";
     } else {
       s += " update=backward-prologue(unsupported:epilogue)";
     }

@@ -22,9 +22,14 @@ template <class K, class T, int SP>
 hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   using R = typename K::R;
   const bool tl = (L.B == 1);
-  if (L.pk == ProKind::Update) {
-    if constexpr (SP == kSplitBwd && K::kUpdate)
-      if (!tl && L.ek == EpiKind::Store) return K::template go<T, false, SP, ProUpdateF<R>, EpiStoreF<R>>(L, s);
+  if (L.pk == ProKind::Update || L.pk == ProKind::UpdateOtf) {
+    if constexpr (SP == kSplitBwd && K::kUpdate) {
+      if (!tl && L.ek == EpiKind::Store) {
+        if (L.pk == ProKind::Update) return K::template go<T, false, SP, ProUpdateF<R>, EpiStoreF<R>>(L, s);
+        if constexpr (mp_operand_lds<R, T, SP>() + kOtfMaxRows * sizeof(typename ProUpdateOtfF<R>::RowEnt) <= kLdsBytes)
+          if (L.n <= kOtfMaxRows) return K::template go<T, false, SP, ProUpdateOtfF<R>, EpiStoreF<R>>(L, s);
+      }
+    }
     return hipErrorInvalidValue;
   }
   if (!tl) {

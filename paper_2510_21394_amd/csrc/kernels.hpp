@@ -26,6 +26,7 @@
 
 #include <cstdint>
 #include <type_traits>
+#include <utility>
 
 #include "fz.hpp"
 #include "launch.h"
@@ -78,6 +79,7 @@ __device__ __forceinline__ uint32_t xcd_remap(uint32_t w, uint32_t nblocks) {
 struct ProIdF {
   static constexpr bool kId = true;
   static constexpr bool kUpdate = false;  // see ProUpdateF
+  static constexpr bool kRowLds = false;  // see ProUpdateOtfF
   struct Pre {};
   ProIdF() = default;
   explicit ProIdF(const ProParams&) {}
@@ -93,6 +95,7 @@ template <class R>
 struct ProNonlinF {
   static constexpr bool kId = false;
   static constexpr bool kUpdate = false;
+  static constexpr bool kRowLds = false;  // see ProUpdateOtfF
   struct Pre {};
   using C = typename Cx<R>::T;
   const C* up;
@@ -436,6 +439,8 @@ template <class R>
 struct ProUpdateF {
   static constexpr bool kId = false;
   static constexpr bool kUpdate = true;
+  static constexpr bool kRowLds = false;
+  struct RowEnt {};
   using C = typename Cx<R>::T;
   struct Pre {
     C u, P;
@@ -457,6 +462,62 @@ struct ProUpdateF {
     const zc eu = zmul(zmul(Eo, pre.f), to_zc(pre.u));
     const C pg = cmul(pre.P, g);
     return from_zc<C>(zc{eu.re + tau * (double)pg.x, eu.im + tau * (double)pg.y});
+  }
+  __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
+};
+
+// The same update with P1 = phi_1(z) = (e^z - 1) / z formed on the fly in FP64 instead of read
+// from the P1 grid (one HBM stream less).  z = (zre + i zim)(lam_row + lam_col), e^z = E_col E_row
+// and e^z - 1 = a + b + a b with a = E_col - 1, b = E_row - 1 (all from separable tables, both
+// of the same sign pattern, so the sum does not cancel); below |z| = 1e-8 the series 1 + z/2.
+// The row entries (factor, factor - 1, eigenvalue of the axis) of all n rows are staged in LDS
+// once per workgroup (n <= kOtfMaxRows); the column context once per loader unit.
+template <class R>
+struct ProUpdateOtfF {
+  static constexpr bool kId = false;
+  static constexpr bool kUpdate = true;
+  static constexpr bool kRowLds = true;
+  using C = typename Cx<R>::T;
+  struct Pre {
+    C u;
+  };
+  struct __attribute__((aligned(16))) RowEnt {
+    zc f, fm1;
+    double lam, pad_;
+  };
+  struct Col {
+    zc E, Em1;
+    double lam;
+  };
+  const C* uhat;
+  C* uhat_out;
+  SepParams s;
+  double tau;
+  ProUpdateOtfF() = default;
+  explicit ProUpdateOtfF(const ProParams& p)
+      : uhat((const C*)p.uhat), uhat_out((C*)p.uhat_out), s(p.sep), tau(p.tau) {}
+  __device__ __forceinline__ RowEnt row_entry(int i) const {
+    return RowEnt{((const zc*)s.fac[s.mu])[i], ((const zc*)s.facm1[s.mu])[i], s.lam[s.mu][i], 0.0};
+  }
+  __device__ __forceinline__ Col col(uint32_t, uint32_t b) const {
+    return Col{((const zc*)s.other_first)[b], ((const zc*)s.first_m1)[b], s.first_lam[b]};
+  }
+  __device__ __forceinline__ Pre load(int64_t j, int) const { return Pre{uhat[j]}; }
+  __device__ __forceinline__ C update(const Col& c, const RowEnt& r, C g, const Pre& pre) const {
+    const zc eu = zmul(zmul(c.E, r.f), to_zc(pre.u));
+    const zc em1 = zadd(zadd(c.Em1, r.fm1), zmul(c.Em1, r.fm1));
+    const double l = c.lam + r.lam;
+    const zc z{s.zre * l, s.zim * l};
+    const double zz = z.re * z.re + z.im * z.im;
+    zc p1;
+    if (zz > 1e-16) {
+      const double inv = 1.0 / zz;
+      p1 = zc{(em1.re * z.re + em1.im * z.im) * inv, (em1.im * z.re - em1.re * z.im) * inv};
+    } else {
+      p1 = zc{1.0 + 0.5 * z.re, 0.5 * z.im};
+    }
+    const zc pg = zmul(p1, to_zc(g));
+    return from_zc<C>(zc{eu.re + tau * pg.re, eu.im + tau * pg.im});
   }
   __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
 };
@@ -564,6 +625,16 @@ __device__ __forceinline__ void pro_b_unit(const Geo& g, uint32_t a, uint32_t b,
   }
 }
 
+// Column context type of an update prologue (zc for the other prologues).
+template <class Pro, bool U>
+struct UpdColOf {
+  using type = zc;
+};
+template <class Pro>
+struct UpdColOf<Pro, true> {
+  using type = decltype(std::declval<const Pro&>().col(0u, 0u));
+};
+
 // Loads of the update-prologue kernels (ProUpdateF): the tensor element, and the update's
 // operands, of each element of one B unit (same element mapping as load_b_unit).  Every
 // load is issued unconditionally from a clamped index (element 0 / row 0 when outside the
@@ -595,13 +666,18 @@ __device__ __forceinline__ void pre_b_unit(const Geo& g, const Pro& pro, uint32_
   }
 }
 
-template <class C, int G, bool TL, class Pro>
+template <class C, int G, bool TL, class Pro, class Ctx, class RowT>
 __device__ __forceinline__ void upd_b_unit(const Geo& g, const Pro& pro, uint32_t a, uint32_t b, int kb, int klim,
-                                           int koff, const zc& Eo, const typename Pro::Pre (&p)[G], bool write,
-                                           C (&v)[G]) {
+                                           int koff, const Ctx& Eo, const typename Pro::Pre (&p)[G], bool write,
+                                           const RowT* rows, C (&v)[G]) {
   const bool colok = TL ? a < g.A : b < g.B;
 #pragma unroll
-  for (int e = 0; e < G; ++e) v[e] = (colok && kb + e < klim) ? pro.update(Eo, v[e], p[e]) : C{0, 0};
+  for (int e = 0; e < G; ++e) {
+    if constexpr (Pro::kRowLds)
+      v[e] = (colok && kb + e < klim) ? pro.update(Eo, rows[koff + kb + e], v[e], p[e]) : C{0, 0};
+    else
+      v[e] = (colok && kb + e < klim) ? pro.update(Eo, v[e], p[e]) : C{0, 0};
+  }
   if (!write) return;
 #pragma unroll
   for (int e = 0; e < G; ++e) {
@@ -769,6 +845,16 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
   }
 }
 
+// LDS of the double-buffered operand tiles of mp_mfma_tile (N loader; the T-loader epilogue
+// may need more), and whether the rows of the on-the-fly update fit beside them.
+template <class R, class T, int SP>
+constexpr size_t mp_operand_lds() {
+  constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;
+  constexpr int LDK = T::TK + (sizeof(R) == 8 ? 2 : 4);
+  return (size_t)2 * NB * T::TM * LDK * sizeof(R) + (size_t)2 * NB * 2 * T::TNC * LDK * sizeof(R);
+}
+constexpr size_t kLdsBytes = 163840;  // 160 KB per workgroup on gfx950
+
 template <class C, class T>
 constexpr size_t epi_lds_bytes() {
   return (size_t)16 * (T::TM + 1) * sizeof(C);
@@ -848,7 +934,16 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   constexpr bool UPD = Pro::kUpdate;
   static_assert(!UPD || SP == kSplitBwd, "the update prologue runs on backward even/odd products");
   typename Pro::Pre rp[UPD ? NR : 1][UPD ? BIT : 1][G];
-  zc eo[UPD ? BIT : 1];
+  using ColT = typename UpdColOf<Pro, UPD>::type;
+  ColT eo[UPD ? BIT : 1];
+  // row entries of the on-the-fly update, staged in LDS for all n rows of the axis
+  using RowT = typename std::conditional_t<UPD, Pro, ProUpdateF<R>>::RowEnt;
+  constexpr int kRows = Pro::kRowLds ? kOtfMaxRows : 1;
+  __shared__ RowT rowtab[kRows];
+  if constexpr (Pro::kRowLds) {
+    for (int k = tid; k < g.n; k += T::THREADS) rowtab[k] = pro.row_entry(k);
+    __syncthreads();
+  }
 
   auto unit_b = [&](int u, int& row, int& kq) {
     if (TL) {
@@ -961,8 +1056,9 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         } else {
           if constexpr (UPD) {
             // the first row tile writes the updated state; every row tile contracts it
-            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rb[0][it]);
-            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rb[NR - 1][it]);
+            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
+            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rowtab,
+                                 rb[NR - 1][it]);
           }
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, rb[0][it]);
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB + 1, row, kq, rb[NR - 1][it]);
@@ -1016,7 +1112,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
-      eo[it] = zc{0.0, 0.0};
+      eo[it] = ColT{};
       if (BU % T::THREADS == 0 || u < BU) {
         int row, kq;
         unit_b(u, row, kq);

@@ -16,7 +16,10 @@ enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2, kSplitFwd2 = 3 };
 // Pointwise map applied to the input of a mode product while its tile is loaded.
 //  Update: the exponential-Euler update uhat_out = E uhat + tau P1 v of the input v (the
 //  transformed nonlinearity), contracted and also stored (first backward even/odd product).
-enum class ProKind : int { Id = 0, Nonlin = 1, Update = 2 };
+//  UpdateOtf: as Update with P1 = (E - 1) / z formed on the fly from separable tables (no
+//  P1 grid read; axis lengths n_1 <= kOtfMaxRows).
+enum class ProKind : int { Id = 0, Nonlin = 1, Update = 2, UpdateOtf = 3 };
+constexpr int kOtfMaxRows = 512;
 // What the last stage of a mode product does with each output element.
 enum class EpiKind : int {
   Store = 0,     // out[j] = v
@@ -43,6 +46,12 @@ struct SepParams {
   const double* lam[4] = {nullptr, nullptr, nullptr, nullptr}; // eigenvalues (adjoint)
   const void* other_last = nullptr;   // double2[N / n_{d-1}]
   const void* other_first = nullptr;  // double2[N / n_0]
+  // for phi_1 on the fly: the exponent scale z = (zre + i zim) ell, expm1 of each axis factor,
+  // and over the axes after the first prod e^{z_mu} - 1 (double2) and sum lambda_mu (double)
+  double zre = 0, zim = 0;
+  const void* facm1[4] = {nullptr, nullptr, nullptr, nullptr};
+  const void* first_m1 = nullptr;
+  const double* first_lam = nullptr;
 };
 
 // Nonlin: g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with
@@ -175,6 +184,10 @@ hipError_t launch_reduce_partials(const double* partial, int64_t count, int widt
 // other = prod over the axes != mu (mu = 0 or d-1) of the separable factors, for all
 // `count` flat indices over the remaining axes (FP64, double2).
 hipError_t launch_sep_table(const SepParams& sep, int mu, int64_t count, void* other, hipStream_t s);
+// first_m1[j] = prod_{mu >= 1} (1 + facm1[mu][j_mu]) - 1 (accumulated without cancellation)
+// and first_lam[j] = sum_{mu >= 1} lam[mu][j_mu], for the count = N / n_0 flat indices.
+hipError_t launch_sep_table_m1(const SepParams& sep, int64_t count, void* first_m1, double* first_lam,
+                               hipStream_t s);
 // Elementwise f-grid from separable eigenvalues: F[j] = f(theta (nu + i eta) sum lam_mu[j_mu]),
 // evaluated in FP64 on the device and stored in the state type.
 hipError_t launch_fgrid(int prec, int kind, double theta_re, double theta_im, const SepParams& sep,

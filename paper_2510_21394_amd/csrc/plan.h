@@ -65,6 +65,9 @@ struct SepBuf {
   void* fac[4];       // double2[n_mu] each
   void* other_last;   // double2[N / n_{d-1}]: product over the axes before the last
   void* other_first;  // double2[N / n_0]: product over the axes after the first
+  void* facm1[4];     // double2[n_mu]: expm1 of each factor's exponent
+  void* first_m1;     // double2[N / n_0]: product over the axes after the first, minus 1
+  double* first_lam;  // double[N / n_0]: sum of their eigenvalues
 };
 
 struct TimedLaunch {

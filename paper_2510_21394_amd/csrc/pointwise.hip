@@ -82,6 +82,24 @@ __global__ void __launch_bounds__(kPwThreads)
     out[j] = (mu == 0) ? sep_other_direct(s, 0, (uint32_t)j) : sep_other_direct(s, (uint32_t)j, 0);
 }
 
+__global__ void __launch_bounds__(kPwThreads)
+    sep_table_m1_kernel(SepParams s, int64_t count, zc* __restrict__ m1, double* __restrict__ lam) {
+  for (int64_t j = blockIdx.x * (int64_t)kPwThreads + threadIdx.x; j < count; j += (int64_t)gridDim.x * kPwThreads) {
+    uint32_t b = (uint32_t)j;
+    zc a{0.0, 0.0};  // prod (1 + x_mu) - 1 over the axes done so far
+    double l = 0.0;
+    for (int nu = s.d - 1; nu > 0; --nu) {
+      const uint32_t jn = b % (uint32_t)s.n[nu];
+      b /= (uint32_t)s.n[nu];
+      const zc x = ((const zc*)s.facm1[nu])[jn];
+      a = zadd(zadd(a, x), zmul(a, x));
+      l += s.lam[nu][jn];
+    }
+    m1[j] = a;
+    lam[j] = l;
+  }
+}
+
 template <class C>
 __global__ void __launch_bounds__(kPwThreads) finite_kernel(int64_t N, const C* __restrict__ u, int* flag) {
   bool bad = false;
@@ -143,7 +161,7 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
 }  // namespace
 
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek) {
-  if (pk == ProKind::Update) return !tloader && ek == EpiKind::Store;
+  if (pk == ProKind::Update || pk == ProKind::UpdateOtf) return !tloader && ek == EpiKind::Store;
   if (pk != ProKind::Id) return ek == EpiKind::Store;
   if (!tloader) return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler;
   return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler ||
@@ -162,6 +180,13 @@ hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, 
 
 hipError_t launch_sep_table(const SepParams& sep, int mu, int64_t count, void* other, hipStream_t s) {
   hipLaunchKernelGGL(sep_table_kernel, dim3(pw_blocks(count)), dim3(kPwThreads), 0, s, sep, mu, count, (zc*)other);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_table_m1(const SepParams& sep, int64_t count, void* first_m1, double* first_lam,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(sep_table_m1_kernel, dim3(pw_blocks(count)), dim3(kPwThreads), 0, s, sep, count, (zc*)first_m1,
+                     first_lam);
   return hipGetLastError();
 }
 

@@ -326,25 +326,29 @@ def test_autotuned_exp_euler_matches_oracle(F):
         assert O.rel_l2(_host(u), ref) <= tol
 
 
+@pytest.mark.parametrize("otf", [False, True], ids=["p1grid", "p1otf"])
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n", [(150, 21, 26), (37, 30, 19), (131, 64)], ids=lambda s: "x".join(map(str, s)))
-def test_update_in_backward_prologue(F, prec, cfg, n):
+def test_update_in_backward_prologue(F, prec, cfg, n, otf):
     """Exponential-Euler update applied by the first backward product while it loads its tile
     (fusion bit 3), in every tile configuration of that product: odd and even axis lengths,
     ragged column tiles, and two row tiles per column (n0 = 150 and 131 with 64-row tiles), where
-    only the first row tile stores the new state.  Against the oracle trajectory, and the timing
-    record shows the update prologue on the axis-0 backward product."""
+    only the first row tile stores the new state; phi_1 read from the grid or formed on the fly
+    (the FP64 128x64 tile has no LDS left for the staged rows and reads the grid).  Against the
+    oracle trajectory, and the timing record shows the update prologue on the axis-0 backward
+    product."""
     alpha, h = _setup(n, 31)
     params = (0.9, -0.4, 0.8, 1.1, 0.6)
     tau, steps = 2e-3, 6
     U0 = 1.5 * sech_product(grid_axes(n, ((-9.0, 9.0),) * len(n)), [0.7] + [0.2] * (len(n) - 1), 0.3)
     ref = O.run(O.Problem(n, alpha, h, params), "exp_euler", U0, tau, steps)
     plan = F.Plan(n, alpha, h, params, tau=tau, precision=prec)
-    plan.set_fusion(True, True, False, update_in_backward=True)
+    plan.set_fusion(True, True, False, update_in_backward=True, phi1_on_the_fly=otf)
     plan.set_tiles(0, 0, cfg)
     desc = plan.describe()
     assert "update=backward-prologue" in desc and "unsupported" not in desc
+    assert ("phi1-on-the-fly" in desc) == otf
     u = _dev(U0, prec)
     plan.step("exp_euler", u, 0.0)
     plan.timing_enable(64)
@@ -354,7 +358,8 @@ def test_update_in_backward_prologue(F, prec, cfg, n):
     print(f"[update prologue {prec} cfg{cfg} {n}] rel_l2 = {err:.3e}")
     assert err <= TOL_OP[prec]
     pro = {F.fcgle.decode_signature(r[2])["prologue"] for r in rec if r[0] == 0 and r[1] == 0}
-    assert pro == {"exp_euler_update"}
+    grid_only = not otf or (prec == "fp64" and cfg == 4)
+    assert pro == {"exp_euler_update" if grid_only else "exp_euler_update_otf"}
     epi = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[1] == 1}
     assert epi == {"store"}
     plan.close()
@@ -374,7 +379,7 @@ def test_update_modes_interleave(F, prec):
     u = _dev(U0, prec)
     t = 0.0
     for k, upd in enumerate([True, True, True, False, False, True, False, True, True]):
-        plan.set_fusion(True, True, k % 2 == 1, update_in_backward=upd)
+        plan.set_fusion(True, True, k % 2 == 1, update_in_backward=upd, phi1_on_the_fly=k % 3 == 0)
         plan.step("exp_euler", u, t)
         t += tau
     err = O.rel_l2(_host(u), ref)
@@ -448,3 +453,21 @@ def test_fused_forward_tiles_rejected_where_unsupported(F):
         with pytest.raises(F.FcgleError):
             plan.set_tiles(0, 0, 5)  # backward products have no fused form
         plan.close()
+
+
+def test_phi1_on_the_fly_ignored_for_long_first_axis(F):
+    """phi_1 on the fly stages the rows of axis 1 in LDS (at most 512): a longer axis keeps the
+    grid-reading update; results match the oracle either way."""
+    n = (600, 12)
+    alpha, h = _setup(n, 81)
+    tau = 2e-3
+    U0 = random_complex(n, 82) * 0.3
+    ref = O.run(O.Problem(n, alpha, h, BASE_PARAMS), "exp_euler", U0, tau, 3)
+    plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=tau, precision="fp32")
+    plan.set_fusion(True, True, False, update_in_backward=True, phi1_on_the_fly=True)
+    desc = plan.describe()
+    assert "update=backward-prologue" in desc and "phi1-on-the-fly" not in desc
+    u = _dev(U0, "fp32")
+    plan.run("exp_euler", u, 0.0, 3)
+    assert O.rel_l2(_host(u), ref) <= 1e-5
+    plan.close()
