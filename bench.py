@@ -161,14 +161,17 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
     if tile_sweep:
         from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
         v = u0.clone()
-        for reverse, upd in ((False, False), (True, False), (False, True), (True, True)):
-            plan.set_fusion(True, True, reverse, update_in_backward=upd)
-            for cfg in range(NUM_TILE_CONFIGS):
-                for axis in range(len(w.n)):
-                    for fwd in (False, True):
-                        plan.set_tiles(axis, fwd, cfg)
-                plan.set_state(v)
-                plan.run("exp_euler", v, 0.0, 1)
+        fused_ok = prec in ("fp32", "fp64")
+        for reverse in (False, True):
+            for upd, otf in ((False, False), (True, False), (True, True)):
+                plan.set_fusion(True, True, reverse, update_in_backward=upd, phi1_on_the_fly=otf)
+                for fused in ((False, True) if fused_ok else (False,)):
+                    for cfg in range(NUM_TILE_CONFIGS):
+                        for axis in range(len(w.n)):
+                            plan.set_tiles(axis, False, cfg)
+                            plan.set_tiles(axis, True, cfg + (NUM_TILE_CONFIGS if fused else 0))
+                        plan.set_state(v)
+                        plan.run("exp_euler", v, 0.0, 1)
         torch.cuda.synchronize()
     # per-kernel aggregation (kernel instantiation = signature)
     per = {}
