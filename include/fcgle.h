@@ -223,10 +223,10 @@ int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
 /* Choose the tile configuration (0..4; rows x columns per tile depend on the precision and
  * structure, see fcgle_describe) of the mode product on `axis` in direction fwd (1: Q^T, 0: Q).
- * For a forward product of an even/odd FP64 / FP32 plan, cfg 5..9 selects configuration
+ * For a forward product of an even/odd plan, cfg 5..9 selects configuration
  * cfg - 5 in the form that computes both blocks in one tile (one load of each mirrored pair,
  * marked F by fcgle_describe).  Results do not depend on it beyond rounding order.
- * Errors: ERR_ARG, ERR_UNSUPPORTED (cfg >= 5 on another plan). */
+ * Errors: ERR_ARG, ERR_UNSUPPORTED (cfg >= 5 on a dense-structure plan). */
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
 
 /* Structure of the mode products.  Every D_mu is symmetric Toeplitz, hence persymmetric

@@ -1037,7 +1037,7 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
       float best = 1e30f;
       int best_c = plan->cfg[mu][dir];
       // forward even/odd products: also the form with both blocks in one tile
-      const int nform = (dir == 1 && plan->split && (pr == P_F64 || pr == P_F32)) ? 2 : 1;
+      const int nform = (dir == 1 && plan->split) ? 2 : 1;
       bool best_f2 = false;
       for (int form = 0; form < nform; ++form)
         for (int c = 0; c < kNumCfg; ++c) {
@@ -1134,8 +1134,8 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
   const bool f2 = fwd == 1 && cfg >= kNumCfg;
   if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= (fwd ? 2 * kNumCfg : kNumCfg))
     return fail(FCGLE_ERR_ARG, "set_tiles: bad argument");
-  if (f2 && !(plan->split && (pr == P_F64 || pr == P_F32)))
-    return fail(FCGLE_ERR_UNSUPPORTED, "set_tiles: fused forward tiles need an even/odd FP64 / FP32 plan");
+  (void)pr;
+  if (f2 && !plan->split) return fail(FCGLE_ERR_UNSUPPORTED, "set_tiles: fused forward tiles need an even/odd plan");
   if (fwd == 1) plan->fwd2[axis] = f2;
   plan->cfg[axis][fwd] = f2 ? cfg - kNumCfg : cfg;
   if (axis == 0 && fwd == 0) plan->cfg_upd = -1;  // the update-prologue product follows it again

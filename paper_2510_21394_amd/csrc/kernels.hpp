@@ -1232,7 +1232,7 @@ __global__ void __launch_bounds__(T::THREADS)
   using C = float2;
   constexpr int TM = T::TM, TNC = T::TNC, TK = T::TK;
   static_assert(TK % 32 == 0, "k tile");
-  constexpr int NB = (SP == kSplitBwd) ? 2 : 1;
+  constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;
   constexpr int NR = (SP == kDense) ? 1 : 2;
   constexpr int LDK = TK + 8;  // 16-byte pad
   constexpr int LG = 4;        // B loader unit: 4 consecutive k of one column
@@ -1322,6 +1322,9 @@ __global__ void __launch_bounds__(T::THREADS)
         } else if (SP == kSplitFwd) {
           load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+        } else if (SP == kSplitFwd2) {
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
+          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else {
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
@@ -1383,6 +1386,19 @@ __global__ void __launch_bounds__(T::THREADS)
             v[e].y = rb[0][it][e].y + sg * rb[NR - 1][it][e].y;
           }
           put_b(buf, 0, row, kq, v);
+        } else if (SP == kSplitFwd2) {
+          pro_b_unit<C, LG, TL, Pro>(g, a, b, kb, g.me, 0, false, pro, rb[0][it]);
+          pro_b_unit<C, LG, TL, Pro>(g, a, b, kb, g.me, 0, true, pro, rb[NR - 1][it]);
+          C sv[LG], dv[LG];
+#pragma unroll
+          for (int e = 0; e < LG; ++e) {
+            sv[e].x = rb[0][it][e].x + rb[NR - 1][it][e].x;
+            sv[e].y = rb[0][it][e].y + rb[NR - 1][it][e].y;
+            dv[e].x = rb[0][it][e].x - rb[NR - 1][it][e].x;
+            dv[e].y = rb[0][it][e].y - rb[NR - 1][it][e].y;
+          }
+          put_b(buf, 0, row, kq, sv);
+          put_b(buf, NB - 1, row, kq, dv);
         } else {
           put_b(buf, 0, row, kq, rb[0][it]);
           put_b(buf, NB - 1, row, kq, rb[NR - 1][it]);
@@ -1453,7 +1469,15 @@ __global__ void __launch_bounds__(T::THREADS)
   }
 
   auto rowmap = [](int l, int r) { return MfmaT<float>::row(l, r); };
-  if (SP != kSplitBwd) {
+  if (SP == kSplitFwd2) {
+    run_epilogue<float, T, TL>(
+        g, a_fix, c0, m0, g.me, epi, [&](int fm, int fn, int p, int r) { return acc[0][fm][fn][p][r]; }, rowmap,
+        [](int i) { return i; }, smem);
+    run_epilogue<float, T, TL>(
+        g, a_fix, c0, g.me + m0, g.me + g.mo, epi,
+        [&](int fm, int fn, int p, int r) { return acc[NB - 1][fm][fn][p][r]; }, rowmap, [](int i) { return i; },
+        smem);
+  } else if (SP != kSplitBwd) {
     run_epilogue<float, T, TL>(
         g, a_fix, c0, base + m0, base + row_end, epi,
         [&](int fm, int fn, int p, int r) { return acc[0][fm][fn][p][r]; }, rowmap, [](int i) { return i; }, smem);

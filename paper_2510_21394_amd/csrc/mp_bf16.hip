@@ -6,7 +6,7 @@ namespace fcgle {
 template <int NP>
 struct BFK {
   static constexpr bool kUpdate = false;
-  static constexpr bool kFwd2 = false;
+  static constexpr bool kFwd2 = true;  // fused even/odd forward tiles instantiated
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {

@@ -408,7 +408,7 @@ def test_update_in_backward_ignored_where_unsupported(F):
         plan.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n", [(300, 70, 129), (37, 30, 19), (131, 64)], ids=lambda s: "x".join(map(str, s)))
 def test_fused_forward_tiles(F, prec, cfg, n):
@@ -445,7 +445,7 @@ def test_fused_forward_tiles(F, prec, cfg, n):
 def test_fused_forward_tiles_rejected_where_unsupported(F):
     n = (24, 30)
     alpha, h = _setup(n, 73)
-    for prec, split in (("bf16x3", True), ("fp32", False)):
+    for prec, split in (("bf16x3", False), ("fp32", False)):
         plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
         plan.set_structure(split)
         with pytest.raises(F.FcgleError):
