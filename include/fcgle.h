@@ -247,7 +247,7 @@ int fcgle_set_structure(fcgle_plan* plan, int split);
  * on a product along a slow axis.  Bit 3 moves the exponential-Euler update
  * uhat <- E uhat + tau P1 ghat out of the forward operator into the first backward product,
  * which applies it to ghat while loading its tile, stores the new state and contracts it
- * (even/odd FP64 / FP32 plans with d >= 2; otherwise bit 3 is ignored).  Bit 5 (32), with
+ * (even/odd plans with d >= 2; otherwise bit 3 is ignored).  Bit 5 (32), with
  * bit 3: that update forms P1 = phi_1(z) = (e^z - 1)/z in FP64 from separable tables (e^z - 1
  * accumulated from the per-axis expm1 without cancellation) instead of reading the stored P1
  * grid (n_1 <= 512; otherwise ignored).  Bit 4 is reserved.  Default 3; fcgle_autotune picks

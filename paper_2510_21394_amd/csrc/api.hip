@@ -277,9 +277,16 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
 // on-the-fly update (the same budget the kernels are instantiated under: operand tiles with
 // k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows 48-byte rows).
 bool otf_fits(int pr, int cfg) {
-  const size_t r = (pr == P_F64) ? 8 : 4, ldk = 16 + (pr == P_F64 ? 2 : 4);
   const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
-  return 2 * 2 * tm * ldk * r + 2 * 2 * 2 * tnc * ldk * r + (size_t)kOtfMaxRows * 48 <= 163840;
+  size_t ops;
+  if (pr == P_F64 || pr == P_F32) {
+    const size_t r = (pr == P_F64) ? 8 : 4, ldk = 16 + (pr == P_F64 ? 2 : 4);
+    ops = 2 * 2 * tm * ldk * r + 2 * 2 * 2 * tnc * ldk * r;
+  } else {  // split BF16: NP pieces of 2 bytes, k-tiles of 32 padded by 8
+    const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = 40;
+    ops = 2 * 2 * np * tm * ldk * 2 + 2 * 2 * np * 2 * tnc * ldk * 2;
+  }
+  return ops + (size_t)kOtfMaxRows * 48 <= 163840;
 }
 
 // One Tucker operator: out = epi( pro(in) x_1 M_1 ... x_d M_d ) with M = Q^T (fwd) or Q.
@@ -391,8 +398,7 @@ int default_cfg(int pr, int64_t n, bool split) {
 // The exponential-Euler update can run in the loads of the first backward product (axis 0,
 // N loader) when that product is an even/odd FP64 / FP32 one.
 bool update_prologue_ok(const fcgle_plan* P) {
-  const int pr = precision_of(P);
-  return P->split && P->d > 1 && (pr == P_F64 || pr == P_F32) && mp_supported(false, ProKind::Update, EpiKind::Store);
+  return P->split && P->d > 1 && mp_supported(false, ProKind::Update, EpiKind::Store);
 }
 
 // ... and with phi_1 formed on the fly (rows of axis 0 staged in LDS)

@@ -26,7 +26,8 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
     if constexpr (SP == kSplitBwd && K::kUpdate) {
       if (!tl && L.ek == EpiKind::Store) {
         if (L.pk == ProKind::Update) return K::template go<T, false, SP, ProUpdateF<R>, EpiStoreF<R>>(L, s);
-        if constexpr (mp_operand_lds<R, T, SP>() + kOtfMaxRows * sizeof(typename ProUpdateOtfF<R>::RowEnt) <= kLdsBytes)
+        if constexpr (K::template operand_lds<T, SP>() + kOtfMaxRows * sizeof(typename ProUpdateOtfF<R>::RowEnt) <=
+                      kLdsBytes)
           if (L.n <= kOtfMaxRows) return K::template go<T, false, SP, ProUpdateOtfF<R>, EpiStoreF<R>>(L, s);
       }
     }

@@ -1286,6 +1286,19 @@ __global__ void __launch_bounds__(T::THREADS)
 
   v8bf ra[NB][AIT];
   C rb[NR][BIT][LG];
+  // update prologue (ProUpdateF / ProUpdateOtfF, backward split products), as in mp_mfma_tile
+  constexpr bool UPD = Pro::kUpdate;
+  static_assert(!UPD || SP == kSplitBwd, "the update prologue runs on backward even/odd products");
+  typename Pro::Pre rp[UPD ? NR : 1][UPD ? BIT : 1][LG];
+  using ColT = typename UpdColOf<Pro, UPD>::type;
+  ColT eo[UPD ? BIT : 1];
+  using RowT = typename std::conditional_t<UPD, Pro, ProUpdateF<float>>::RowEnt;
+  constexpr int kRows = Pro::kRowLds ? kOtfMaxRows : 1;
+  __shared__ RowT rowtab[kRows];
+  if constexpr (Pro::kRowLds) {
+    for (int k = tid; k < g.n; k += T::THREADS) rowtab[k] = pro.row_entry(k);
+    __syncthreads();
+  }
 
   auto unit_b = [&](int u, int& row, int& kq) {
     if (TL) {
@@ -1325,6 +1338,11 @@ __global__ void __launch_bounds__(T::THREADS)
         } else if (SP == kSplitFwd2) {
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
+        } else if constexpr (UPD) {
+          load_b_unit_clamped<C, LG, TL>(g, U, a, b, kb, g.me, 0, rb[0][it]);
+          load_b_unit_clamped<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, rb[NR - 1][it]);
+          pre_b_unit<C, LG, TL>(g, pro, a, b, kb, g.me, 0, rp[0][it]);
+          pre_b_unit<C, LG, TL>(g, pro, a, b, kb, g.mo, g.me, rp[NR - 1][it]);
         } else {
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
@@ -1400,6 +1418,12 @@ __global__ void __launch_bounds__(T::THREADS)
           put_b(buf, 0, row, kq, sv);
           put_b(buf, NB - 1, row, kq, dv);
         } else {
+          if constexpr (UPD) {
+            // the first row tile writes the updated state; every row tile contracts it
+            upd_b_unit<C, LG, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
+            upd_b_unit<C, LG, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rowtab,
+                                  rb[NR - 1][it]);
+          }
           put_b(buf, 0, row, kq, rb[0][it]);
           put_b(buf, NB - 1, row, kq, rb[NR - 1][it]);
         }
@@ -1456,6 +1480,19 @@ __global__ void __launch_bounds__(T::THREADS)
       }
   };
 
+  if constexpr (UPD) {
+#pragma unroll
+    for (int it = 0; it < BIT; ++it) {
+      const int u = tid + it * T::THREADS;
+      eo[it] = ColT{};
+      if (BU % T::THREADS == 0 || u < BU) {
+        int row, kq;
+        unit_b(u, row, kq);
+        const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
+        if (TL ? a < g.A : b < g.B) eo[it] = pro.col(a, b);
+      }
+    }
+  }
   const int KT = (K + TK - 1) / TK;
   gload(0);
   sstore(0, 0);

@@ -110,7 +110,7 @@ int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
 bool split_supported(int prec);
 
 // True when the fused kernel exists for this (loader, prologue, epilogue) combination
-// (ProKind::Update: backward even/odd FP64 / FP32 products with the N loader only).
+// (ProKind::Update / UpdateOtf: backward even/odd products with the N loader only).
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek);
 
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s);

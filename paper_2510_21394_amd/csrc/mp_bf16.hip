@@ -5,8 +5,14 @@ namespace fcgle {
 
 template <int NP>
 struct BFK {
-  static constexpr bool kUpdate = false;
-  static constexpr bool kFwd2 = true;  // fused even/odd forward tiles instantiated
+  static constexpr bool kUpdate = true;  // ProUpdateF / ProUpdateOtfF instantiated
+  static constexpr bool kFwd2 = true;    // fused even/odd forward tiles instantiated
+  // LDS of the operand tiles of mp_bf16_kernel: NP pieces, k-tiles of TK padded by 8
+  template <class T, int SP>
+  static constexpr size_t operand_lds() {
+    constexpr size_t NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1, LDK = T::TK + 8;
+    return 2 * NB * NP * T::TM * LDK * 2 + 2 * NB * NP * 2 * T::TNC * LDK * 2;
+  }
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {

@@ -6,6 +6,10 @@ namespace fcgle {
 struct F32K {
   static constexpr bool kUpdate = true;  // ProUpdateF instantiated
   static constexpr bool kFwd2 = true;    // fused even/odd forward tiles instantiated
+  template <class T, int SP>
+  static constexpr size_t operand_lds() {
+    return mp_operand_lds<float, T, SP>();
+  }
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
   static hipError_t go(const MPLaunch& L, hipStream_t s) {

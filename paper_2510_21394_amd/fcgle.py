@@ -200,7 +200,7 @@ class Plan:
         """Fuse the nonlinearity into the first / the pointwise epilogue into the last mode
         product; reverse: run forward operators from the last axis to the first;
         update_in_backward: apply the exponential-Euler update in the loads of the first
-        backward product instead (even/odd fp64 / fp32 plans, d >= 2); phi1_on_the_fly: that
+        backward product instead (even/odd plans, d >= 2); phi1_on_the_fly: that
         update forms phi_1 from separable tables instead of reading the grid (n_1 <= 512)."""
         L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)
                                           | (4 if reverse else 0) | (8 if update_in_backward else 0)

@@ -327,7 +327,7 @@ def test_autotuned_exp_euler_matches_oracle(F):
 
 
 @pytest.mark.parametrize("otf", [False, True], ids=["p1grid", "p1otf"])
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3", "bf16x6"])
 @pytest.mark.parametrize("cfg", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("n", [(150, 21, 26), (37, 30, 19), (131, 64)], ids=lambda s: "x".join(map(str, s)))
 def test_update_in_backward_prologue(F, prec, cfg, n, otf):
@@ -335,7 +335,8 @@ def test_update_in_backward_prologue(F, prec, cfg, n, otf):
     (fusion bit 3), in every tile configuration of that product: odd and even axis lengths,
     ragged column tiles, and two row tiles per column (n0 = 150 and 131 with 64-row tiles), where
     only the first row tile stores the new state; phi_1 read from the grid or formed on the fly
-    (the FP64 128x64 tile has no LDS left for the staged rows and reads the grid).  Against the
+    (the FP64 128x64 and split-BF16x6 128x16 tiles have no LDS left for the staged rows and read
+    the grid).  Against the
     oracle trajectory, and the timing record shows the update prologue on the axis-0 backward
     product."""
     alpha, h = _setup(n, 31)
@@ -358,7 +359,7 @@ def test_update_in_backward_prologue(F, prec, cfg, n, otf):
     print(f"[update prologue {prec} cfg{cfg} {n}] rel_l2 = {err:.3e}")
     assert err <= TOL_OP[prec]
     pro = {F.fcgle.decode_signature(r[2])["prologue"] for r in rec if r[0] == 0 and r[1] == 0}
-    grid_only = not otf or (prec == "fp64" and cfg == 4)
+    grid_only = not otf or (prec, cfg) in (("fp64", 4), ("bf16x6", 2))
     assert pro == {"exp_euler_update" if grid_only else "exp_euler_update_otf"}
     epi = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[1] == 1}
     assert epi == {"store"}
@@ -389,9 +390,9 @@ def test_update_modes_interleave(F, prec):
 
 
 def test_update_in_backward_ignored_where_unsupported(F):
-    """1-D plans (no N-loader backward product) and dense / split-BF16 plans keep the
-    epilogue form when bit 3 is set; results still match the oracle."""
-    cases = [((300,), "fp64", True), ((24, 30), "fp32", False), ((24, 30), "bf16x6", True)]
+    """1-D plans (no N-loader backward product) and dense-structure plans keep the epilogue
+    form when bit 3 is set; results still match the oracle."""
+    cases = [((300,), "fp64", True), ((24, 30), "fp32", False), ((24, 30), "bf16x6", False)]
     for n, prec, split in cases:
         alpha, h = _setup(n, 51)
         tau = 2e-3
