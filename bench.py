@@ -402,6 +402,8 @@ def main():
             "hbm_frac": dom["achieved_gbs"] / HBM_PEAK_GBS,
         }),
         "variants": {p: {k: v for k, v in d.items() if k != "kernels"} for p, d in variants.items()},
+        "speedup_over_fp64": ({p: d["steps_per_s"] / variants["fp64"]["steps_per_s"] for p, d in variants.items()}
+                              if "fp64" in variants else None),
         "kernels": head["kernels"],
     }
     if not a.no_extras:

@@ -36,7 +36,10 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   if (!tl) {
     if (L.pk != ProKind::Id) {
       if constexpr (SP != kSplitBwd)
-        if (L.ek == EpiKind::Store) return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+        if (L.ek == EpiKind::Store) {
+          if (L.pp.ns == 0 && !L.pp.up) return K::template go<T, false, SP, ProNonlinF<R, true>, EpiStoreF<R>>(L, s);
+          return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+        }
       return hipErrorInvalidValue;
     }
     switch (L.ek) {
@@ -61,7 +64,10 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   }
   if (L.pk != ProKind::Id) {
     if constexpr (SP != kSplitBwd)
-      if (L.ek == EpiKind::Store) return K::template go<T, true, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+      if (L.ek == EpiKind::Store) {
+        if (L.pp.ns == 0 && !L.pp.up) return K::template go<T, true, SP, ProNonlinF<R, true>, EpiStoreF<R>>(L, s);
+        return K::template go<T, true, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
+      }
     return hipErrorInvalidValue;
   }
   switch (L.ek) {

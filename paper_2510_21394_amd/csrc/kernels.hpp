@@ -91,7 +91,9 @@ struct ProIdF {
 
 // out = cu u + cp up + cg g(t, e),  e = eu u + ep up,
 // g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc_k S_k[j]   (Section 2, the map g)
-template <class R>
+// Plain: no previous state and no source terms (up == nullptr, ns == 0), so no per-element
+// index arithmetic or extra loads.
+template <class R, bool Plain = false>
 struct ProNonlinF {
   static constexpr bool kId = false;
   static constexpr bool kUpdate = false;
@@ -121,21 +123,32 @@ struct ProNonlinF {
     cg = (R)p.cg;
   }
   __device__ __forceinline__ C operator()(int64_t j, C u) const {
-    C p = {0, 0};
-    if (up) p = up[j];
-    const R er = eu * u.x + ep * p.x, ei = eu * u.y + ep * p.y;
-    const R m = er * er + ei * ei;
-    R gr = gamma * er - m * (kre * er - kim * ei);
-    R gi = gamma * ei - m * (kre * ei + kim * er);
-    for (int k = 0; k < ns; ++k) {
-      const C s = S[k][j];
-      gr += sc[k] * s.x;
-      gi += sc[k] * s.y;
+    if constexpr (Plain) {
+      const R er = eu * u.x, ei = eu * u.y;
+      const R m = er * er + ei * ei;
+      const R gr = gamma * er - m * (kre * er - kim * ei);
+      const R gi = gamma * ei - m * (kre * ei + kim * er);
+      C o;
+      o.x = cu * u.x + cg * gr;
+      o.y = cu * u.y + cg * gi;
+      return o;
+    } else {
+      C p = {0, 0};
+      if (up) p = up[j];
+      const R er = eu * u.x + ep * p.x, ei = eu * u.y + ep * p.y;
+      const R m = er * er + ei * ei;
+      R gr = gamma * er - m * (kre * er - kim * ei);
+      R gi = gamma * ei - m * (kre * ei + kim * er);
+      for (int k = 0; k < ns; ++k) {
+        const C s = S[k][j];
+        gr += sc[k] * s.x;
+        gi += sc[k] * s.y;
+      }
+      C o;
+      o.x = cu * u.x + cp * p.x + cg * gr;
+      o.y = cu * u.y + cp * p.y + cg * gi;
+      return o;
     }
-    C o;
-    o.x = cu * u.x + cp * p.x + cg * gr;
-    o.y = cu * u.y + cp * p.y + cg * gi;
-    return o;
   }
 };
 

@@ -472,3 +472,23 @@ def test_phi1_on_the_fly_ignored_for_long_first_axis(F):
     plan.run("exp_euler", u, 0.0, 3)
     assert O.rel_l2(_host(u), ref) <= 1e-5
     plan.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-13), ("fp32", 2e-6)])
+def test_dispersive_exponential_conserves_norm(F, prec, tol):
+    """With nu = 0 the exponential e^{theta i eta K} is unitary (K symmetric): the GPU result keeps
+    the L2 norm of its input to rounding, for every structure."""
+    n = (40, 33, 28)
+    alpha, h = _setup(n, 91)
+    params = (0.0, 0.7, 0.0, 0.0, 0.4)
+    V = random_complex(n, 92)
+    ref = O.Problem(n, alpha, h, params).f("exp", 0.05, V)
+    for split in (True, False):
+        plan = F.Plan(n, alpha, h, params, tau=1e-3, precision=prec)
+        plan.set_structure(split)
+        out = _host(plan.apply_f("exp", 0.05, _dev(V, prec)))
+        drift = abs(np.linalg.norm(out) / np.linalg.norm(V) - 1.0)
+        print(f"[unitary {prec} split={split}] norm drift = {drift:.3e}")
+        assert drift <= tol
+        assert O.rel_l2(out, ref) <= TOL_OP[prec]
+        plan.close()
