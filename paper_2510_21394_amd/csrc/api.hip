@@ -396,7 +396,7 @@ int default_cfg(int pr, int64_t n, bool split) {
 }
 
 // The exponential-Euler update can run in the loads of the first backward product (axis 0,
-// N loader) when that product is an even/odd FP64 / FP32 one.
+// N loader) when that product is an even/odd one (any precision).
 bool update_prologue_ok(const fcgle_plan* P) {
   return P->split && P->d > 1 && mp_supported(false, ProKind::Update, EpiKind::Store);
 }
