@@ -260,7 +260,6 @@ int get_graph(BatchData* B, int64_t steps, hipGraphExec_t* out) {
 }
 
 constexpr int64_t kGraphChunk = 500;  // steps per captured graph (longer runs replay it)
-constexpr int kGroupCfg = 3;          // tile configurations of the grouped kernels (group_f32.hip)
 
 int batch_run_impl(fcgle_plan* P, void* const* u, int64_t nsteps, hipStream_t st) {
   BatchData* B = P->batch;
@@ -390,7 +389,7 @@ int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
   std::string s = "batch count=" + std::to_string(B->count) + " n in [" + std::to_string(nmin) + "," +
                   std::to_string(nmax) + "] precision=fp32 structure=even-odd tiles(rows)=";
   for (int p = 0; p < PH_COUNT; ++p)
-    s += std::string(names[p]) + ":" + std::to_string(cfg_rows(P_F32, B->ph[p].cfg, 1)) +
+    s += std::string(names[p]) + ":" + std::to_string(group_cfg_rows(B->ph[p].cfg)) +
          (B->ph[p].sp == kSplitFwd2 ? "F" : "") + (p + 1 < PH_COUNT ? "," : "");
   s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
   char tail[96];

@@ -54,13 +54,17 @@ bool with_combo(bool tl, ProKind pk, EpiKind ek, int sp, F&& f) {
   return true;
 }
 
-// The FP32 tile configurations of the even/odd kernels.
+// The FP32 tile configurations of the grouped even/odd kernels (rows x complex columns x k,
+// waves): the 64-row tiles waste fewer padded rows on the half-block lengths 48..256 of
+// the batched instances.
 template <class F>
 bool with_cfg(int cfg, F&& f) {
   switch (cfg) {
     case 0: f(TileCfg<128, 64, 16, 2, 2>{}); return true;
     case 1: f(TileCfg<64, 64, 16, 1, 2>{}); return true;
     case 2: f(TileCfg<128, 32, 16, 2, 2>{}); return true;
+    case 3: f(TileCfg<64, 64, 16, 2, 2>{}); return true;
+    case 4: f(TileCfg<64, 128, 16, 1, 4>{}); return true;
     default: return false;
   }
 }
@@ -96,6 +100,12 @@ __global__ void __launch_bounds__(256)
 }
 
 }  // namespace
+
+int group_cfg_rows(int cfg) {
+  int r = 0;
+  with_cfg(cfg, [&](auto t) { r = decltype(t)::TM; });
+  return r;
+}
 
 bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd) {
   return with_combo(tloader, pk, ek, fwd ? kSplitFwd : kSplitBwd, [](auto) {});

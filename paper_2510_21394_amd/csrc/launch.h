@@ -131,6 +131,8 @@ inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
 // backward).  Supported: forward (N loader, Nonlin or Id, Store), (T loader, Id, Store or
 // ExpEuler); backward (either loader, Id, Store).
 bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd);
+constexpr int kGroupCfg = 5;  // tile configurations of the grouped kernels
+int group_cfg_rows(int cfg);   // rows per tile of grouped configuration cfg
 size_t group_item_bytes(ProKind pk, EpiKind ek);
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host);
