@@ -106,3 +106,35 @@ def test_adjoint_missing_conjugate_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "expeuler_vjp", bad)
     assert _fails(pins.test_exp_euler_adjoint_matches_central_differences)
+
+
+def test_flow_phi1_argument_slip_is_caught(monkeypatch):
+    # phi_1(gamma t) instead of phi_1(2 gamma t) in the exact nonlinear flow
+    def bad(W, t, params):
+        _, _, gamma, kappa, zeta = params
+        tp1 = t * O.phi(1, np.array([gamma * t])).real[0]
+        m = np.abs(W) ** 2
+        return np.exp(t * gamma - (kappa + 1j * zeta) / (2.0 * kappa) * np.log(1.0 + 2.0 * tp1 * kappa * m)) * W
+
+    monkeypatch.setattr(O, "nonlinear_flow", bad)
+    assert _fails(pins.test_nonlinear_flow_solves_its_ode, (0.0, 0.0, 1.0, 1.0, 2.0))
+
+
+def test_flow_phase_sign_is_caught(monkeypatch):
+    orig = O.nonlinear_flow
+
+    def bad(W, t, params):
+        nu, eta, gamma, kappa, zeta = params
+        return orig(W, t, (nu, eta, gamma, kappa, -zeta))
+
+    monkeypatch.setattr(O, "nonlinear_flow", bad)
+    assert _fails(pins.test_nonlinear_flow_solves_its_ode, (0.0, 0.0, 1.3, 0.0, 0.9))
+
+
+def test_strang_full_step_flows_are_caught(monkeypatch):
+    # both nonlinear substeps taken with tau instead of tau / 2
+    def bad(P, U, t, tau):
+        return O.nonlinear_flow(P.f("exp", tau, O.nonlinear_flow(U, tau, P.params)), tau, P.params)
+
+    monkeypatch.setattr(O, "step_strang", bad)
+    assert _fails(pins.test_strang_is_second_order_against_the_ode_solution)

@@ -266,3 +266,77 @@ def test_exp_euler_adjoint_matches_central_differences():
               - _loss(PARAMS, U0 - fd_h * dlt, n, alpha, h, target, tau, steps)) / (2 * fd_h)
         an = float(np.real(np.vdot(ubar0, dlt)))
         assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-3), (fd, an)
+
+
+# --- Strang splitting (Section 4, eq. Strang) ----------------------------------------------
+
+def _ode_solution(rhs, y0, T):
+    """Adaptive 8th-order Runge-Kutta (scipy DOP853) on the real view of a complex system."""
+    from scipy.integrate import solve_ivp
+    y0 = np.asarray(y0, np.complex128)
+    shape = y0.shape
+
+    def f(_, y):
+        w = (y[: y.size // 2] + 1j * y[y.size // 2:]).reshape(shape)
+        d = rhs(w).ravel()
+        return np.concatenate([d.real, d.imag])
+
+    sol = solve_ivp(f, (0.0, T), np.concatenate([y0.real.ravel(), y0.imag.ravel()]), method="DOP853",
+                    rtol=1e-13, atol=1e-15)
+    assert sol.success
+    y = sol.y[:, -1]
+    return (y[: y.size // 2] + 1j * y[y.size // 2:]).reshape(shape)
+
+
+@pytest.mark.parametrize("params", [(0.0, 0.0, 1.0, 1.0, 2.0), (0.0, 0.0, -0.7, 0.4, -1.3),
+                                    (0.0, 0.0, 0.0, 0.8, 0.5), (0.0, 0.0, 1.3, 0.0, 0.9),
+                                    (0.0, 0.0, 0.0, 0.0, 1.0)])
+def test_nonlinear_flow_solves_its_ode(params):
+    _, _, gamma, kappa, zeta = params
+    W0 = 1.5 * random_complex((40,), 3)
+    for t in (0.05, 0.7):
+        ref = _ode_solution(lambda w: gamma * w - (kappa + 1j * zeta) * np.abs(w) ** 2 * w, W0, t)
+        assert O.rel_l2(O.nonlinear_flow(W0, t, params), ref) <= 1e-11
+
+
+def test_nonlinear_flow_is_a_semigroup():
+    params = (0.3, 0.2, 0.9, 0.6, -1.1)
+    W0 = 2.0 * random_complex((5, 6), 4)
+    a = O.nonlinear_flow(O.nonlinear_flow(W0, 0.13, params), 0.29, params)
+    assert O.rel_l2(a, O.nonlinear_flow(W0, 0.42, params)) <= 1e-14
+
+
+def test_strang_conserves_the_norm_when_dispersive():
+    # nu = gamma = kappa = 0, s = 0: e^{tau K} is unitary (i eta D anti-Hermitian) and the flow is
+    # a pointwise phase, so every Strang step keeps the L2 norm up to rounding
+    params = (0.0, 1.0, 0.0, 0.0, 1.0)
+    n = (16, 12)
+    axes = grid_axes(n, ((-10.0, 10.0),) * 2)
+    U0 = sech_product(axes, (1.0, 1.0))
+    P = O.Problem(n, (1.2, 1.8), [20.0 / 17, 20.0 / 13], params)
+    U = O.run(P, "strang", U0, 0.05, 40)
+    assert abs(np.linalg.norm(U) / np.linalg.norm(U0) - 1.0) <= 1e-13
+
+
+def test_strang_is_second_order_against_the_ode_solution():
+    # the paper's second example (no source) on a small grid; reference: the semi-discrete ODE
+    # u' = K u + g(u) integrated by an adaptive solver with K assembled densely
+    params = (1.0, 1.0, 1.0, 1.0, 1.0)
+    n = (10, 12)
+    dom = ((-10.0, 10.0),) * 2
+    h = [(b - a) / (m + 1) for (a, b), m in zip(dom, n)]
+    U0 = sech_product(grid_axes(n, dom), (1.0, 1.0))
+    P = O.Problem(n, (1.2, 1.8), h, params)
+    K = O.kron_sum(P.Ds, params)
+    T = 0.5
+    ref = _ode_solution(lambda w: (K @ w.ravel()).reshape(n) + O.g_nonlin(0.0, w, params), U0, T)
+    taus = [0.1, 0.05, 0.025, 0.0125]
+    errs = [O.rel_l2(O.run(P, "strang", U0, tau, int(round(T / tau))), ref) for tau in taus]
+    slopes = np.diff(np.log(errs)) / np.diff(np.log(taus))
+    assert abs(slopes[-1] - 2.0) <= 0.1, (errs, slopes)
+
+
+def test_strang_rejects_a_source():
+    P, U0 = _manufactured((6, 5), ((-8.0, 8.0),) * 2, (1.3, 1.6))
+    with pytest.raises(ValueError):
+        O.step_strang(P, U0, 0.0, 0.01)
