@@ -322,6 +322,39 @@ def refine_timing(w, U0, reps=5):
     return out
 
 
+def strang_timing():
+    """Context: Strang splitting on the paper's Example 2 in 3-D at 256^3 (T = 1: 100 steps of
+    tau = 1e-2) with FP32-MFMA and FP64-MFMA plans (autotuned tiles); steps/s of each and the
+    relative L2 difference of the two results at T."""
+    import torch
+    import workloads as W
+    from paper_2510_21394_amd import Plan
+    w = W.strang_3d()
+    U0 = W.u0_strang(w)
+    out = {"workload": w.name, "steps": w.steps}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        plan = Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
+        plan.autotune(3)
+        u = torch.from_numpy(U0).to(dt).cuda()
+        plan.run("strang", u.clone(), 0.0, 5)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run("strang", u, 0.0, w.steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{prec}_steps_per_s"] = w.steps / el
+        out[f"{prec}_ms_per_step"] = 1e3 * el / w.steps
+        res[prec] = u.to(torch.complex128)
+        plan.close()
+    out["rel_l2_fp32_vs_fp64_at_T"] = float(torch.linalg.vector_norm(res["fp32"] - res["fp64"]) /
+                                            torch.linalg.vector_norm(res["fp64"]))
+    del res
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
     """The FP64 oracle as it stands, timed on the host cores (bounded sample of the workload)."""
     from oracle import fcgle_oracle as O
@@ -407,9 +440,12 @@ def main():
         "kernels": head["kernels"],
     }
     if not a.no_extras:
-        line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing(), "refine": refine_timing(w, U0)}
+        line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing(), "refine": refine_timing(w, U0),
+                           "strang": strang_timing()}
         print(f"# batch: {line['context']['batch']['steps_per_s']:.1f} steps/s; adjoint backward/forward = "
-              f"{line['context']['adjoint']['backward_over_forward']:.2f}", file=sys.stderr, flush=True)
+              f"{line['context']['adjoint']['backward_over_forward']:.2f}; strang 256^3 FP32 "
+              f"{line['context']['strang']['fp32_steps_per_s']:.1f} steps/s, FP64 "
+              f"{line['context']['strang']['fp64_steps_per_s']:.1f}", file=sys.stderr, flush=True)
     if not a.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, U0)
     print(json.dumps(line, default=lambda o: list(o) if isinstance(o, (set, tuple)) else str(o)))

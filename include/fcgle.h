@@ -71,7 +71,10 @@ typedef enum {
   FCGLE_EXP_EULER = 0, /* u+ = e^{tau K} u + tau phi_1(tau K) g(t, u)                      */
   FCGLE_LAWSON = 1,    /* u+ = e^{tau K} (u + tau g(t, u))                                  */
   FCGLE_LIE = 2,       /* backward-forward Euler (Section 4): (I - tau K) u+ = u + tau g(t, u) */
-  FCGLE_LBDF2 = 3      /* linearised BDF2 with BFE start (Section 4, eq. lbdf2-v)          */
+  FCGLE_LBDF2 = 3,     /* linearised BDF2 with BFE start (Section 4, eq. lbdf2-v)          */
+  FCGLE_STRANG = 4     /* Strang splitting (Section 4, eq. Strang):
+                          u+ = phi_{tau/2}(e^{tau K} phi_{tau/2}(u)), phi_t the exact flow of
+                          w' = gamma w - (kappa + i zeta)|w|^2 w; no source term            */
 } fcgle_scheme;
 
 /* Arithmetic of the mode-product contractions.  Setup (weights, eigenpairs,
@@ -164,10 +167,19 @@ int fcgle_set_state(fcgle_plan* plan, const void* u_dev, const void* u_prev_dev,
  * same u_dev, so a steady-state step costs one forward and one backward Tucker
  * operator; the first step on a buffer (or after fcgle_set_state) adds one
  * forward transform.  FCGLE_LBDF2 takes the BFE start when it has no history
- * for u_dev and keeps u_{n-1} in the plan afterwards.  Errors: ERR_ARG, ERR_HIP. */
+ * for u_dev and keeps u_{n-1} in the plan afterwards.  FCGLE_STRANG keeps no state: a step
+ * is the exact flow over tau/2, e^{tau K} as Q (E . (Q^T v)) with the separable E in the last
+ * forward epilogue, and the flow over tau/2 again (streaming passes, or fused with fusion
+ * bit 6); with fusion bit 1 its forward products run from the last axis to the first whatever
+ * bit 2 says (the E epilogue is cheapest on axis 0).  A plan with a source term gives
+ * ERR_UNSUPPORTED for it.
+ * Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_HIP. */
 int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, void* stream);
 
-/* nsteps consecutive fcgle_step calls from t0 (t_k = t0 + k tau). */
+/* nsteps consecutive fcgle_step calls from t0 (t_k = t0 + k tau).  For FCGLE_STRANG the
+ * trailing flow over tau/2 of each step and the leading one of the next run as one flow over
+ * tau (the flow of an autonomous equation composes exactly), so intermediate states are not
+ * formed; the result equals nsteps single steps up to rounding. */
 int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps,
               void* stream);
 
@@ -250,8 +262,12 @@ int fcgle_set_structure(fcgle_plan* plan, int split);
  * (even/odd plans with d >= 2; otherwise bit 3 is ignored).  Bit 5 (32), with
  * bit 3: that update forms P1 = phi_1(z) = (e^z - 1)/z in FP64 from separable tables (e^z - 1
  * accumulated from the per-axis expm1 without cancellation) instead of reading the stored P1
- * grid (n_1 <= 512; otherwise ignored).  Bit 4 is reserved.  Default 3; fcgle_autotune picks
- * them by timing whole exponential-Euler steps.  Errors: ERR_ARG. */
+ * grid (n_1 <= 512; otherwise ignored).  Bit 6 (64) fuses the exact nonlinear flows of
+ * FCGLE_STRANG into the first forward / the last backward mode product (cleared: streaming
+ * passes, which are the faster form on MI355X at 256^3 since the flow's log1p and sincos would
+ * stall the contraction).  Bit 4 is reserved.  Default 3; fcgle_autotune picks bits 0-5 by
+ * timing whole exponential-Euler steps (and sets bit 1 when the update runs in the backward
+ * prologue, where it has no effect on exponential Euler).  Errors: ERR_ARG. */
 int fcgle_set_fusion(fcgle_plan* plan, int flags);
 
 /* Human-readable plan summary (sizes, precision, chosen tiles) into buf. */
@@ -267,12 +283,14 @@ int fcgle_timing_enable(fcgle_plan* plan, int capacity);
  * record.  For launch i < *count (at most cap): axis[i] = mode axis (0-based),
  * fwd[i] = 1 for a Q^T (forward) and 0 for a Q (backward) mode product, ms[i] =
  * its duration, sig[i] = the kernel instantiation it ran:
- *   sig = structure * 2048 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 4 + prologue) * 8 + epilogue
+ *   sig = structure * 4096 + (((prec * 8 + tile_cfg) * 2 + t_loader) * 8 + prologue) * 8 + epilogue
  * (structure 0 dense, 1 even/odd Q^T, 2 even/odd Q, 3 even/odd Q^T with both blocks per tile;
  * prec 0..3 as fcgle_precision;
  * t_loader 1 for the fastest axis; prologue 0 none, 1 nonlinearity, 2 exponential-Euler
- * update, 3 the same with phi_1 on the fly; epilogue 0 store, 1 grid, 2 separable exp, 3 exp-Euler update,
- * 4 keep-old, 5 exp-Euler update with adjoint record).  Errors: ERR_STATE if timing is off, ERR_HIP. */
+ * update, 3 the same with phi_1 on the fly, 4 exact nonlinear flow (Strang); epilogue 0 store,
+ * 1 grid, 2 separable exp, 3 exp-Euler update, 4 keep-old, 5 exp-Euler update with adjoint
+ * record, 6 FP64 axpy (refinement residual), 7 exact nonlinear flow (Strang)).
+ * Errors: ERR_STATE if timing is off, ERR_HIP. */
 int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, double* ms,
                       int64_t* count);
 

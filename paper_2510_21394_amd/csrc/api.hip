@@ -239,7 +239,7 @@ int launch_timed(fcgle_plan* P, const MPLaunch& L, int axis, hipStream_t st) {
     tl.e1 = P->ev_pool[2 * P->timed.size() + 1];
     tl.axis = axis;
     tl.fwd = L.split ? (L.split != 2 ? 1 : 0) : (L.M == P->Mf[axis] ? 1 : 0);
-    tl.sig = L.split * 2048 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 4 + (int)L.pk) * 8) + (int)L.ek;
+    tl.sig = L.split * 4096 + ((((L.prec * 8 + L.cfg) * 2 + (L.B == 1 ? 1 : 0)) * 8 + (int)L.pk) * 8) + (int)L.ek;
     HIP_TRY(hipEventRecord(tl.e0, st));
   }
   HIP_TRY(launch_mode_product(L, st));
@@ -323,18 +323,20 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
         L.pp.sep.mu = mu;
         if (P->cfg_upd >= 0) L.cfg = P->cfg_upd;
         if (pk == ProKind::UpdateOtf && !otf_fits(L.prec, L.cfg)) L.pk = ProKind::Update;  // reads the P1 grid
-      } else if ((P->fusion & 1) && mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
+      } else if ((pk == ProKind::Flow ? (P->fusion & 64) : (P->fusion & 1)) &&
+                 mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
         L.pk = pk;
         L.pp = pp;
       } else {
         void* t = pick(cur);
-        HIP_TRY(launch_pointwise_pro(pr, P->N, cur, t, pp, st));
+        HIP_TRY(launch_pointwise_pro(pr, P->N, cur, t, pk, pp, st));
         L.in = t;
       }
     }
     if (last) {
       ep.sep.mu = mu;
-      if ((ek == EpiKind::Store || (P->fusion & 2)) && mp_supported(tl, L.pk, ek)) {
+      const int epi_bit = (ek == EpiKind::Flow) ? 64 : 2;
+      if ((ek == EpiKind::Store || (P->fusion & epi_bit)) && mp_supported(tl, L.pk, ek)) {
         L.ek = ek;
         L.ep = ep;
         FC_TRY(launch_timed(P, L, mu, st));
@@ -445,7 +447,59 @@ int expeuler_body(fcgle_plan* P, void* u, double t, hipStream_t st) {
   return FCGLE_OK;
 }
 
+// Scalars of the exact flow over a time t of w' = gamma w - (kappa + i zeta)|w|^2 w
+// (Section 4, Strang splitting), in FP64: t phi_1(2 gamma t) = t (e^x - 1)/x with x = 2 gamma t
+// (expm1 keeps it accurate for small x), e^{gamma t}, 2 kappa, zeta.
+FlowParams flow_params(const fcgle_plan* P, double t) {
+  FlowParams f;
+  const double x = 2.0 * P->p.gamma * t;
+  f.tp1 = (x == 0.0) ? t : t * std::expm1(x) / x;
+  f.eg = std::exp(P->p.gamma * t);
+  f.k2 = 2.0 * P->p.kappa;
+  f.zeta = P->p.zeta;
+  return f;
+}
+
+// nsteps Strang steps (Section 4, eq. Strang) on u in place.  The e^{tau K} substep runs as
+// Q (E . (Q^T v)) with the separable E in the last forward epilogue.  The trailing flow over
+// tau/2 of one step and the leading one of the next merge into a single flow over tau
+// (phi_{tau/2} o phi_{tau/2} = phi_tau, the flow of an autonomous equation), so a call runs
+// phi_{tau/2}, then per step the exponential substep followed by phi_tau, or phi_{tau/2} after
+// its last step; only the state at the end of the call is observable.  The flows run as
+// streaming passes unless fusion bit 6 puts them into the first forward / last backward product
+// (measured at 256^3: the fused flow's log1p and sincos add more to the product than a
+// streaming pass costs).
+int strang_run(fcgle_plan* P, void* u, int64_t nsteps, hipStream_t st) {
+  if (P->ns > 0) return fail(FCGLE_ERR_UNSUPPORTED, "Strang splitting: the exact nonlinear flow takes no source term");
+  P->uhat_valid = false;
+  P->hist_valid = false;
+  const double tau = P->tau;
+  ProParams pp;
+  pp.flow = flow_params(P, 0.5 * tau);
+  const FlowParams full = flow_params(P, tau);
+  EpiParams ep;
+  ep.out = P->s[2];
+  FC_TRY(get_sep(P, tau, &ep.sep));
+  // A fused separable exponential is cheapest in the epilogue of an N-loader product (no LDS
+  // staging), so the forward products run from the last axis to the first and end on axis 0.
+  struct RevGuard {
+    fcgle_plan* P;
+    bool saved;
+    ~RevGuard() { P->fwd_rev = saved; }
+  } rev_guard{P, P->fwd_rev};
+  if (P->fusion & 2) P->fwd_rev = true;
+  for (int64_t k = 0; k < nsteps; ++k) {
+    FC_TRY(tucker(P, true, u, k == 0 ? ProKind::Flow : ProKind::Id, pp, EpiKind::Sep, ep, P->s[0], P->s[1], st));
+    EpiParams eb;
+    eb.out = u;
+    eb.flow = (k + 1 == nsteps) ? pp.flow : full;
+    FC_TRY(tucker(P, false, P->s[2], ProKind::Id, ProParams(), EpiKind::Flow, eb, P->s[0], P->s[1], st));
+  }
+  return FCGLE_OK;
+}
+
 int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
+  if (scheme == FCGLE_STRANG) return strang_run(P, u, 1, st);
   FC_TRY(ensure_state_buffers(P));
   const double tau = P->tau;
   if (scheme == FCGLE_EXP_EULER) {
@@ -980,7 +1034,7 @@ int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, 
   if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
   if (!std::isfinite(t)) return fail(FCGLE_ERR_ARG, "t not finite");
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   DeviceGuard g(plan->device);
   return step_impl(plan, scheme, u_dev, t, as_stream(stream));
 }
@@ -988,6 +1042,13 @@ int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, 
 int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps, void* stream) {
   FC_TRY(check_plan(plan));
   if (nsteps < 0) return fail(FCGLE_ERR_ARG, "nsteps < 0");
+  if (scheme == FCGLE_STRANG && nsteps > 0) {
+    if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+    if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+    if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
+    DeviceGuard g(plan->device);
+    return strang_run(plan, u_dev, nsteps, as_stream(stream));
+  }
   for (int64_t k = 0; k < nsteps; ++k) FC_TRY(fcgle_step(plan, scheme, u_dev, t0 + (double)k * tau, tau, stream));
   return FCGLE_OK;
 }
@@ -1105,6 +1166,10 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
     }
   (void)pr;
   plan->fwd_rev = best_rev;
+  // with the update in the backward prologue the last forward product of an exponential-Euler
+  // step only stores, so bit 1 has no effect there; set it for the separable-exponential
+  // epilogue of the Lawson and Strang forward operators (fused is the faster form of it)
+  if (best_fusion & 8) best_fusion |= 2;
   plan->fusion = best_fusion;
   plan->cfg_upd = best_cfg_upd;
   return FCGLE_OK;
@@ -1167,9 +1232,9 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
 
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
-  if (flags < 0 || flags > 47 || (flags & 16))
-    return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15, optionally with bit 5 (32)");
-  plan->fusion = flags & 43;
+  if (flags < 0 || flags > 111 || (flags & 16))
+    return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15, optionally with bits 5 (32) and 6 (64)");
+  plan->fusion = flags & 107;
   plan->fwd_rev = (flags & 4) != 0;
   return FCGLE_OK;
 }
@@ -1190,7 +1255,8 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
          (plan->split && plan->fwd2[m] ? "F" : "") + "]";
   }
   s += plan->split ? " structure=even-odd" : " structure=dense";
-  s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-");
+  s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-") +
+       ((plan->fusion & 64) ? "/flows" : "");
   if (plan->fusion & 8) {
     if (update_prologue_ok(plan)) {
       const int c = plan->cfg_upd >= 0 ? plan->cfg_upd : plan->cfg[0][0];
@@ -1250,7 +1316,7 @@ int fcgle_vjp_run(fcgle_plan* plan, int scheme, const void* u_start_dev, int64_t
   if (m < 0) return fail(FCGLE_ERR_ARG, "vjp: m < 0");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
   if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
   if (u_start_dev == ubar_dev) return fail(FCGLE_ERR_ARG, "vjp: u_start and ubar must be distinct buffers");
   DeviceGuard g(plan->device);
@@ -1264,7 +1330,7 @@ int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* uba
   if (u_n_dev == ubar_n_dev || u_n_dev == ubar_next_dev)
     return fail(FCGLE_ERR_ARG, "vjp: u_n must not alias a cotangent buffer");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_LBDF2) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
   if (ubar_n_dev != ubar_next_dev) {
     DeviceGuard g(plan->device);

@@ -37,6 +37,7 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
     if (L.pk != ProKind::Id) {
       if constexpr (SP != kSplitBwd)
         if (L.ek == EpiKind::Store) {
+          if (L.pk == ProKind::Flow) return K::template go<T, false, SP, ProFlowF<R>, EpiStoreF<R>>(L, s);
           if (L.pp.ns == 0 && !L.pp.up) return K::template go<T, false, SP, ProNonlinF<R, true>, EpiStoreF<R>>(L, s);
           return K::template go<T, false, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
         }
@@ -58,6 +59,9 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
         if constexpr (SP == kDense && std::is_same<R, double>::value)
           return K::template go<T, false, SP, ProIdF, EpiAxpyF<R>>(L, s);
         return hipErrorInvalidValue;
+      case EpiKind::Flow:
+        if constexpr (SP == kDense || SP == kSplitBwd) return K::template go<T, false, SP, ProIdF, EpiFlowF<R>>(L, s);
+        return hipErrorInvalidValue;
       default:
         return hipErrorInvalidValue;
     }
@@ -65,6 +69,7 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
   if (L.pk != ProKind::Id) {
     if constexpr (SP != kSplitBwd)
       if (L.ek == EpiKind::Store) {
+        if (L.pk == ProKind::Flow) return K::template go<T, true, SP, ProFlowF<R>, EpiStoreF<R>>(L, s);
         if (L.pp.ns == 0 && !L.pp.up) return K::template go<T, true, SP, ProNonlinF<R, true>, EpiStoreF<R>>(L, s);
         return K::template go<T, true, SP, ProNonlinF<R>, EpiStoreF<R>>(L, s);
       }
@@ -88,6 +93,9 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
     case EpiKind::Axpy:
       if constexpr (SP == kDense && std::is_same<R, double>::value)
         return K::template go<T, true, SP, ProIdF, EpiAxpyF<R>>(L, s);
+      return hipErrorInvalidValue;
+    case EpiKind::Flow:
+      if constexpr (SP == kDense || SP == kSplitBwd) return K::template go<T, true, SP, ProIdF, EpiFlowF<R>>(L, s);
       return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;

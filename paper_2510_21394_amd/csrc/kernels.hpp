@@ -152,6 +152,58 @@ struct ProNonlinF {
   }
 };
 
+// Exact flow of the nonlinear subproblem of Strang splitting (Section 4, eq. Strang) over a
+// time t, in the state precision:  w -> w e^{gamma t} (1 + 2 kappa a)^{-1/2} e^{-i zeta L},
+// a = t phi_1(2 gamma t) |w|^2, L = log(1 + 2 kappa a) / (2 kappa), and L = a for kappa = 0
+// (the limit).  Rewritten from the printed exponent t gamma - (kappa + i zeta)/(2 kappa) log(...):
+// its real part gives the modulus factor, its imaginary part the phase.  The scalars t phi_1,
+// e^{gamma t} and 2 kappa are formed on the host in FP64.
+template <class R>
+struct FlowF {
+  using C = typename Cx<R>::T;
+  R tp1, eg, k2, zeta;
+  FlowF() = default;
+  explicit FlowF(const FlowParams& f) : tp1((R)f.tp1), eg((R)f.eg), k2((R)f.k2), zeta((R)f.zeta) {}
+  __device__ __forceinline__ C operator()(C w) const {
+    const R a = tp1 * (w.x * w.x + w.y * w.y);
+    R L = a, s = eg;
+    if (k2 > (R)0) {
+      const R x = k2 * a;
+      if constexpr (std::is_same<R, float>::value) {
+        L = log1pf(x) / k2;
+        s = eg * rsqrtf(1.0f + x);
+      } else {
+        L = log1p(x) / k2;
+        s = eg * rsqrt(1.0 + x);
+      }
+    }
+    R sn, cs;
+    if constexpr (std::is_same<R, float>::value)
+      sincosf(-zeta * L, &sn, &cs);
+    else
+      sincos(-zeta * L, &sn, &cs);
+    C o;
+    o.x = s * (w.x * cs - w.y * sn);
+    o.y = s * (w.x * sn + w.y * cs);
+    return o;
+  }
+};
+
+template <class R>
+struct ProFlowF {
+  static constexpr bool kId = false;
+  static constexpr bool kUpdate = false;
+  static constexpr bool kRowLds = false;
+  struct Pre {};
+  FlowF<R> f;
+  ProFlowF() = default;
+  explicit ProFlowF(const ProParams& p) : f(p.flow) {}
+  template <class C>
+  __device__ __forceinline__ C operator()(int64_t, C u) const {
+    return f(u);
+  }
+};
+
 // ---------------------------------------------------------------------------------------
 // Epilogue functors.  col(a, b) is evaluated once per output column (a: flat index over the
 // axes slower than mu, b: over the faster ones).  Each functor works in two phases over V
@@ -232,6 +284,29 @@ struct EpiStoreF {
 #pragma unroll
     for (int v = 0; v < V; ++v)
       if (ok[v]) out[j[v]] = mkc<C>(re[v], im[v]);
+  }
+  FCGLE_EPI_APPLY
+};
+
+// out[j] = phi_t(v): the trailing half step of Strang splitting on the backward product.
+template <class R>
+struct EpiFlowF {
+  using C = typename Cx<R>::T;
+  using Ctx = NoCtx;
+  using Pre = NoPre;
+  C* out;
+  FlowF<R> f;
+  EpiFlowF() = default;
+  explicit EpiFlowF(const EpiParams& p) : out((C*)p.out), f(p.flow) {}
+  __device__ __forceinline__ Ctx col(uint32_t, uint32_t) const { return {}; }
+  template <int V>
+  __device__ __forceinline__ void load(const int*, const int64_t*, const bool*, Pre*) const {}
+  template <int V>
+  __device__ __forceinline__ void store(const Ctx&, const int*, const int64_t* j, const bool* ok, const R* re,
+                                        const R* im, const Pre*) const {
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+      if (ok[v]) out[j[v]] = f(mkc<C>(re[v], im[v]));
   }
   FCGLE_EPI_APPLY
 };

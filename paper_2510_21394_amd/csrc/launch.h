@@ -18,7 +18,8 @@ enum : int { kDense = 0, kSplitFwd = 1, kSplitBwd = 2, kSplitFwd2 = 3 };
 //  transformed nonlinearity), contracted and also stored (first backward even/odd product).
 //  UpdateOtf: as Update with P1 = (E - 1) / z formed on the fly from separable tables (no
 //  P1 grid read; axis lengths n_1 <= kOtfMaxRows).
-enum class ProKind : int { Id = 0, Nonlin = 1, Update = 2, UpdateOtf = 3 };
+//  Flow: the exact flow of the nonlinear subproblem of Strang splitting (FlowParams).
+enum class ProKind : int { Id = 0, Nonlin = 1, Update = 2, UpdateOtf = 3, Flow = 4 };
 constexpr int kOtfMaxRows = 512;
 // What the last stage of a mode product does with each output element.
 enum class EpiKind : int {
@@ -31,7 +32,8 @@ enum class EpiKind : int {
                     //   streaming pass only)
   Axpy = 6,         // out[j] += c v, c complex            (FP64 residual of the refinement sweep;
                     //   dense FP64 products only)
-  Count = 7
+  Flow = 7,         // out[j] = phi_t(v), the exact nonlinear flow (FlowParams; backward products)
+  Count = 8
 };
 
 // Separable per-axis complex factors (FP64): value(j) = prod_mu fac[mu][j_mu].
@@ -54,6 +56,16 @@ struct SepParams {
   const double* first_lam = nullptr;
 };
 
+// Exact flow over a time t of w' = gamma w - (kappa + i zeta)|w|^2 w (Section 4, Strang
+// splitting): w e^{gamma t} (1 + 2 kappa a)^{-1/2} e^{-i zeta L} with a = t phi_1(2 gamma t)|w|^2
+// and L = log(1 + 2 kappa a)/(2 kappa) (L = a when kappa = 0).  The scalars, in FP64:
+struct FlowParams {
+  double tp1 = 0;   // t phi_1(2 gamma t)
+  double eg = 1;    // e^{gamma t}
+  double k2 = 0;    // 2 kappa
+  double zeta = 0;
+};
+
 // Nonlin: g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc[k] S_k[j], with
 // e = eu u + ep up; output = cu u + cp up + cg g.
 // Update: uhat_out[j] = E_j uhat[j] + tau F[j] v[j] (E from sep, F = the phi_1 grid).
@@ -69,6 +81,7 @@ struct ProParams {
   void* uhat_out = nullptr;
   SepParams sep;
   double tau = 0;
+  FlowParams flow;  // Flow
 };
 
 struct EpiParams {
@@ -81,6 +94,7 @@ struct EpiParams {
   const void* F2 = nullptr;  // ExpEulerRec: phi_2 grid
   void* out2 = nullptr;      // ExpEulerRec: X
   double cre = 0, cim = 0;   // Axpy: c
+  FlowParams flow;           // Flow
 };
 
 // One mode product out[a, i, b] = sum_k M[i, k] in[a, k, b] on a complex tensor
@@ -110,7 +124,8 @@ int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
 bool split_supported(int prec);
 
 // True when the fused kernel exists for this (loader, prologue, epilogue) combination
-// (ProKind::Update / UpdateOtf: backward even/odd products with the N loader only).
+// (ProKind::Update / UpdateOtf: backward even/odd products with the N loader only; prologues
+// other than Id: forward products; EpiKind::Flow: backward products).
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek);
 
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s);
@@ -147,7 +162,7 @@ hipError_t launch_pw_group_f32(EpiKind ek, const void* items_dev, int count, uin
 
 // Standalone pointwise passes (unfused fallbacks and helpers), complex tensors of N
 // elements in the state type of `prec`.
-hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,
+hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, ProKind pk, const ProParams& p,
                                 hipStream_t s);
 // Applies epilogue `ek` to v[j] for every j, with the tensor viewed as (N / n_last, n_last).
 hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,

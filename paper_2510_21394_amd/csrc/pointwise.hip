@@ -128,10 +128,16 @@ __global__ void __launch_bounds__(kPwThreads)
 }
 
 template <class R>
-hipError_t pro_impl(int64_t N, const void* in, void* out, const ProParams& p, hipStream_t s) {
+hipError_t pro_impl(int64_t N, const void* in, void* out, ProKind pk, const ProParams& p, hipStream_t s) {
   using C = typename Cx<R>::T;
-  hipLaunchKernelGGL((pw_pro_kernel<R, ProNonlinF<R>>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
-                     (const C*)in, (C*)out, ProNonlinF<R>(p));
+  if (pk == ProKind::Nonlin)
+    hipLaunchKernelGGL((pw_pro_kernel<R, ProNonlinF<R>>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
+                       (const C*)in, (C*)out, ProNonlinF<R>(p));
+  else if (pk == ProKind::Flow)
+    hipLaunchKernelGGL((pw_pro_kernel<R, ProFlowF<R>>), dim3(pw_blocks(N)), dim3(kPwThreads), 0, s, N,
+                       (const C*)in, (C*)out, ProFlowF<R>(p));
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -154,6 +160,7 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
     case EpiKind::ExpEuler: return epi_launch<R, EpiExpEulerF<R>>(N, nlast, v, p, s);
     case EpiKind::KeepOld: return epi_launch<R, EpiKeepOldF<R>>(N, nlast, v, p, s);
     case EpiKind::ExpEulerRec: return epi_launch<R, EpiExpEulerRecF<R>>(N, nlast, v, p, s);
+    case EpiKind::Flow: return epi_launch<R, EpiFlowF<R>>(N, nlast, v, p, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -163,14 +170,16 @@ hipError_t epi_impl(int64_t N, int nlast, const void* v, EpiKind ek, const EpiPa
 bool mp_supported(bool tloader, ProKind pk, EpiKind ek) {
   if (pk == ProKind::Update || pk == ProKind::UpdateOtf) return !tloader && ek == EpiKind::Store;
   if (pk != ProKind::Id) return ek == EpiKind::Store;
-  if (!tloader) return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler;
+  if (!tloader)
+    return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler ||
+           ek == EpiKind::Flow;
   return ek == EpiKind::Store || ek == EpiKind::Grid || ek == EpiKind::Sep || ek == EpiKind::ExpEuler ||
-         ek == EpiKind::KeepOld;
+         ek == EpiKind::KeepOld || ek == EpiKind::Flow;
 }
 
-hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, const ProParams& p,
+hipError_t launch_pointwise_pro(int prec, int64_t N, const void* in, void* out, ProKind pk, const ProParams& p,
                                 hipStream_t s) {
-  return prec == P_F64 ? pro_impl<double>(N, in, out, p, s) : pro_impl<float>(N, in, out, p, s);
+  return prec == P_F64 ? pro_impl<double>(N, in, out, pk, p, s) : pro_impl<float>(N, in, out, pk, p, s);
 }
 
 hipError_t launch_pointwise_epi(int prec, int64_t N, int n_last, const void* v, EpiKind ek,

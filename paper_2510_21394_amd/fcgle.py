@@ -196,15 +196,16 @@ class Plan:
         L.check(self.lib.fcgle_set_tiles(self.handle, int(axis), int(bool(fwd)), int(cfg)))
 
     def set_fusion(self, prologue: bool = True, epilogue: bool = True, reverse: bool = False,
-                   update_in_backward: bool = False, phi1_on_the_fly: bool = False):
+                   update_in_backward: bool = False, phi1_on_the_fly: bool = False, flows: bool = False):
         """Fuse the nonlinearity into the first / the pointwise epilogue into the last mode
         product; reverse: run forward operators from the last axis to the first;
         update_in_backward: apply the exponential-Euler update in the loads of the first
         backward product instead (even/odd plans, d >= 2); phi1_on_the_fly: that
-        update forms phi_1 from separable tables instead of reading the grid (n_1 <= 512)."""
+        update forms phi_1 from separable tables instead of reading the grid (n_1 <= 512);
+        flows: fuse the exact nonlinear flows of Strang splitting into the mode products."""
         L.check(self.lib.fcgle_set_fusion(self.handle, (1 if prologue else 0) | (2 if epilogue else 0)
                                           | (4 if reverse else 0) | (8 if update_in_backward else 0)
-                                          | (32 if phi1_on_the_fly else 0)))
+                                          | (32 if phi1_on_the_fly else 0) | (64 if flows else 0)))
 
     def set_structure(self, split: bool):
         """True: even/odd half-size mode products (default for fp64/fp32); False: dense."""
@@ -291,20 +292,22 @@ class BatchPlan:
 
 def decode_signature(sig: int) -> dict:
     """Inverse of the kernel signature of fcgle_timing_read."""
-    structure = sig // 2048
-    sig %= 2048
+    structure = sig // 4096
+    sig %= 4096
     ek = sig % 8
     sig //= 8
-    pk = sig % 4
-    sig //= 4
+    pk = sig % 8
+    sig //= 8
     tl = sig % 2
     sig //= 2
     cfg = sig % 8
     prec = sig // 8
     return {"precision": ["fp64", "fp32", "bf16x3", "bf16x6"][prec], "tile_cfg": cfg, "t_loader": bool(tl),
             "structure": ["dense", "even_odd_fwd", "even_odd_bwd", "even_odd_fwd_fused"][structure],
-            "prologue": ["none", "nonlinearity", "exp_euler_update", "exp_euler_update_otf"][pk],
-            "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "?", "?"][ek]}
+            "prologue": ["none", "nonlinearity", "exp_euler_update", "exp_euler_update_otf", "nonlinear_flow",
+                         "?", "?", "?"][pk],
+            "epilogue": ["store", "grid", "sep_exp", "exp_euler", "keep_old", "exp_euler_rec", "axpy",
+                         "nonlinear_flow"][ek]}
 
 
 # -- host-only helpers ---------------------------------------------------------------------
