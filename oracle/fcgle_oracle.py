@@ -37,10 +37,12 @@ function.  All schemes here are stateless and work in physical space.
 Parity status: every function is pinned by the CPU tests (closed forms,
 brute force, Neudecker/Sylvester identities, invariants, observed orders,
 an adaptive ODE solver for the exact nonlinear flow and for Strang splitting,
+the errors the paper prints for its Example 1 (reproduced to all printed digits),
 finite differences); none is "parity unpinned".
 """
 from __future__ import annotations
 
+import cmath
 import math
 from typing import Callable, List, Optional, Sequence, Tuple
 
@@ -275,16 +277,16 @@ def brute_apply(kind: str, theta: float, V: np.ndarray, Ds, params: Params) -> n
 
 
 class Source:
-    """s(t) = sum_k exp(rate_k t) S_k  (zero when there are no terms)."""
+    """s(t) = sum_k exp(rate_k t) S_k with real or complex rates (zero when there are no terms)."""
 
-    def __init__(self, rates: Sequence[float] = (), tensors: Sequence[np.ndarray] = ()):
+    def __init__(self, rates: Sequence[complex] = (), tensors: Sequence[np.ndarray] = ()):
         self.rates = list(rates)
         self.tensors = list(tensors)
 
     def __call__(self, t: float, shape) -> np.ndarray:
         s = np.zeros(shape, np.complex128)
         for r, S in zip(self.rates, self.tensors):
-            s = s + math.exp(r * t) * S
+            s = s + cmath.exp(r * t) * S
         return s
 
 
@@ -305,6 +307,64 @@ def manufactured_source(U0: np.ndarray, Ds, params: Params) -> Source:
     S1 = -(1.0 + gamma) * U0 - apply_K(U0, Ds, params)
     S3 = (kappa + 1j * zeta) * (np.abs(U0) ** 2) * U0
     return Source((-1.0, -3.0), (S1, S3))
+
+
+# ---------------------------------------------------------------------------
+# The paper's Example 1 (Section 4): exact solution e^{-it} prod_mu (1 - x_mu^2)^4
+# ---------------------------------------------------------------------------
+
+
+def rl_left_bump(x, alpha: float) -> np.ndarray:
+    """Left Riemann-Liouville derivative from -1 (Section 1) of f(x) = (1 - x^2)^4 on (-1, 1)
+    (f extended by zero outside).  Writing 1 - x = 2 - (1 + x),
+    f = sum_{k=0..4} C(4,k) 2^{4-k} (-1)^k (1 + x)^{4+k}, and each power has
+    D^alpha (1 + x)^p = Gamma(p + 1) / Gamma(p + 1 - alpha) (1 + x)^{p - alpha}."""
+    from scipy.special import gamma as Gam
+    x = np.asarray(x, dtype=np.float64)
+    out = np.zeros_like(x)
+    for k in range(5):
+        p = 4 + k
+        c = math.comb(4, k) * 2.0 ** (4 - k) * (-1.0) ** k
+        out = out + c * Gam(p + 1.0) / Gam(p + 1.0 - alpha) * (1.0 + x) ** (p - alpha)
+    return out
+
+
+def riesz_bump(x, alpha: float) -> np.ndarray:
+    """Riesz derivative of f(x) = (1 - x^2)^4 (Section 1): -(D_left f + D_right f)/(2 cos(alpha pi/2)).
+    f is even, so its right Riemann-Liouville derivative at x is the left one at -x."""
+    x = np.asarray(x, dtype=np.float64)
+    return -(rl_left_bump(x, alpha) + rl_left_bump(-x, alpha)) / (2.0 * math.cos(alpha * math.pi / 2.0))
+
+
+def example1(n: int, alpha: Sequence[float], params: Params):
+    """The paper's Example 1 (Section 4) on (-1,1)^d, n inner points per axis (h = 2/(n+1)):
+    u(t, x) = e^{-it} F(x), F = prod_mu (1 - x_mu^2)^4, solves eq. FCGLE with the source
+    s = u_t - (nu + i eta) sum_mu d^{alpha_mu} u - gamma u + (kappa + i zeta)|u|^2 u = e^{-it} S,
+    S = -i F - (nu + i eta) sum_mu R_mu F - gamma F + (kappa + i zeta) F^3  (F real and |e^{-it}| = 1,
+    R_mu the Riesz derivative along axis mu).  Returns (U0 = F, Source with rate -i, h)."""
+    nu, eta, gamma, kappa, zeta = params
+    d = len(alpha)
+    h = 2.0 / (n + 1)
+    x = -1.0 + h * np.arange(1, n + 1)
+    f = (1.0 - x ** 2) ** 4
+
+    def outer(vs):
+        out = vs[0]
+        for v in vs[1:]:
+            out = np.multiply.outer(out, v)
+        return out
+
+    F = outer([f] * d)
+    RF = np.zeros_like(F)
+    for mu in range(d):
+        RF = RF + outer([riesz_bump(x, alpha[mu]) if nu_ == mu else f for nu_ in range(d)])
+    S = -1j * F - (nu + 1j * eta) * RF - gamma * F + (kappa + 1j * zeta) * F ** 3
+    return F.astype(np.complex128), Source((-1j,), (S,)), (h,) * d
+
+
+def discrete_l2(E: np.ndarray, h: Sequence[float]) -> float:
+    """(prod_mu h_mu sum_j |E_j|^2)^{1/2}, the discrete L2 norm of the paper's absolute errors."""
+    return math.sqrt(float(np.prod(h)) * float(np.sum(np.abs(E) ** 2)))
 
 
 # ---------------------------------------------------------------------------

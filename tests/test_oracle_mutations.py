@@ -138,3 +138,30 @@ def test_strang_full_step_flows_are_caught(monkeypatch):
 
     monkeypatch.setattr(O, "step_strang", bad)
     assert _fails(pins.test_strang_is_second_order_against_the_ode_solution)
+
+
+def test_riesz_normalisation_slip_is_caught(monkeypatch):
+    # cos(alpha pi) instead of cos(alpha pi / 2) in the Riesz normalisation
+    def bad(x, alpha):
+        x = np.asarray(x, dtype=np.float64)
+        return -(O.rl_left_bump(x, alpha) + O.rl_left_bump(-x, alpha)) / (2.0 * math.cos(alpha * math.pi))
+
+    monkeypatch.setattr(O, "riesz_bump", bad)
+    assert _fails(pins.test_fd2_matrix_converges_to_the_riesz_derivative_of_the_bump)
+
+
+def test_rl_gamma_ratio_slip_is_caught(monkeypatch):
+    # Gamma(p) / Gamma(p - alpha) instead of Gamma(p + 1) / Gamma(p + 1 - alpha)
+    from scipy.special import gamma as Gam
+
+    def bad(x, alpha):
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros_like(x)
+        for k in range(5):
+            p = 4 + k
+            c = math.comb(4, k) * 2.0 ** (4 - k) * (-1.0) ** k
+            out = out + c * Gam(p) / Gam(p - alpha) * (1.0 + x) ** (p - alpha)
+        return out
+
+    monkeypatch.setattr(O, "rl_left_bump", bad)
+    assert _fails(pins.test_rl_derivative_of_the_bump_matches_its_integral_definition, 1.5)

@@ -340,3 +340,73 @@ def test_strang_rejects_a_source():
     P, U0 = _manufactured((6, 5), ((-8.0, 8.0),) * 2, (1.3, 1.6))
     with pytest.raises(ValueError):
         O.step_strang(P, U0, 0.0, 0.01)
+
+
+# --- the paper's Example 1: continuous source and printed errors ---------------------------
+
+def _bump_second_derivative(x):
+    # f = (1 - x^2)^4: f' = -8x (1 - x^2)^3, f'' = -8 (1 - x^2)^3 + 48 x^2 (1 - x^2)^2
+    return -8.0 * (1 - x ** 2) ** 3 + 48.0 * x ** 2 * (1 - x ** 2) ** 2
+
+
+def test_riesz_bump_reduces_to_the_second_derivative_at_alpha_2():
+    x = np.linspace(-0.99, 0.99, 41)
+    assert np.max(np.abs(O.riesz_bump(x, 2.0) - _bump_second_derivative(x))) <= 1e-11
+
+
+@pytest.mark.parametrize("alpha", [1.2, 1.5, 1.8])
+def test_rl_derivative_of_the_bump_matches_its_integral_definition(alpha):
+    # f(-1) = f'(-1) = 0, so two integrations by parts of the left Riemann-Liouville derivative
+    # (Section 1) give D^alpha f(x) = 1/Gamma(2 - alpha) int_{-1}^x (x - xi)^{1-alpha} f''(xi) dxi;
+    # w = (x - xi)^{2-alpha} removes the endpoint singularity before the quadrature
+    mpmath.mp.dps = 30
+    q = 1.0 / (2.0 - alpha)
+    for x in (-0.7, 0.1, 0.85):
+        val = mpmath.quad(lambda w: _bump_second_derivative(x - w ** q), [0, (x + 1) ** (2 - alpha)]) * q
+        ref = float(val / mpmath.gamma(2 - alpha))
+        assert abs(O.rl_left_bump(np.array([x]), alpha)[0] - ref) <= 1e-11 * max(1.0, abs(ref))
+
+
+def test_fd2_matrix_converges_to_the_riesz_derivative_of_the_bump():
+    # D = -h^{-alpha} Toeplitz(g) (eq. FD2) applied to the grid values of f approaches the Riesz
+    # derivative at second order away from the boundary: pins the sign and scaling that link the
+    # discrete operator to the continuous one
+    alpha = 1.5
+    errs = []
+    for n in (99, 199, 399):
+        h = 2.0 / (n + 1)
+        x = -1.0 + h * np.arange(1, n + 1)
+        D = O.diff_matrix(alpha, n, h)
+        inner = np.abs(x) <= 0.5
+        errs.append(np.max(np.abs((D @ (1 - x ** 2) ** 4 - O.riesz_bump(x, alpha))[inner])))
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(rates > 1.8), (errs, rates)
+
+
+def _printed_errors():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "example1_printed_errors.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                d, n, steps, err = line.split()
+                rows.append((int(d), int(n), int(steps), err))
+    return rows
+
+
+def _half_unit(printed: str) -> float:
+    mant, exp = printed.lower().split("e")
+    decimals = len(mant.split(".")[1]) if "." in mant else 0
+    return 0.5 * 10.0 ** (int(exp) - decimals)
+
+
+@pytest.mark.parametrize("steps", [15, 35])
+def test_lbdf2_reproduces_the_printed_errors_of_example1_2d(steps):
+    row = [r for r in _printed_errors() if r[0] == 2 and r[2] == steps][0]
+    params = (1.0, 1.0, 3.0, 1.0, 2.0)
+    alpha = (1.2, 1.8)
+    U0, src, h = O.example1(row[1], alpha, params)
+    P = O.Problem(U0.shape, alpha, h, params, source=src)
+    U = O.run(P, "lbdf2", U0, 1.0 / steps, steps)
+    err = O.discrete_l2(U - np.exp(-1j) * U0, h)
+    assert abs(err - float(row[3])) <= _half_unit(row[3]), (err, row)
