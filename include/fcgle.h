@@ -123,10 +123,13 @@ const char* fcgle_last_error(void);
  * Errors: ERR_ARG. */
 int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda);
 
-/* Register the source s(t) = sum_k exp(rate[k] t) S_k (Section 2, the term s of
- * g), nterms <= 4, each S_k a device tensor of the plan's state type that must
- * stay alive while steps run.  nterms = 0 removes the source.  Errors: ERR_ARG. */
-int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const void* const* S_dev);
+/* Register the source s(t) = sum_k exp(c_k t) S_k (Section 1, the term s of eq. FCGLE) with
+ * complex rates c_k = rate[k] + i rate_im[k] (rate_im may be NULL: real rates), nterms <= 4,
+ * each S_k a device tensor of the plan's state type that must stay alive while steps run.
+ * exp(c_k t) is formed in FP64 on the host for every evaluation time.  nterms = 0 removes
+ * the source.  Errors: ERR_ARG. */
+int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const double* rate_im,
+                     const void* const* S_dev);
 
 /* ---------------------------------------------------------------------------
  * Matrix-function action and time steps

@@ -369,7 +369,9 @@ ProParams nonlin_params(const fcgle_plan* P, double t_eval) {
   pp.ns = P->ns;
   for (int k = 0; k < P->ns; ++k) {
     pp.S[k] = P->S[k];
-    pp.sc[k] = std::exp(P->rate[k] * t_eval);
+    const double m = std::exp(P->rate[k] * t_eval), ph = P->rate_im[k] * t_eval;
+    pp.sc[k] = m * std::cos(ph);
+    pp.sci[k] = m * std::sin(ph);
   }
   return pp;
 }
@@ -932,18 +934,21 @@ int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda) {
   return FCGLE_OK;
 }
 
-int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const void* const* S_dev) {
+int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const double* rate_im,
+                     const void* const* S_dev) {
   FC_TRY(check_plan(plan));
   if (nterms < 0 || nterms > 4) return fail(FCGLE_ERR_ARG, "nterms must be 0..4");
   if (nterms > 0 && (!rate || !S_dev)) return fail(FCGLE_ERR_ARG, "NULL source arrays");
   for (int k = 0; k < nterms; ++k) {
     if (!S_dev[k]) return fail(FCGLE_ERR_ARG, "source tensor %d is NULL", k);
-    if (!std::isfinite(rate[k])) return fail(FCGLE_ERR_ARG, "source rate %d not finite", k);
+    if (!std::isfinite(rate[k]) || (rate_im && !std::isfinite(rate_im[k])))
+      return fail(FCGLE_ERR_ARG, "source rate %d not finite", k);
   }
   plan->ns = nterms;
   for (int k = 0; k < 4; ++k) {
     plan->S[k] = k < nterms ? S_dev[k] : nullptr;
     plan->rate[k] = k < nterms ? rate[k] : 0.0;
+    plan->rate_im[k] = (k < nterms && rate_im) ? rate_im[k] : 0.0;
   }
   return FCGLE_OK;
 }

@@ -90,7 +90,8 @@ struct ProIdF {
 };
 
 // out = cu u + cp up + cg g(t, e),  e = eu u + ep up,
-// g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc_k S_k[j]   (Section 2, the map g)
+// g(t, e) = gamma e - (kappa + i zeta)|e|^2 e + sum_k sc_k S_k[j]   (Section 2, the map g;
+// sc_k = exp(c_k t) complex)
 // Plain: no previous state and no source terms (up == nullptr, ns == 0), so no per-element
 // index arithmetic or extra loads.
 template <class R, bool Plain = false>
@@ -102,7 +103,7 @@ struct ProNonlinF {
   using C = typename Cx<R>::T;
   const C* up;
   const C* S[4];
-  R sc[4];
+  R sc[4], sci[4];
   int ns;
   R gamma, kre, kim, eu, ep, cu, cp, cg;
   ProNonlinF() = default;
@@ -111,6 +112,7 @@ struct ProNonlinF {
     for (int k = 0; k < 4; ++k) {
       S[k] = (const C*)p.S[k];
       sc[k] = (R)p.sc[k];
+      sci[k] = (R)p.sci[k];
     }
     ns = p.ns;
     gamma = (R)p.gamma;
@@ -141,8 +143,8 @@ struct ProNonlinF {
       R gi = gamma * ei - m * (kre * ei + kim * er);
       for (int k = 0; k < ns; ++k) {
         const C s = S[k][j];
-        gr += sc[k] * s.x;
-        gi += sc[k] * s.y;
+        gr += sc[k] * s.x - sci[k] * s.y;
+        gi += sc[k] * s.y + sci[k] * s.x;
       }
       C o;
       o.x = cu * u.x + cp * p.x + cg * gr;

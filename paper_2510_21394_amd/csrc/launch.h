@@ -72,7 +72,8 @@ struct FlowParams {
 struct ProParams {
   const void* up = nullptr;
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
-  double sc[4] = {0, 0, 0, 0};
+  double sc[4] = {0, 0, 0, 0};   // exp(c_k t): real part
+  double sci[4] = {0, 0, 0, 0};  //   and imaginary part
   int ns = 0;
   double gamma = 0, kappa = 0, zeta = 0;
   double eu = 1, ep = 0, cu = 0, cp = 0, cg = 1;

@@ -106,7 +106,8 @@ struct fcgle_plan {
   bool hist_valid = false;
   const void* hist_src = nullptr;
   int ns = 0;
-  double rate[4] = {0, 0, 0, 0};
+  double rate[4] = {0, 0, 0, 0};     // source rates c_k = rate + i rate_im
+  double rate_im[4] = {0, 0, 0, 0};
   const void* S[4] = {nullptr, nullptr, nullptr, nullptr};
   int cfg[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};  // [axis][fwd], for the active structure
   int cfg_upd = -1;  // tiles of the axis-0 backward product with the update prologue (-1: cfg[0][0])

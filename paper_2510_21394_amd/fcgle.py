@@ -118,14 +118,16 @@ class Plan:
                                                  ctypes.cast(rn, L.P_dbl) if rn is not None else None, _stream()))
         return (out, list(rn)) if residuals else out
 
-    def set_source(self, rates: Sequence[float], tensors: Sequence[torch.Tensor]):
+    def set_source(self, rates: Sequence[complex], tensors: Sequence[torch.Tensor]):
+        """s(t) = sum_k exp(rates[k] t) tensors[k]; rates real or complex."""
         for S in tensors:
             self._check_tensor(S, "S")
         self._sources = list(tensors)  # keep alive
         k = len(rates)
-        rr = (ctypes.c_double * max(k, 1))(*[float(r) for r in rates])
+        rr = (ctypes.c_double * max(k, 1))(*[complex(r).real for r in rates])
+        ri = (ctypes.c_double * max(k, 1))(*[complex(r).imag for r in rates])
         ss = (ctypes.c_void_p * max(k, 1))(*[S.data_ptr() for S in tensors])
-        L.check(self.lib.fcgle_set_source(self.handle, k, rr, ss))
+        L.check(self.lib.fcgle_set_source(self.handle, k, rr, ri, ss))
 
     def set_state(self, u: torch.Tensor, u_prev: Optional[torch.Tensor] = None):
         self._check_tensor(u)

@@ -389,7 +389,7 @@ def _printed_errors():
     with open(os.path.join(os.path.dirname(__file__), "golden", "example1_printed_errors.txt")) as fh:
         for line in fh:
             if line.strip() and not line.startswith("#"):
-                d, n, steps, err = line.split()
+                d, n, steps, err, _series = line.split()
                 rows.append((int(d), int(n), int(steps), err))
     return rows
 
