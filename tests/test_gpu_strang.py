@@ -198,3 +198,72 @@ def test_strang_rejects_a_source_and_has_no_adjoint(F):
     with pytest.raises(F.FcgleError):
         plan.vjp(u, u.clone(), 0.0, torch.zeros(5, dtype=torch.float64, device=u.device), scheme="strang")
     plan.close()
+
+
+def _example2_rows():
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "example2_printed_errors.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                d, n, steps, ref_steps, err, series = line.split()
+                rows.append((int(d), int(n), int(steps), int(ref_steps), err, series))
+    return rows
+
+
+def _example2_errors(F, d, n, prec, step_counts, ref_steps):
+    dom = ((-10.0, 10.0),) * d
+    h = [(b - a) / (n + 1) for (a, b) in dom]
+    alpha = (1.2, 1.8, 1.5)[:d]
+    U0 = sech_product(grid_axes((n,) * d, dom), (1.0,) * d)
+
+    def run(steps):
+        plan = F.Plan((n,) * d, alpha, h, EX2, tau=1.0 / steps, precision=prec)
+        u = _dev(U0, prec)
+        plan.run("strang", u, 0.0, steps)
+        plan.close()
+        return u.to(torch.complex128)
+
+    ref = run(ref_steps)
+    out = {}
+    for steps in step_counts:
+        out[steps] = float(np.sqrt(np.prod(h)) * torch.linalg.vector_norm(run(steps) - ref).item())
+        print(f"[example2 {d}-D n={n} {prec} steps={steps}] error {out[steps]:.5e}", flush=True)
+    return out
+
+
+def _unit(printed: str, digits=None) -> float:
+    mant, exp = printed.lower().split("e")
+    decimals = len(mant.split(".")[1]) if "." in mant else 0
+    if digits is not None:
+        decimals = digits - 1
+    return 10.0 ** (int(exp) - decimals)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_strang_reproduces_the_printed_errors_of_example2_2d(F, prec):
+    """The paper's Example 2 in 2-D, n = 800, Strang with 5..25 steps against 200 steps: FP64 to
+    half a unit of the last of the five printed digits.  FP32: within 3e-6 absolute, the rounding
+    of the complex64 state accumulated over the 200-step reference (about sqrt(200) 2^-24 |u|,
+    |u| = 2 in the discrete L2 norm, with a margin of 3)."""
+    rows = [r for r in _example2_rows() if r[0] == 2]
+    errs = _example2_errors(F, 2, rows[0][1], prec, [r[2] for r in rows], rows[0][3])
+    for _, _, steps, _, printed, _ in rows:
+        tol = 0.5 * _unit(printed) if prec == "fp64" else 3e-6
+        assert abs(errs[steps] - float(printed)) <= tol, (steps, errs[steps], printed)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_strang_example2_3d_against_the_printed_series(F, prec):
+    """The paper's Example 2 in 3-D, n = 250: its three single-precision series (MATLAB, C++,
+    CUDA) differ from one another by up to 6 %, so the check is a band: within 10 % of the
+    range they span (measured: 1-6.5 % above the C++/CUDA values)."""
+    rows = [r for r in _example2_rows() if r[0] == 3]
+    step_counts = sorted({r[2] for r in rows})
+    errs = _example2_errors(F, 3, rows[0][1], prec, step_counts, rows[0][3])
+    for steps in step_counts:
+        vals = [float(r[4]) for r in rows if r[2] == steps]
+        print(f"  steps={steps}: {errs[steps]:.4e}, printed [{min(vals):.3e}, {max(vals):.3e}]")
+    for steps in step_counts:
+        vals = [float(r[4]) for r in rows if r[2] == steps]
+        assert 0.9 * min(vals) <= errs[steps] <= 1.1 * max(vals), (steps, errs[steps], vals)

@@ -410,3 +410,25 @@ def test_lbdf2_reproduces_the_printed_errors_of_example1_2d(steps):
     U = O.run(P, "lbdf2", U0, 1.0 / steps, steps)
     err = O.discrete_l2(U - np.exp(-1j) * U0, h)
     assert abs(err - float(row[3])) <= _half_unit(row[3]), (err, row)
+
+
+def test_strang_reproduces_the_printed_errors_of_example2_2d():
+    # the oracle's Strang splitting at n = 800 against the printed errors for 5 and 25 steps,
+    # with the reference read as 200 Strang steps (see the fixture)
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", "example2_printed_errors.txt")) as fh:
+        for line in fh:
+            if line.strip() and not line.startswith("#"):
+                d, n, steps, ref_steps, err, _series = line.split()
+                if d == "2":
+                    rows.append((int(n), int(steps), int(ref_steps), err))
+    n = rows[0][0]
+    dom = ((-10.0, 10.0),) * 2
+    h = [(b - a) / (n + 1) for (a, b) in dom]
+    U0 = sech_product(grid_axes((n, n), dom), (1.0, 1.0))
+    P = O.Problem((n, n), (1.2, 1.8), h, (1.0, 1.0, 1.0, 1.0, 1.0))
+    ref = O.run(P, "strang", U0, 1.0 / rows[0][2], rows[0][2])
+    for _, steps, _, printed in (rows[0], rows[-1]):
+        err = O.discrete_l2(O.run(P, "strang", U0, 1.0 / steps, steps) - ref, h)
+        assert abs(err - float(printed)) <= _half_unit(printed), (steps, err, printed)
