@@ -412,6 +412,28 @@ def step_lbdf2(P: Problem, U: np.ndarray, Uprev: np.ndarray, t: float, tau: floa
     return P.f("inv", 2.0 * tau / 3.0, rhs)
 
 
+def step_krogstad(P: Problem, U: np.ndarray, t: float, tau: float) -> np.ndarray:
+    """Krogstad's fourth-order exponential Runge-Kutta step (Section 4, eq. krogstad-v):
+    f_n = K u_n + g(t_n, u_n), d_i = g(t_n + c_i tau, u_{ni}) - g(t_n, u_n), c_2 = c_3 = 1/2, c_4 = 1,
+        u_{n2}  = u_n + tau/2 phi_1(tau/2 K) f_n
+        u_{n3}  = u_n + tau/2 phi_1(tau/2 K) f_n + tau phi_2(tau/2 K) d_2
+        u_{n4}  = u_n + tau phi_1(tau K) f_n + 2 tau phi_2(tau K) d_3
+        u_{n+1} = u_n + tau phi_1(tau K) f_n + tau phi_2(tau K)(2 d_2 + 2 d_3 - d_4)
+                  + tau phi_3(tau K)(-4 d_2 - 4 d_3 + 4 d_4),
+    with K u_n formed by dense mode products with the D_mu (eq. kronsumv)."""
+    g_n = P.g(t, U)
+    f_n = apply_K(U, P.Ds, P.params) + g_n
+    half = U + 0.5 * tau * P.f("phi1", 0.5 * tau, f_n)
+    d2 = P.g(t + 0.5 * tau, half) - g_n
+    u3 = half + tau * P.f("phi2", 0.5 * tau, d2)
+    d3 = P.g(t + 0.5 * tau, u3) - g_n
+    full = U + tau * P.f("phi1", tau, f_n)
+    u4 = full + 2.0 * tau * P.f("phi2", tau, d3)
+    d4 = P.g(t + tau, u4) - g_n
+    return (full + tau * P.f("phi2", tau, 2.0 * d2 + 2.0 * d3 - d4)
+            + tau * P.f("phi3", tau, -4.0 * d2 - 4.0 * d3 + 4.0 * d4))
+
+
 def nonlinear_flow(W: np.ndarray, t: float, params: Params) -> np.ndarray:
     """Exact flow phi_t of the nonlinear subproblem w' = gamma w - (kappa + i zeta)|w|^2 w
     (Section 4, Strang splitting):
@@ -439,7 +461,7 @@ def step_strang(P: Problem, U: np.ndarray, t: float, tau: float) -> np.ndarray:
 
 def run(P: Problem, scheme: str, U0: np.ndarray, tau: float, steps: int, t0: float = 0.0,
         callback: Optional[Callable[[int, np.ndarray], None]] = None) -> np.ndarray:
-    """March `steps` steps of `scheme` in {'exp_euler', 'lawson', 'lie', 'lbdf2', 'strang'} from
+    """March `steps` steps of `scheme` in {'exp_euler', 'lawson', 'lie', 'lbdf2', 'strang', 'krogstad'} from
     U0 at t0.  'lie' repeats the backward-forward Euler step; 'lbdf2' starts with one such step."""
     U = U0.astype(np.complex128)
     Uprev = None
@@ -455,6 +477,8 @@ def run(P: Problem, scheme: str, U0: np.ndarray, tau: float, steps: int, t0: flo
             Un = step_bfe(P, U, t, tau) if Uprev is None else step_lbdf2(P, U, Uprev, t, tau)
         elif scheme == "strang":
             Un = step_strang(P, U, t, tau)
+        elif scheme == "krogstad":
+            Un = step_krogstad(P, U, t, tau)
         else:
             raise ValueError(scheme)
         Uprev, U = U, Un

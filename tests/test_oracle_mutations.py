@@ -165,3 +165,21 @@ def test_rl_gamma_ratio_slip_is_caught(monkeypatch):
 
     monkeypatch.setattr(O, "rl_left_bump", bad)
     assert _fails(pins.test_rl_derivative_of_the_bump_matches_its_integral_definition, 1.5)
+
+
+def test_krogstad_phi3_weight_slip_is_caught(monkeypatch):
+    # -4 d_4 instead of +4 d_4 in the phi_3 term of the last stage
+    def bad(P, U, t, tau):
+        g_n = P.g(t, U)
+        f_n = O.apply_K(U, P.Ds, P.params) + g_n
+        half = U + 0.5 * tau * P.f("phi1", 0.5 * tau, f_n)
+        d2 = P.g(t + 0.5 * tau, half) - g_n
+        u3 = half + tau * P.f("phi2", 0.5 * tau, d2)
+        d3 = P.g(t + 0.5 * tau, u3) - g_n
+        full = U + tau * P.f("phi1", tau, f_n)
+        d4 = P.g(t + tau, full + 2.0 * tau * P.f("phi2", tau, d3)) - g_n
+        return (full + tau * P.f("phi2", tau, 2.0 * d2 + 2.0 * d3 - d4)
+                + tau * P.f("phi3", tau, -4.0 * d2 - 4.0 * d3 - 4.0 * d4))
+
+    monkeypatch.setattr(O, "step_krogstad", bad)
+    assert _fails(pins.test_krogstad_is_fourth_order_on_the_manufactured_solution)

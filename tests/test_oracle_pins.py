@@ -389,8 +389,8 @@ def _printed_errors():
     with open(os.path.join(os.path.dirname(__file__), "golden", "example1_printed_errors.txt")) as fh:
         for line in fh:
             if line.strip() and not line.startswith("#"):
-                d, n, steps, err, _series = line.split()
-                rows.append((int(d), int(n), int(steps), err))
+                d, n, steps, err, series = line.split()
+                rows.append((int(d), int(n), int(steps), err, series))
     return rows
 
 
@@ -402,7 +402,7 @@ def _half_unit(printed: str) -> float:
 
 @pytest.mark.parametrize("steps", [15, 35])
 def test_lbdf2_reproduces_the_printed_errors_of_example1_2d(steps):
-    row = [r for r in _printed_errors() if r[0] == 2 and r[2] == steps][0]
+    row = [r for r in _printed_errors() if r[0] == 2 and r[2] == steps and r[4] == "lbdf2-m"][0]
     params = (1.0, 1.0, 3.0, 1.0, 2.0)
     alpha = (1.2, 1.8)
     U0, src, h = O.example1(row[1], alpha, params)
@@ -432,3 +432,24 @@ def test_strang_reproduces_the_printed_errors_of_example2_2d():
     for _, steps, _, printed in (rows[0], rows[-1]):
         err = O.discrete_l2(O.run(P, "strang", U0, 1.0 / steps, steps) - ref, h)
         assert abs(err - float(printed)) <= _half_unit(printed), (steps, err, printed)
+
+
+@pytest.mark.parametrize("steps", [15, 35])
+def test_krogstad_fd4_reproduces_the_printed_errors_of_example1_2d(steps):
+    row = [r for r in _printed_errors() if r[4] == "krogstad-m" and r[2] == steps][0]
+    params = (1.0, 1.0, 3.0, 1.0, 2.0)
+    alpha = (1.2, 1.8)
+    U0, src, h = O.example1(row[1], alpha, params)
+    P = O.Problem(U0.shape, alpha, h, params, source=src, fd_order=4)
+    U = O.run(P, "krogstad", U0, 1.0 / steps, steps)
+    err = O.discrete_l2(U - np.exp(-1j) * U0, h)
+    assert abs(err - float(row[3])) <= _half_unit(row[3]), (err, row)
+
+
+def test_krogstad_is_fourth_order_on_the_manufactured_solution():
+    P, U0 = _manufactured((10, 12, 8), ((-8.0, 8.0),) * 3, (1.3, 1.6, 1.8))
+    T = 0.5
+    taus = [0.1, 0.05, 0.025]
+    errs = [O.rel_l2(O.run(P, "krogstad", U0, tau, int(round(T / tau))), math.exp(-T) * U0) for tau in taus]
+    slopes = np.diff(np.log(errs)) / np.diff(np.log(taus))
+    assert abs(slopes[-1] - 4.0) <= 0.2, (errs, slopes)
