@@ -355,6 +355,35 @@ def strang_timing():
     return out
 
 
+def krogstad_timing(w, U0, steps=20):
+    """Context: Krogstad's fourth-order scheme on the 256^3 workload (FP32 and FP64 plans,
+    autotuned tiles); steps/s and the relative L2 difference of the two results."""
+    import torch
+    from paper_2510_21394_amd import Plan
+    out = {"workload": w.name, "steps": steps}
+    res = {}
+    for prec in ("fp32", "fp64"):
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        plan = Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
+        plan.autotune(3)
+        u = torch.from_numpy(U0).to(dt).cuda()
+        plan.run("krogstad", u, 0.0, 2)  # warm-up: grids, buffers, first transform
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run("krogstad", u, 2 * w.tau, steps)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[f"{prec}_steps_per_s"] = steps / el
+        out[f"{prec}_ms_per_step"] = 1e3 * el / steps
+        res[prec] = u.to(torch.complex128)
+        plan.close()
+    out["rel_l2_fp32_vs_fp64"] = float(torch.linalg.vector_norm(res["fp32"] - res["fp64"]) /
+                                       torch.linalg.vector_norm(res["fp64"]))
+    del res
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(w, U0, budget_s=20.0, max_steps=3):
     """The FP64 oracle as it stands, timed on the host cores (bounded sample of the workload)."""
     from oracle import fcgle_oracle as O
@@ -441,7 +470,7 @@ def main():
     }
     if not a.no_extras:
         line["context"] = {"batch": batch_timing(), "adjoint": adjoint_timing(), "refine": refine_timing(w, U0),
-                           "strang": strang_timing()}
+                           "strang": strang_timing(), "krogstad": krogstad_timing(w, U0)}
         print(f"# batch: {line['context']['batch']['steps_per_s']:.1f} steps/s; adjoint backward/forward = "
               f"{line['context']['adjoint']['backward_over_forward']:.2f}; strang 256^3 FP32 "
               f"{line['context']['strang']['fp32_steps_per_s']:.1f} steps/s, FP64 "

@@ -72,9 +72,11 @@ typedef enum {
   FCGLE_LAWSON = 1,    /* u+ = e^{tau K} (u + tau g(t, u))                                  */
   FCGLE_LIE = 2,       /* backward-forward Euler (Section 4): (I - tau K) u+ = u + tau g(t, u) */
   FCGLE_LBDF2 = 3,     /* linearised BDF2 with BFE start (Section 4, eq. lbdf2-v)          */
-  FCGLE_STRANG = 4     /* Strang splitting (Section 4, eq. Strang):
+  FCGLE_STRANG = 4,    /* Strang splitting (Section 4, eq. Strang):
                           u+ = phi_{tau/2}(e^{tau K} phi_{tau/2}(u)), phi_t the exact flow of
                           w' = gamma w - (kappa + i zeta)|w|^2 w; no source term            */
+  FCGLE_KROGSTAD = 5   /* Krogstad's fourth-order exponential Runge-Kutta scheme (Section 4,
+                          eq. krogstad-v), phi_1..phi_3 at tau/2 and tau                    */
 } fcgle_scheme;
 
 /* Arithmetic of the mode-product contractions.  Setup (weights, eigenpairs,
@@ -175,8 +177,11 @@ int fcgle_set_state(fcgle_plan* plan, const void* u_dev, const void* u_prev_dev,
  * forward epilogue, and the flow over tau/2 again (streaming passes, or fused with fusion
  * bit 6); with fusion bit 1 its forward products run from the last axis to the first whatever
  * bit 2 says (the E epilogue is cheapest on axis 0).  A plan with a source term gives
- * ERR_UNSUPPORTED for it.
- * Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_HIP. */
+ * ERR_UNSUPPORTED for it.  FCGLE_KROGSTAD keeps u_hat like FCGLE_EXP_EULER; a steady-state
+ * step costs four forward and four backward Tucker operators (the nonlinearity at t, t + tau/2
+ * twice and t + tau fused into the forward ones) and four streaming passes that combine the
+ * stages in eigenspace with the phi_1..phi_3 grids and the separable E in FP64; the first step
+ * allocates five more state tensors.  Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_HIP, ERR_NOMEM. */
 int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, void* stream);
 
 /* nsteps consecutive fcgle_step calls from t0 (t_k = t0 + k tau).  For FCGLE_STRANG the

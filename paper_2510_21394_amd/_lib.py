@@ -29,7 +29,7 @@ class Params(ctypes.Structure):
 # status codes
 OK, ERR_ARG, ERR_UNSUPPORTED, ERR_NOMEM, ERR_HIP, ERR_NONFINITE, ERR_STATE = 0, -1, -2, -3, -4, -5, -6
 KINDS = {"inv": 0, "exp": 1, "phi1": 2, "phi2": 3, "phi3": 4}
-SCHEMES = {"exp_euler": 0, "lawson": 1, "lie": 2, "lbdf2": 3, "strang": 4}
+SCHEMES = {"exp_euler": 0, "lawson": 1, "lie": 2, "lbdf2": 3, "strang": 4, "krogstad": 5}
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 # (name, restype, argtypes) of every exported entry point

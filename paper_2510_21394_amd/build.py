@@ -18,8 +18,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libfcgle.so")
 
-HIP_SOURCES = ["api.hip", "batch.hip", "group_f32.hip", "pointwise.hip", "adjoint.hip", "refine.hip", "mp_f64.hip",
-               "mp_f32.hip", "mp_bf16.hip"]
+HIP_SOURCES = ["api.hip", "batch.hip", "group_f32.hip", "pointwise.hip", "adjoint.hip", "refine.hip", "krogstad.hip",
+               "mp_f64.hip", "mp_f32.hip", "mp_bf16.hip"]
 CXX_SOURCES = ["host_math.cpp"]
 ARCH = "gfx950"
 HIPCC_FLAGS = [

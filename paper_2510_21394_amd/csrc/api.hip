@@ -500,17 +500,133 @@ int strang_run(fcgle_plan* P, void* u, int64_t nsteps, hipStream_t st) {
   return FCGLE_OK;
 }
 
+// One step of Krogstad's fourth-order exponential integrator (Section 4, eq. krogstad-v) with
+// the state kept in eigenspace (uhat = Q^T u, cached between steps like exponential Euler's).
+// In eigenspace K is (nu + i eta) ell, so the stage values take the exponential form
+// u_hat + theta phi_1(theta K) f_n = E_theta u_hat + theta phi_1(theta K) g_n (E_theta = e^{theta K},
+// theta phi_1(theta z) z = e^{theta z} - 1), and with d_i = g_i - g_n:
+//   A2 = E_{tau/2} uhat + tau/2 P1_{tau/2} g_n                    -> u_2 = Q A2, g_2 = Q^T g(t + tau/2, u_2)
+//   A3 = A2 + tau P2_{tau/2} (g_2 - g_n)                          -> g_3 at t + tau/2
+//   A4 = E_tau uhat + tau P1_tau g_n + 2 tau P2_tau (g_3 - g_n)    -> g_4 at t + tau
+//   uhat' = E_tau uhat + tau P1_tau g_n + tau P2_tau (2 g_2 + 2 g_3 - g_4 - 3 g_n)
+//           + tau P3_tau (-4 g_2 - 4 g_3 + 4 g_4 + 4 g_n),        u' = Q uhat'.
+// Per step: four forward and four backward Tucker operators (the nonlinearity fused into the
+// forward ones) and four streaming combination passes.
+int krogstad_body(fcgle_plan* P, void* u, double t, hipStream_t st) {
+  const double tau = P->tau;
+  for (int k = 0; k < 5; ++k)
+    if (!P->kg[k]) FC_TRY(plan_alloc(&P->kg[k], (size_t)P->N * P->elem));
+  void* const G0 = P->kg[0];
+  void* const G2 = P->kg[1];
+  void* const G3 = P->kg[2];
+  void* const G4 = P->kg[3];
+  void* const A = P->kg[4];
+  void* const phys = P->s[2];
+  const void *P1h, *P2h, *P1f, *P2f, *P3f;
+  FC_TRY(get_grid(P, FCGLE_PHI1, 0.5 * tau, st, &P1h));
+  FC_TRY(get_grid(P, FCGLE_PHI2, 0.5 * tau, st, &P2h));
+  FC_TRY(get_grid(P, FCGLE_PHI1, tau, st, &P1f));
+  FC_TRY(get_grid(P, FCGLE_PHI2, tau, st, &P2f));
+  FC_TRY(get_grid(P, FCGLE_PHI3, tau, st, &P3f));
+  SepParams Eh, Ef;
+  FC_TRY(get_sep(P, 0.5 * tau, &Eh));
+  FC_TRY(get_sep(P, tau, &Ef));
+  Eh.mu = Ef.mu = P->d - 1;
+  const int pr = precision_of(P);
+  const int nlast = (int)P->n[P->d - 1];
+  // forward transform of g(t_c, v) into G
+  auto gtrans = [&](const void* v, double tc, void* G) {
+    EpiParams eg;
+    eg.out = G;
+    return tucker(P, true, v, ProKind::Nonlin, nonlin_params(P, tc), EpiKind::Store, eg, P->s[0], P->s[1], st);
+  };
+  auto back = [&](const void* vhat, void* out) {
+    EpiParams eb;
+    eb.out = out;
+    return tucker(P, false, vhat, ProKind::Id, ProParams(), EpiKind::Store, eb, P->s[0], P->s[1], st);
+  };
+  FC_TRY(gtrans(u, t, G0));
+  CombParams c;
+  c.out = A;
+  c.uh = P->uhat;
+  c.sep = Eh;
+  c.nt = 1;
+  c.F[0] = P1h;
+  c.v[0] = G0;
+  c.c[0][0] = 0.5 * tau;
+  HIP_TRY(launch_comb(pr, P->N, nlast, c, st));
+  FC_TRY(back(A, phys));
+  FC_TRY(gtrans(phys, t + 0.5 * tau, G2));
+  c = CombParams();
+  c.out = A;
+  c.nt = 2;
+  c.v[0] = G0;
+  c.v[1] = G2;
+  c.v[4] = A;
+  c.c[0][4] = 1.0;  // A2 (F_0 = 1)
+  c.F[1] = P2h;
+  c.c[1][1] = tau;
+  c.c[1][0] = -tau;
+  HIP_TRY(launch_comb(pr, P->N, nlast, c, st));
+  FC_TRY(back(A, phys));
+  FC_TRY(gtrans(phys, t + 0.5 * tau, G3));
+  c = CombParams();
+  c.out = A;
+  c.uh = P->uhat;
+  c.sep = Ef;
+  c.nt = 2;
+  c.v[0] = G0;
+  c.v[2] = G3;
+  c.F[0] = P1f;
+  c.c[0][0] = tau;
+  c.F[1] = P2f;
+  c.c[1][2] = 2.0 * tau;
+  c.c[1][0] = -2.0 * tau;
+  HIP_TRY(launch_comb(pr, P->N, nlast, c, st));
+  FC_TRY(back(A, phys));
+  FC_TRY(gtrans(phys, t + tau, G4));
+  c = CombParams();
+  c.out = A;
+  c.uh = P->uhat;
+  c.sep = Ef;
+  c.nt = 3;
+  c.v[0] = G0;
+  c.v[1] = G2;
+  c.v[2] = G3;
+  c.v[3] = G4;
+  c.F[0] = P1f;
+  c.c[0][0] = tau;
+  c.F[1] = P2f;
+  c.c[1][0] = -3.0 * tau;
+  c.c[1][1] = 2.0 * tau;
+  c.c[1][2] = 2.0 * tau;
+  c.c[1][3] = -tau;
+  c.F[2] = P3f;
+  c.c[2][0] = 4.0 * tau;
+  c.c[2][1] = -4.0 * tau;
+  c.c[2][2] = -4.0 * tau;
+  c.c[2][3] = 4.0 * tau;
+  HIP_TRY(launch_comb(pr, P->N, nlast, c, st));
+  FC_TRY(back(A, u));
+  std::swap(P->uhat, P->kg[4]);  // the new eigenspace state
+  return FCGLE_OK;
+}
+
 int step_impl(fcgle_plan* P, int scheme, void* u, double t, hipStream_t st) {
   if (scheme == FCGLE_STRANG) return strang_run(P, u, 1, st);
   FC_TRY(ensure_state_buffers(P));
   const double tau = P->tau;
-  if (scheme == FCGLE_EXP_EULER) {
+  if (scheme == FCGLE_EXP_EULER || scheme == FCGLE_KROGSTAD) {
     if (!(P->uhat_valid && P->uhat_src == u)) {
       EpiParams ep;
       ep.out = P->uhat;
       FC_TRY(tucker(P, true, u, ProKind::Id, ProParams(), EpiKind::Store, ep, P->s[0], P->s[1], st));
     }
-    FC_TRY(expeuler_body(P, u, t, st));
+    P->uhat_valid = false;  // until the step has written the new state
+    if (scheme == FCGLE_EXP_EULER)
+      FC_TRY(expeuler_body(P, u, t, st));
+    else
+      FC_TRY(krogstad_body(P, u, t, st));
     P->uhat_valid = true;
     P->uhat_src = u;
     P->hist_valid = false;
@@ -716,6 +832,7 @@ void free_plan(fcgle_plan* P) {
   f(P->rf_part);
   f(P->uhat);
   f(P->uhat2);
+  for (int k = 0; k < 5; ++k) f(P->kg[k]);
   f(P->uprev);
   f(P->dflag);
   for (int k = 0; k < 3; ++k) f(P->adj[k]);
@@ -1039,7 +1156,7 @@ int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, 
   if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
   if (!std::isfinite(t)) return fail(FCGLE_ERR_ARG, "t not finite");
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_KROGSTAD) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   DeviceGuard g(plan->device);
   return step_impl(plan, scheme, u_dev, t, as_stream(stream));
 }
@@ -1321,7 +1438,7 @@ int fcgle_vjp_run(fcgle_plan* plan, int scheme, const void* u_start_dev, int64_t
   if (m < 0) return fail(FCGLE_ERR_ARG, "vjp: m < 0");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
   if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_KROGSTAD) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
   if (u_start_dev == ubar_dev) return fail(FCGLE_ERR_ARG, "vjp: u_start and ubar must be distinct buffers");
   DeviceGuard g(plan->device);
@@ -1335,7 +1452,7 @@ int fcgle_vjp(fcgle_plan* plan, int scheme, const void* u_n_dev, const void* uba
   if (u_n_dev == ubar_n_dev || u_n_dev == ubar_next_dev)
     return fail(FCGLE_ERR_ARG, "vjp: u_n must not alias a cotangent buffer");
   if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
-  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_STRANG) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
+  if (scheme < FCGLE_EXP_EULER || scheme > FCGLE_KROGSTAD) return fail(FCGLE_ERR_ARG, "bad scheme %d", scheme);
   if (scheme != FCGLE_EXP_EULER) return fail(FCGLE_ERR_UNSUPPORTED, "vjp: only FCGLE_EXP_EULER has an adjoint");
   if (ubar_n_dev != ubar_next_dev) {
     DeviceGuard g(plan->device);

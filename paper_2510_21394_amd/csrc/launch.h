@@ -186,6 +186,21 @@ hipError_t launch_adj_phys(int prec, int64_t N, int nlast, void* wq, const void*
 hipError_t launch_adj_hat(int prec, int64_t N, int nlast, const void* v, void* ahat, void* p, const void* X,
                           const void* P1, const SepParams& sep, double tau, double* partial, hipStream_t s);
 
+// Stage combination of Krogstad's scheme in eigenspace (streaming, FP64 arithmetic):
+//   out[j] = E_j uh[j] + sum_{t < nt} F_t[j] (sum_{m < 5} c[t][m] v_m[j])
+// E from sep (with sep.mu = d - 1; omitted when uh is null), F_t null means 1, v_m null means 0.
+// out may alias any input (each element is read before it is written by the same thread).
+struct CombParams {
+  const void* uh = nullptr;
+  SepParams sep;
+  const void* F[3] = {nullptr, nullptr, nullptr};
+  const void* v[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double c[3][5] = {};
+  int nt = 0;
+  void* out = nullptr;
+};
+hipError_t launch_comb(int prec, int64_t N, int nlast, const CombParams& p, hipStream_t s);
+
 // Refinement sweep of the inverse (refine.hip).  v, x, r: complex128 tensors of N elements;
 // y: the state type of `prec` (complex64, or complex128 for FP64).
 hipError_t launch_rf_sub(int64_t N, const void* v, const void* x, void* r, hipStream_t s);  // r = v - x

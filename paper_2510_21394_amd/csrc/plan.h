@@ -100,6 +100,7 @@ struct fcgle_plan {
   void* s[3] = {nullptr, nullptr, nullptr};  // scratch tensors
   void* uhat = nullptr;
   void* uhat2 = nullptr;  // second eigenspace state (update prologue writes here, then swapped)
+  void* kg[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};  // Krogstad: ghat_n, ghat_2..4, stage
   bool uhat_valid = false;
   const void* uhat_src = nullptr;
   void* uprev = nullptr;
