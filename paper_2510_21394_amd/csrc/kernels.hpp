@@ -556,8 +556,9 @@ struct ProUpdateF {
   __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
 };
 
-// The same update with P1 = phi_1(z) = (e^z - 1) / z formed on the fly in FP64 instead of read
-// from the P1 grid (one HBM stream less).  z = (zre + i zim)(lam_row + lam_col), e^z = E_col E_row
+// The same update with P1 = phi_1(z) = (e^z - 1) / z formed on the fly instead of read from the
+// P1 grid (one HBM stream less; the tables are FP64, the quotient is formed in the state
+// precision).  z = (zre + i zim)(lam_row + lam_col), e^z = E_col E_row
 // and e^z - 1 = a + b + a b with a = E_col - 1, b = E_row - 1 (all from separable tables, both
 // of the same sign pattern, so the sum does not cancel); below |z| = 1e-8 the series 1 + z/2.
 // The row entries (factor, factor - 1, eigenvalue of the axis) of all n rows are staged in LDS
@@ -593,21 +594,29 @@ struct ProUpdateOtfF {
     return Col{((const zc*)s.other_first)[b], ((const zc*)s.first_m1)[b], s.first_lam[b]};
   }
   __device__ __forceinline__ Pre load(int64_t j, int) const { return Pre{uhat[j]}; }
+  // E u in FP64 (a state-precision E would be a fixed per-element bias every step, see
+  // EpiSepF); the correction tau phi_1(z) g in the state precision: e^z - 1 = a + b + ab from the
+  // per-axis expm1 values (no cancellation: Re z <= 0 on every axis), divided by z, with the
+  // series 1 + z/2 below |z| = 1e-8.
   __device__ __forceinline__ C update(const Col& c, const RowEnt& r, C g, const Pre& pre) const {
     const zc eu = zmul(zmul(c.E, r.f), to_zc(pre.u));
-    const zc em1 = zadd(zadd(c.Em1, r.fm1), zmul(c.Em1, r.fm1));
-    const double l = c.lam + r.lam;
-    const zc z{s.zre * l, s.zim * l};
-    const double zz = z.re * z.re + z.im * z.im;
-    zc p1;
-    if (zz > 1e-16) {
-      const double inv = 1.0 / zz;
-      p1 = zc{(em1.re * z.re + em1.im * z.im) * inv, (em1.im * z.re - em1.re * z.im) * inv};
+    const R ar = (R)c.Em1.re, ai = (R)c.Em1.im, br = (R)r.fm1.re, bi = (R)r.fm1.im;
+    const R mr = (ar + br) + (ar * br - ai * bi), mi = (ai + bi) + (ar * bi + ai * br);
+    const R l = (R)(c.lam + r.lam);
+    const R zr = (R)s.zre * l, zi = (R)s.zim * l;
+    const R zz = zr * zr + zi * zi;
+    R pr, pi;
+    if (zz > (R)1e-16) {
+      const R inv = (R)1 / zz;
+      pr = (mr * zr + mi * zi) * inv;
+      pi = (mi * zr - mr * zi) * inv;
     } else {
-      p1 = zc{1.0 + 0.5 * z.re, 0.5 * z.im};
+      pr = (R)1 + (R)0.5 * zr;
+      pi = (R)0.5 * zi;
     }
-    const zc pg = zmul(p1, to_zc(g));
-    return from_zc<C>(zc{eu.re + tau * pg.re, eu.im + tau * pg.im});
+    const R t = (R)tau;
+    const R gr = t * (pr * g.x - pi * g.y), gi = t * (pr * g.y + pi * g.x);
+    return from_zc<C>(zc{eu.re + (double)gr, eu.im + (double)gi});
   }
   __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
 };
