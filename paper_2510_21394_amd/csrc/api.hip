@@ -278,13 +278,14 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
 // k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows 48-byte rows).
 bool otf_fits(int pr, int cfg) {
   const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
+  const size_t nbuf = (size_t)cfg_bufs(pr, cfg, 1);
   size_t ops;
   if (pr == P_F64 || pr == P_F32) {
     const size_t r = (pr == P_F64) ? 8 : 4, ldk = 16 + (pr == P_F64 ? 2 : 4);
-    ops = 2 * 2 * tm * ldk * r + 2 * 2 * 2 * tnc * ldk * r;
+    ops = nbuf * 2 * tm * ldk * r + nbuf * 2 * 2 * tnc * ldk * r;
   } else {  // split BF16: NP pieces of 2 bytes, k-tiles of 32 padded by 8
     const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = 40;
-    ops = 2 * 2 * np * tm * ldk * 2 + 2 * 2 * np * 2 * tnc * ldk * 2;
+    ops = nbuf * 2 * np * tm * ldk * 2 + nbuf * 2 * np * 2 * tnc * ldk * 2;
   }
   return ops + (size_t)kOtfMaxRows * 48 <= 163840;
 }
@@ -1372,9 +1373,12 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
   const int pr = precision_of(plan);
   const int sp = plan->split ? 1 : 0;
   for (int m = 0; m < plan->d; ++m) {
-    s += "[" + std::to_string(cfg_rows(pr, plan->cfg[m][0], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][0], sp)) +
-         "/" + std::to_string(cfg_rows(pr, plan->cfg[m][1], sp)) + "x" + std::to_string(cfg_cols(pr, plan->cfg[m][1], sp)) +
-         (plan->split && plan->fwd2[m] ? "F" : "") + "]";
+    // suffix s: single-buffered operand tiles; F: both even/odd blocks per forward tile
+    auto tile = [&](int c) {
+      return std::to_string(cfg_rows(pr, c, sp)) + "x" + std::to_string(cfg_cols(pr, c, sp)) +
+             (cfg_bufs(pr, c, sp) == 1 ? "s" : "");
+    };
+    s += "[" + tile(plan->cfg[m][0]) + "/" + tile(plan->cfg[m][1]) + (plan->split && plan->fwd2[m] ? "F" : "") + "]";
   }
   s += plan->split ? " structure=even-odd" : " structure=dense";
   s += std::string(" fusion=") + ((plan->fusion & 1) ? "pro" : "-") + "/" + ((plan->fusion & 2) ? "epi" : "-") +

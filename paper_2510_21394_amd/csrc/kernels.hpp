@@ -625,9 +625,13 @@ struct ProUpdateOtfF {
 // Tile configurations and geometry
 // ---------------------------------------------------------------------------------------
 
-template <int TM_, int TNC_, int TK_, int WM_, int WN_>
+// NBUF_: operand tiles in LDS double-buffered (2: one barrier per k-tile) or single-buffered (1:
+// half the LDS, so two workgroups can share a CU, for a second barrier per k-tile; split-BF16
+// kernels only).
+template <int TM_, int TNC_, int TK_, int WM_, int WN_, int NBUF_ = 2>
 struct TileCfg {
-  static constexpr int TM = TM_, TNC = TNC_, TK = TK_, WM = WM_, WN = WN_;
+  static constexpr int TM = TM_, TNC = TNC_, TK = TK_, WM = WM_, WN = WN_, NBUF = NBUF_;
+  static_assert(NBUF == 1 || NBUF == 2, "operand buffers");
   static constexpr int THREADS = 64 * WM * WN;
   static constexpr int NW = WM * WN;
   static constexpr int WTM = TM / WM, WTNC = TNC / WN;
@@ -980,6 +984,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;  // operand pairs (even / odd block)
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
+  static_assert(T::NBUF == 2, "the FP32/FP64 kernels double-buffer their operand tiles");
   constexpr size_t kAsBytes = (size_t)2 * NB * TM * LDK * sizeof(R);
   constexpr size_t kBsBytes = (size_t)2 * NB * 2 * TNC * LDK * sizeof(R);
   constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? (size_t)16 * (TM + 1) * sizeof(C) : 0);
@@ -1335,8 +1340,8 @@ __global__ void __launch_bounds__(T::THREADS)
   constexpr int NR = (SP == kDense) ? 1 : 2;
   constexpr int LDK = TK + 8;  // 16-byte pad
   constexpr int LG = 4;        // B loader unit: 4 consecutive k of one column
-  constexpr size_t kAsBytes = (size_t)2 * NB * NP * TM * LDK * sizeof(__bf16);
-  constexpr size_t kBsBytes = (size_t)2 * NB * NP * 2 * TNC * LDK * sizeof(__bf16);
+  constexpr size_t kAsBytes = (size_t)T::NBUF * NB * NP * TM * LDK * sizeof(__bf16);
+  constexpr size_t kBsBytes = (size_t)T::NBUF * NB * NP * 2 * TNC * LDK * sizeof(__bf16);
   constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? epi_lds_bytes<C, T>() : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   // [buffer][block][piece][...]
@@ -1597,10 +1602,13 @@ __global__ void __launch_bounds__(T::THREADS)
   sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
+    const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
     if (kt + 1 < KT) gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) sstore(cur ^ 1, kt + 1);
+    if (kt + 1 < KT) {
+      if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
+      sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
+    }
     __syncthreads();
   }
 

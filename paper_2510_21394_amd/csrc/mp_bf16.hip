@@ -7,11 +7,12 @@ template <int NP>
 struct BFK {
   static constexpr bool kUpdate = true;  // ProUpdateF / ProUpdateOtfF instantiated
   static constexpr bool kFwd2 = true;    // fused even/odd forward tiles instantiated
-  // LDS of the operand tiles of mp_bf16_kernel: NP pieces, k-tiles of TK padded by 8
+  // LDS of the operand tiles of mp_bf16_kernel: NBUF buffers of NP pieces, k-tiles of TK
+  // padded by 8
   template <class T, int SP>
   static constexpr size_t operand_lds() {
     constexpr size_t NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1, LDK = T::TK + 8;
-    return 2 * NB * NP * T::TM * LDK * 2 + 2 * NB * NP * 2 * T::TNC * LDK * 2;
+    return T::NBUF * NB * NP * T::TM * LDK * 2 + T::NBUF * NB * NP * 2 * T::TNC * LDK * 2;
   }
   using R = float;
   template <class T, bool TL, int SP, class Pro, class Epi>
@@ -24,15 +25,16 @@ struct BFK {
 };
 
 hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
-  // Split tiles stay within the 160 KB of LDS with two operand blocks of NP pieces each.
+  // Split tiles stay within the 160 KB of LDS with two operand blocks of NP pieces each; the
+  // single-buffered configurations (last template argument 1) let two workgroups share a CU.
   if (L.prec == P_BF16X3) {
     if (L.split) {
       switch (L.cfg) {
         case 0: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
         case 1: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
         case 2: return dispatch_split<BFK<2>, TileCfg<64, 32, 32, 1, 2>>(L, s);
-        case 3: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
-        case 4: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
+        case 3: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2, 1>>(L, s);
+        case 4: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2, 1>>(L, s);
         default: return hipErrorInvalidValue;
       }
     }
@@ -50,8 +52,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
       case 0: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
       case 1: return dispatch_split<BFK<3>, TileCfg<64, 16, 32, 1, 1>>(L, s);
       case 2: return dispatch_split<BFK<3>, TileCfg<128, 16, 32, 2, 1>>(L, s);
-      case 3: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
-      case 4: return dispatch_split<BFK<3>, TileCfg<64, 16, 32, 1, 1>>(L, s);
+      case 3: return dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2, 1>>(L, s);
+      case 4: return dispatch_split<BFK<3>, TileCfg<128, 16, 32, 2, 1, 1>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }
