@@ -626,8 +626,7 @@ struct ProUpdateOtfF {
 // ---------------------------------------------------------------------------------------
 
 // NBUF_: operand tiles in LDS double-buffered (2: one barrier per k-tile) or single-buffered (1:
-// half the LDS, so two workgroups can share a CU, for a second barrier per k-tile; split-BF16
-// kernels only).
+// half the LDS, so more workgroups can share a CU, for a second barrier per k-tile).
 template <int TM_, int TNC_, int TK_, int WM_, int WN_, int NBUF_ = 2>
 struct TileCfg {
   static constexpr int TM = TM_, TNC = TNC_, TK = TK_, WM = WM_, WN = WN_, NBUF = NBUF_;
@@ -948,13 +947,13 @@ __device__ __forceinline__ void run_epilogue(const Geo& g, uint32_t a_fix, uint3
   }
 }
 
-// LDS of the double-buffered operand tiles of mp_mfma_tile (N loader; the T-loader epilogue
-// may need more), and whether the rows of the on-the-fly update fit beside them.
+// LDS of the operand tiles of mp_mfma_tile (N loader; the T-loader epilogue may need more),
+// and whether the rows of the on-the-fly update fit beside them.
 template <class R, class T, int SP>
 constexpr size_t mp_operand_lds() {
   constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;
   constexpr int LDK = T::TK + (sizeof(R) == 8 ? 2 : 4);
-  return (size_t)2 * NB * T::TM * LDK * sizeof(R) + (size_t)2 * NB * 2 * T::TNC * LDK * sizeof(R);
+  return (size_t)T::NBUF * NB * T::TM * LDK * sizeof(R) + (size_t)T::NBUF * NB * 2 * T::TNC * LDK * sizeof(R);
 }
 constexpr size_t kLdsBytes = 163840;  // 160 KB per workgroup on gfx950
 
@@ -984,9 +983,8 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;  // operand pairs (even / odd block)
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
-  static_assert(T::NBUF == 2, "the FP32/FP64 kernels double-buffer their operand tiles");
-  constexpr size_t kAsBytes = (size_t)2 * NB * TM * LDK * sizeof(R);
-  constexpr size_t kBsBytes = (size_t)2 * NB * 2 * TNC * LDK * sizeof(R);
+  constexpr size_t kAsBytes = (size_t)T::NBUF * NB * TM * LDK * sizeof(R);
+  constexpr size_t kBsBytes = (size_t)T::NBUF * NB * 2 * TNC * LDK * sizeof(R);
   constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? (size_t)16 * (TM + 1) * sizeof(C) : 0);
   __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   R (*As)[NB][TM * LDK] = reinterpret_cast<R (*)[NB][TM * LDK]>(smem);
@@ -1230,10 +1228,13 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   sstore(0, 0);
   __syncthreads();
   for (int kt = 0; kt < KT; ++kt) {
-    const int cur = kt & 1;
+    const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
     if (kt + 1 < KT) gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) sstore(cur ^ 1, kt + 1);
+    if (kt + 1 < KT) {
+      if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
+      sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
+    }
     __syncthreads();
   }
 
