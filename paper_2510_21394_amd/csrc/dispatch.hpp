@@ -18,7 +18,7 @@ constexpr int kCfgCols[2][4][kNumCfg] = {
 // LDS buffers of the operand tiles (1: single-buffered configurations).
 constexpr int kCfgBufs[2][4][kNumCfg] = {
     {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}},
-    {{2, 2, 2, 2, 2}, {2, 1, 1, 2, 2}, {1, 2, 2, 1, 1}, {2, 1, 2, 1, 1}}};
+    {{2, 1, 1, 2, 2}, {2, 1, 1, 2, 2}, {1, 2, 2, 1, 1}, {2, 1, 2, 1, 1}}};
 
 // Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
 // combinations a structure never needs are not instantiated.
