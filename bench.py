@@ -361,6 +361,24 @@ def strang_timing():
     out["rel_l2_fp32_vs_fp64_at_T"] = float(torch.linalg.vector_norm(res["fp32"] - res["fp64"]) /
                                             torch.linalg.vector_norm(res["fp64"]))
     del res
+    # the paper's own timed configurations of this example (Section 4, second 3-D experiment):
+    # n = 250, 30 steps in FP64 (its workstation figure: V100, 0.567 s) and 25 steps in FP32 (its
+    # laptop figure: GTX 1650 Ti, 1.91 s); wall-clock of the time integration, set-up excluded
+    w250 = W.strang_3d(n=250)
+    U250 = W.u0_strang(w250)
+    for prec, steps, paper_s, paper_hw in (("fp64", 30, 0.567, "V100"), ("fp32", 25, 1.91, "GTX 1650 Ti")):
+        dt = torch.complex128 if prec == "fp64" else torch.complex64
+        plan = Plan(w250.n, w250.alpha, w250.h, w250.params, tau=1.0 / steps, precision=prec)
+        plan.autotune(3)
+        u = torch.from_numpy(U250).to(dt).cuda()
+        plan.run("strang", u.clone(), 0.0, 2)  # warm-up (grids, tables)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan.run("strang", u, 0.0, steps)
+        torch.cuda.synchronize()
+        out[f"n250_{prec}_{steps}_steps_s"] = time.perf_counter() - t0
+        out[f"n250_{prec}_paper_s"] = {"seconds": paper_s, "hardware": paper_hw}
+        plan.close()
     torch.cuda.empty_cache()
     return out
 
