@@ -144,12 +144,15 @@ class Plan:
         self._state_ver = (u.data_ptr(), u._version)
 
     def step(self, scheme: str, u: torch.Tensor, t: float) -> torch.Tensor:
+        """One step in place from time t.  scheme: 'exp_euler', 'lawson', 'lie', 'lbdf2',
+        'strang' (no source term) or 'krogstad'."""
         self._check_tensor(u)
         self._sync_state(u)
         L.check(self.lib.fcgle_step(self.handle, L.SCHEMES[scheme], _ptr(u), float(t), self.tau, _stream()))
         return u
 
     def run(self, scheme: str, u: torch.Tensor, t0: float, nsteps: int) -> torch.Tensor:
+        """nsteps steps in place from t0 (schemes as for step)."""
         self._check_tensor(u)
         self._sync_state(u)
         L.check(self.lib.fcgle_run(self.handle, L.SCHEMES[scheme], _ptr(u), float(t0), self.tau, int(nsteps),
