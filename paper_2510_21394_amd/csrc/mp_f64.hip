@@ -25,7 +25,7 @@ hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s) {
     switch (L.cfg) {
       case 0: return dispatch_split<F64K, TileCfg<128, 32, 16, 2, 2>>(L, s);
       case 1: return dispatch_split<F64K, TileCfg<64, 32, 16, 1, 2, 1>>(L, s);
-      case 2: return dispatch_split<F64K, TileCfg<64, 16, 16, 1, 1, 1>>(L, s);
+      case 2: return dispatch_split<F64K, TileCfg<128, 64, 16, 4, 4>>(L, s);
       case 3: return dispatch_split<F64K, TileCfg<128, 32, 16, 4, 2>>(L, s);
       case 4: return dispatch_split<F64K, TileCfg<128, 64, 16, 2, 4>>(L, s);
       default: return hipErrorInvalidValue;
