@@ -119,7 +119,8 @@ void fcgle_destroy(fcgle_plan* plan);
  * The pointer stays valid until the next failing call on the same thread. */
 const char* fcgle_last_error(void);
 
-/* Eigenpairs of axis mu (0-based) in FP64: Q[n_mu * n_mu] row-major with
+/* Eigenpairs of axis mu (0-based), D_mu = Q_mu Lambda_mu Q_mu^T (Section 2, eq. diag), in FP64:
+ * Q[n_mu * n_mu] row-major with
  * column k the eigenvector of lambda[k]; lambda ascending (the plan itself keeps them in
  * even/odd block order, see fcgle_set_structure).  Host buffers.
  * Errors: ERR_ARG. */
@@ -161,9 +162,12 @@ int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, v
 int fcgle_apply_inv_refined(fcgle_plan* plan, double theta, const void* v_dev, void* x_dev, int sweeps,
                             double* rnorm, void* stream);
 
-/* Forget the cached eigenspace state and the LBDF2 history, then (if u_prev_dev
- * is not NULL) record u_prev_dev as u_{n-1} for the next FCGLE_LBDF2 step on
- * u_dev.  Call it whenever the caller writes u_dev between steps.  Errors: ERR_ARG. */
+/* Forget the cached eigenspace state (u_hat = u x_1 Q_1^T ... x_d Q_d^T, the transformed
+ * state of Section 3, eq. fKu_diag) and the LBDF2 history, then (if u_prev_dev is not NULL)
+ * record u_prev_dev as u_{n-1}, the second starting value of the two-step scheme (Section 4,
+ * eq. lbdf2-v), for the next FCGLE_LBDF2 step on u_dev.  Both caches are keyed by the device
+ * address u_dev only: call it whenever the caller writes u_dev between steps, or hands the
+ * library a new tensor that may occupy a freed buffer's address.  Errors: ERR_ARG. */
 int fcgle_set_state(fcgle_plan* plan, const void* u_dev, const void* u_prev_dev, void* stream);
 
 /* Advance u_dev in place from time t to t + tau by one step of `scheme`.
@@ -237,8 +241,9 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
  * direction; then time whole exponential-Euler steps (as many) for every placement of
  * the nonlinearity and of the update (fcgle_set_fusion) and keep the fastest.
  * For a batch plan: the same per grouped phase over all instances (`reps` launches).
- * Overwrites the plan's scratch and cached eigenspace state.  Synchronous.
- * Errors: ERR_HIP. */
+ * Overwrites the plan's scratch buffers, so the cached eigenspace state and the LBDF2 history
+ * are forgotten (as by fcgle_set_state): the next step of any scheme starts from u_dev alone.
+ * Synchronous.  Errors: ERR_HIP. */
 int fcgle_autotune(fcgle_plan* plan, int reps, void* stream);
 
 /* Choose the tile configuration (0..4; rows x columns per tile depend on the precision and
@@ -318,7 +323,9 @@ int fcgle_timing_read(fcgle_plan* plan, int cap, int* axis, int* fwd, int* sig, 
 int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const double* h,
                       const fcgle_params* params, int precision, double tau, fcgle_plan** out);
 
-/* nsteps exponential-Euler steps (the scheme of fcgle_step) of every instance, in place on
+/* nsteps exponential-Euler steps (the scheme of fcgle_step; each instance is its own problem
+ * u' = K u + g(t, u) of Section 2, advanced through the Tucker form of Section 3, eq. fKu_diag,
+ * with its own eigenpairs) of every instance, in place on
  * the caller's device buffers u_dev[i] (n[2i] * n[2i+1] complex64, C order), from t0.
  * Sources are not supported in batches.  The call forms each eigenspace state from u_dev
  * (two grouped launches), then replays a HIP graph that holds the whole trajectory (up to

@@ -1316,7 +1316,12 @@ extern "C" int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   plan->tuned = (rc == FCGLE_OK);
-  plan->uhat_valid = false;  // scratch buffers were overwritten
+  // the timed steps ran on the plan's own buffers: the eigenspace state and u_{n-1} of the
+  // LBDF2 history were overwritten, so both caches are forgotten
+  plan->uhat_valid = false;
+  plan->uhat_src = nullptr;
+  plan->hist_valid = false;
+  plan->hist_src = nullptr;
   return rc;
 }
 

@@ -6,6 +6,7 @@ provides device memory and the current stream.
 from __future__ import annotations
 
 import ctypes
+import weakref
 from typing import Optional, Sequence, Tuple
 
 import numpy as np
@@ -56,7 +57,7 @@ class Plan:
             L.check(self.lib.fcgle_setup(self.d, nn, aa, hh, ctypes.byref(pp), int(fd_order),
                                          L.PRECISIONS[precision], self.tau, ctypes.byref(out)))
         self.handle = out
-        self._state_ver = None
+        self._state = None  # (weakref to the tensor the library's cached state belongs to, its _version)
         self._sources = []
 
     # -- lifetime --------------------------------------------------------------------------
@@ -134,14 +135,18 @@ class Plan:
         if u_prev is not None:
             self._check_tensor(u_prev, "u_prev")
         L.check(self.lib.fcgle_set_state(self.handle, _ptr(u), _ptr(u_prev), _stream()))
-        self._state_ver = (u.data_ptr(), u._version)
+        self._state = (weakref.ref(u), u._version)
 
     def _sync_state(self, u: torch.Tensor):
-        # The plan caches the eigenspace state of u between steps; if torch wrote u in place
-        # since our last step, tell the library.
-        if self._state_ver is not None and self._state_ver != (u.data_ptr(), u._version):
+        # The library caches the eigenspace state (and the LBDF2 history) of the buffer it last
+        # stepped, keyed by its device address.  That address says nothing about the tensor:
+        # the caching allocator hands a freed block to the next tensor, and writes through the
+        # library do not bump _version.  So the cache is kept only while the caller passes the
+        # very tensor object of the last step, not written by torch since.
+        st = self._state
+        if st is None or st[0]() is not u or st[1] != u._version:
             L.check(self.lib.fcgle_set_state(self.handle, _ptr(u), ctypes.c_void_p(0), _stream()))
-        self._state_ver = (u.data_ptr(), u._version)
+        self._state = (weakref.ref(u), u._version)
 
     def step(self, scheme: str, u: torch.Tensor, t: float) -> torch.Tensor:
         """One step in place from time t.  scheme: 'exp_euler', 'lawson', 'lie', 'lbdf2',
@@ -170,7 +175,7 @@ class Plan:
             raise ValueError("pbar must be 5 float64 values on the plan's device")
         L.check(self.lib.fcgle_vjp(self.handle, L.SCHEMES[scheme], _ptr(u_n), _ptr(ubar_next), _ptr(ubar_n),
                                    _ptr(pbar), float(t), self.tau, _stream()))
-        self._state_ver = None
+        self._state = None
         return ubar_n
 
     def vjp_run(self, u_start: torch.Tensor, m: int, ubar: torch.Tensor, pbar: torch.Tensor, t0: float,
@@ -183,7 +188,7 @@ class Plan:
             raise ValueError("pbar must be 5 float64 values on the plan's device")
         L.check(self.lib.fcgle_vjp_run(self.handle, L.SCHEMES[scheme], _ptr(u_start), int(m), _ptr(ubar),
                                        _ptr(pbar), float(t0), self.tau, _stream()))
-        self._state_ver = None
+        self._state = None
         return ubar
 
     def check_finite(self, u: torch.Tensor) -> bool:
@@ -195,7 +200,9 @@ class Plan:
         return True
 
     def autotune(self, reps: int = 3):
+        """Overwrites the library's cached state: the next step starts from the tensor again."""
         L.check(self.lib.fcgle_autotune(self.handle, int(reps), _stream()))
+        self._state = None
 
     def set_tiles(self, axis: int, fwd: bool, cfg: int):
         L.check(self.lib.fcgle_set_tiles(self.handle, int(axis), int(bool(fwd)), int(cfg)))
@@ -356,6 +363,7 @@ class ExpEulerTrajectory(torch.autograd.Function):
     def forward(ctx, u0, params, problem, steps, every, t0):
         plan = problem.plan_for(tuple(float(p) for p in params.detach().cpu().tolist()))
         u = u0.detach().to(plan.dtype).contiguous().clone()
+        plan.set_state(u)
         ckpts = []
         k = 0
         while k < steps:
@@ -384,7 +392,9 @@ class ExpEulerTrajectory(torch.autograd.Function):
 class Problem:
     """Grid, orders, time step and precision of a problem whose parameters may vary: keeps
     the plan of the most recent parameter set (setting up a plan costs the FP64
-    eigendecompositions and the f-grids)."""
+    eigendecompositions and the f-grids).  A plan replaced by one for other parameters is not
+    closed here: an autograd graph that ran on it still holds it for its backward pass, and it
+    is released with its last reference."""
 
     def __init__(self, n, alpha, h, tau: float, precision: str = "fp64", fd_order: int = 2):
         self.n, self.alpha, self.h = tuple(n), tuple(alpha), tuple(h)
@@ -394,8 +404,7 @@ class Problem:
 
     def plan_for(self, params) -> Plan:
         if self._key != params:
-            if self._plan is not None:
-                self._plan.close()
+            self._plan = None  # dropped, not closed (see the class comment)
             self._plan = Plan(self.n, self.alpha, self.h, params, tau=self.tau, precision=self.precision,
                               fd_order=self.fd_order)
             self._key = params

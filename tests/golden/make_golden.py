@@ -7,7 +7,11 @@ Each case runs a whole trajectory on the CPU and stores, in <case>.npz:
   norm  : the L2 norm of the whole oracle u(T)
   steps, tau, scheme : the trajectory that produced it
 
-The adjoint case stores the oracle's gradient instead (see case_adjoint).
+The adjoint case stores the oracle's gradient instead (see case_adjoint).  The refined-step
+cases of the 256^3 workload (case_headline_refined) repeat its trajectory to the same T with
+tau/2 and tau/4; they sample the same indices, so the temporal discretisation error of the
+tau = 1e-3 trajectory can be estimated from the stored samples alone (Richardson: for a
+first-order scheme u_tau - u_exact ~ 2 (u_tau - u_{tau/2})).
 
 Usage: python tests/golden/make_golden.py [case ...]   (all cases by default)
 """
@@ -52,6 +56,17 @@ def case_headline():
     _save(w.name, U, w.steps, w.tau, "exp_euler")
 
 
+def case_headline_refined(k):
+    """The 256^3 workload to the same T = 0.2 with tau / k (200 k steps); stored under the
+    headline's name with the suffix _tau<k>."""
+    w = W.headline_3d()
+    U0 = W.u0_headline(w)
+    P = O.Problem(w.n, w.alpha, w.h, w.params)
+    tau, steps = w.tau / k, w.steps * k
+    U = O.run(P, "exp_euler", U0, tau, steps)
+    _save(f"{w.name}_tau{k}", U, steps, tau, "exp_euler")
+
+
 def case_adjoint():
     """96^3 adjoint workload: L = ||u(T) - u_target||^2 with u_target the trajectory under the
     perturbed parameters; stores the oracle gradient (u0 samples, five parameters) and L."""
@@ -93,6 +108,8 @@ CASES = {
     "3d_128_manufactured_lie": lambda: case_manufactured("lie"),
     "3d_128_manufactured_exp_euler": lambda: case_manufactured("exp_euler"),
     "3d_256_gauss4_expeuler": case_headline,
+    "3d_256_gauss4_expeuler_tau2": lambda: case_headline_refined(2),
+    "3d_256_gauss4_expeuler_tau4": lambda: case_headline_refined(4),
 }
 
 

@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -59,3 +60,28 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     line = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in line["error"]
+
+
+def test_temporal_error_estimate():
+    """Richardson estimate on synthetic samples of a first-order trajectory: u_tau = u* + c tau."""
+    rng = np.random.default_rng(0)
+    idx = np.arange(64)
+    ustar = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    c = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    tau = 1e-3
+    g = {k: {"idx": idx, "val": ustar + c * tau / k, "tau": tau / k} for k in (1, 2, 4)}
+    t = bench.temporal_error(g[1], g[2], g[4])
+    exact = np.linalg.norm(c * tau)
+    assert abs(t["rel_l2"] - exact / np.linalg.norm(g[2]["val"])) < 1e-12
+    assert abs(t["successive_difference_ratio"] - 2.0) < 1e-12
+    assert abs(t["rel_l2_vs_extrapolated"] - exact / np.linalg.norm(ustar)) < 1e-12
+    assert bench.temporal_error(g[1], {"idx": idx[::-1], "val": g[2]["val"]}) is None
+
+
+def test_equal_accuracy_selection():
+    v = {"fp64": {"steps_per_s": 100.0, "rel_l2_vs_fp64_oracle_at_T": 1e-14},
+         "fp32": {"steps_per_s": 180.0, "rel_l2_vs_fp64_oracle_at_T": 3e-7},
+         "bf16x3": {"steps_per_s": 200.0, "rel_l2_vs_fp64_oracle_at_T": 8e-6}}
+    sp = bench.equal_accuracy(v, {"rel_l2": 1e-5})
+    assert sp == {"fp64": 1.0, "fp32": 1.8}
+    assert bench.equal_accuracy(v, None) is None

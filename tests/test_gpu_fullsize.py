@@ -67,19 +67,47 @@ def test_manufactured_128_full_trajectory(F, scheme):
     plan.close()
 
 
+_HEADLINE_ERR = {}
+
+
+def _headline_error(F, prec):
+    """256^3 on (-12,12)^3, alpha = 1.7, four Gaussians, 200 exponential-Euler steps of
+    tau = 1e-3 from u0, autotuned plan: sampled relative L2 error and relative norm error
+    against the stored FP64 oracle u(T).  Computed once per precision and module."""
+    if prec not in _HEADLINE_ERR:
+        w = headline_3d()
+        g = _golden(w.name)
+        plan = F.Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
+        plan.autotune(2)
+        u = torch.from_numpy(u0_headline(w)).to(CDT[prec]).cuda()
+        plan.set_state(u)
+        plan.run("exp_euler", u, 0.0, w.steps)
+        err, nerr = _compare(u, g)
+        print(f"[{w.name} {prec} x{w.steps}] sampled rel_l2 = {err:.3e}, norm rel = {nerr:.3e} "
+              f"({plan.describe()})")
+        plan.close()
+        del u
+        torch.cuda.empty_cache()
+        _HEADLINE_ERR[prec] = (err, nerr)
+    return _HEADLINE_ERR[prec]
+
+
+# Bounds at T: FP64 1e-12, FP32 1e-5 and split-BF16 1e-6 as stated for the method's precision
+# forms.  Split-BF16 with 3 products (2 BF16 pieces per operand) carries the 2-piece
+# representation error of FP32 data, about 2^-17 relative, into every mode product, so it
+# cannot reach 1e-6: it is held to 1e-4 here as a regression guard, and to the stated 1e-6 by
+# the strict expected failure below, which records the miss.
 @pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5), ("bf16x6", 1e-6), ("bf16x3", 1e-4)])
 def test_headline_256_full_trajectory(F, prec, tol):
-    """256^3 on (-12,12)^3, alpha = 1.7, four Gaussians, 200 exponential-Euler steps of
-    tau = 1e-3 from u0, autotuned plan: vs the stored FP64 oracle u(T)."""
-    w = headline_3d()
-    g = _golden(w.name)
-    plan = F.Plan(w.n, w.alpha, w.h, w.params, tau=w.tau, precision=prec)
-    plan.autotune(2)
-    u = torch.from_numpy(u0_headline(w)).to(CDT[prec]).cuda()
-    plan.set_state(u)
-    plan.run("exp_euler", u, 0.0, w.steps)
-    err, nerr = _compare(u, g)
-    print(f"[{w.name} {prec} x{w.steps}] sampled rel_l2 = {err:.3e}, norm rel = {nerr:.3e} ({plan.describe()})")
+    err, nerr = _headline_error(F, prec)
     assert err <= tol
     assert nerr <= tol
-    plan.close()
+
+
+@pytest.mark.xfail(strict=True, reason="split-BF16 with 3 products (2 BF16 pieces per operand) represents FP32 data "
+                                       "to about 2^-17, so its error at T (measured 8e-6) misses the stated 1e-6; "
+                                       "the 6-product form (3 pieces) meets it")
+def test_headline_256_bf16x3_stated_bound(F):
+    err, nerr = _headline_error(F, "bf16x3")
+    assert err <= 1e-6
+    assert nerr <= 1e-6

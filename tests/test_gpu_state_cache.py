@@ -1,0 +1,139 @@
+"""GPU regression tests of the cached per-buffer state (eigenspace state u_hat of exponential
+Euler, u_{n-1} of LBDF2) against the FP64 oracle.
+
+The library keys both caches by the device address of the state buffer.  These cases hand
+it a new tensor at a freed address, run the differentiable trajectory twice without a
+backward pass in between, and autotune between LBDF2 steps; every result must be the
+oracle's trajectory from the tensor's own contents.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import fcgle_oracle as O
+from workloads import BASE_PARAMS, random_complex
+
+pytestmark = pytest.mark.gpu
+
+N3 = (24, 30, 20)
+ALPHA = (1.45, 1.7, 1.3)
+H = (0.21, 0.17, 0.3)
+
+
+@pytest.fixture(scope="module")
+def F():
+    import paper_2510_21394_amd as pkg
+    return pkg
+
+
+def _host(t):
+    return t.detach().cpu().numpy().astype(np.complex128)
+
+
+def test_new_tensor_at_freed_address(F):
+    """Run on u, free it, build a new tensor (fresh, version 0) from other data: the caching
+    allocator usually returns the same block.  The second run must start from the new data."""
+    U0a = random_complex(N3, 11) * 0.3
+    U0b = random_complex(N3, 12) * 0.3
+    P = O.Problem(N3, ALPHA, H, BASE_PARAMS)
+    plan = F.Plan(N3, ALPHA, H, BASE_PARAMS, tau=1e-3)
+    u = torch.from_numpy(U0a).cuda()
+    addr = u.data_ptr()
+    plan.run("exp_euler", u, 0.0, 3)
+    torch.cuda.synchronize()
+    del u
+    v = torch.from_numpy(U0b).cuda()
+    print(f"second tensor at the freed address: {v.data_ptr() == addr}")
+    plan.run("exp_euler", v, 0.0, 3)
+    err = O.rel_l2(_host(v), O.run(P, "exp_euler", U0b, 1e-3, 3))
+    print(f"rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+    plan.close()
+
+
+def test_new_tensor_same_address_lbdf2(F):
+    """The LBDF2 history must not carry over to a new tensor at the same address either."""
+    U0a = random_complex(N3, 13) * 0.3
+    U0b = random_complex(N3, 14) * 0.3
+    P = O.Problem(N3, ALPHA, H, BASE_PARAMS)
+    plan = F.Plan(N3, ALPHA, H, BASE_PARAMS, tau=1e-3)
+    u = torch.from_numpy(U0a).cuda()
+    plan.run("lbdf2", u, 0.0, 2)
+    torch.cuda.synchronize()
+    del u
+    v = torch.from_numpy(U0b).cuda()
+    plan.run("lbdf2", v, 0.0, 3)
+    err = O.rel_l2(_host(v), O.run(P, "lbdf2", U0b, 1e-3, 3))
+    print(f"rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+    plan.close()
+
+
+def test_trajectory_twice_without_backward(F):
+    """Two differentiable forward passes with the same parameters and no backward between (as a
+    no-grad finite-difference check does): each must start from its own u0."""
+    prob = F.Problem(N3, ALPHA, H, tau=1e-3, precision="fp64")
+    p = torch.tensor(BASE_PARAMS, dtype=torch.float64)
+    P = O.Problem(N3, ALPHA, H, BASE_PARAMS)
+    for seed in (15, 16, 15):
+        U0 = random_complex(N3, seed) * 0.3
+        with torch.no_grad():
+            uT = prob.trajectory(torch.from_numpy(U0).cuda(), p, 7, every=3)
+        err = O.rel_l2(_host(uT), O.run(P, "exp_euler", U0, 1e-3, 7))
+        print(f"seed {seed}: rel_l2 = {err:.3e}")
+        assert err <= 1e-12
+    prob.close()
+
+
+def test_old_graph_backward_after_parameter_change(F):
+    """A graph built with one parameter set keeps its plan when the problem moves on to other
+    parameters: its backward pass still runs and matches the oracle's adjoint."""
+    prob = F.Problem(N3, ALPHA, H, tau=1e-3, precision="fp64")
+    U0 = random_complex(N3, 17) * 0.3
+    x = torch.from_numpy(U0).cuda().requires_grad_(True)
+    p = torch.tensor(BASE_PARAMS, dtype=torch.float64, requires_grad=True)
+    uT = prob.trajectory(x, p, 4, every=2)
+    other = torch.tensor([v + 0.1 for v in BASE_PARAMS], dtype=torch.float64)
+    with torch.no_grad():
+        prob.trajectory(torch.from_numpy(U0).cuda(), other, 4, every=2)
+    uT.abs().pow(2).sum().backward()
+    P = O.Problem(N3, ALPHA, H, BASE_PARAMS)
+    _, g, pb = O.expeuler_loss_and_grad(P, U0, np.zeros_like(U0), 1e-3, 4)
+    eg = O.rel_l2(_host(x.grad), g)
+    ep = float(np.linalg.norm(p.grad.numpy() - pb) / np.linalg.norm(pb))
+    print(f"grad u0 rel_l2 = {eg:.3e}, params rel = {ep:.3e}")
+    assert eg <= 1e-10 and ep <= 1e-10
+    prob.close()
+
+
+def test_lbdf2_autotune_between_steps(F):
+    """Autotuning between LBDF2 steps overwrites the plan's history buffer, so the library must
+    forget it: continuing without history restarts with the backward-forward Euler step, and a
+    history handed back with set_state continues the two-step scheme."""
+    U0 = random_complex(N3, 18) * 0.3
+    P = O.Problem(N3, ALPHA, H, BASE_PARAMS)
+    tau = 1e-3
+    plan = F.Plan(N3, ALPHA, H, BASE_PARAMS, tau=tau)
+    u = torch.from_numpy(U0).cuda()
+    plan.run("lbdf2", u, 0.0, 3)
+    plan.autotune(1)
+    plan.run("lbdf2", u, 3 * tau, 3)
+    U3 = O.run(P, "lbdf2", U0, tau, 3)
+    ref = O.run(P, "lbdf2", U3, tau, 3, t0=3 * tau)  # fresh start from u_3
+    err = O.rel_l2(_host(u), ref)
+    print(f"restart after autotune: rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+
+    u = torch.from_numpy(U0).cuda()
+    plan.set_state(u)
+    plan.run("lbdf2", u, 0.0, 2)
+    u_prev = u.clone()
+    plan.run("lbdf2", u, 2 * tau, 1)
+    plan.autotune(1)
+    plan.set_state(u, u_prev)
+    plan.run("lbdf2", u, 3 * tau, 3)
+    err = O.rel_l2(_host(u), O.run(P, "lbdf2", U0, tau, 6))
+    print(f"history handed back after autotune: rel_l2 = {err:.3e}")
+    assert err <= 1e-12
+    plan.close()
