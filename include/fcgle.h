@@ -341,6 +341,34 @@ int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0,
                     int64_t nsteps, void* stream);
 
 /* ---------------------------------------------------------------------------
+ * Allocation-free variant
+ * ------------------------------------------------------------------------- */
+
+/* Bytes of each of the three work tensors of fcgle_apply_f_noalloc (16 MiB). */
+#define FCGLE_NOALLOC_TENSOR_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Computes what fcgle_apply_f(plan, kind, theta,
+ * u_dev, out_dev, stream) computes, with the same kernels, but takes the three state-sized work
+ * tensors of its Tucker operators from a fixed work space instead of the plan's own buffers,
+ * and allocates nothing (no hipMalloc, hipFree or allocating library call).  The work space is
+ * a device array of 3 * FCGLE_NOALLOC_TENSOR_BYTES bytes that every device the library runs on
+ * holds from the load of the library's code object until the process ends; its address is
+ * resolved when a plan is set up on the device.
+ *   Limit: N * elem_bytes <= FCGLE_NOALLOC_TENSOR_BYTES (complex64 states up to 2^21 elements,
+ *     e.g. 128^3; complex128 up to 2^20), else ERR_ARG.
+ *   The f-grid for (kind, theta) (for FCGLE_EXP the separable factors for theta) must already
+ *     exist on the plan, i.e. fcgle_apply_f ran once with the same pair (grids are built, and
+ *     allocated, there); else ERR_STATE and nothing is launched.
+ *   u_dev and out_dev may be the same buffer.  The work space needs no initial contents and
+ *     keeps those of the last call.  It is shared by every call on one device: calls that may
+ *     overlap there (other streams, threads or plans) race on it and must be serialised by the
+ *     caller.
+ * Errors: ERR_ARG, ERR_STATE, ERR_HIP. */
+int fcgle_apply_f_noalloc(fcgle_plan* plan, int kind, double theta, const void* u_dev, void* out_dev,
+                          void* stream);
+
+/* ---------------------------------------------------------------------------
  * Host-only helpers (no device calls; usable without a GPU)
  * ------------------------------------------------------------------------- */
 

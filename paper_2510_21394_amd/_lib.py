@@ -41,6 +41,7 @@ SIGNATURES = [
     ("fcgle_get_eig", c_int, [c_vp, c_int, P_dbl, P_dbl]),
     ("fcgle_set_source", c_int, [c_vp, c_int, P_dbl, P_dbl, ctypes.POINTER(c_vp)]),
     ("fcgle_apply_f", c_int, [c_vp, c_int, c_dbl, c_vp, c_vp, c_vp]),
+    ("fcgle_apply_f_noalloc", c_int, [c_vp, c_int, c_dbl, c_vp, c_vp, c_vp]),
     ("fcgle_apply_inv_refined", c_int, [c_vp, c_dbl, c_vp, c_vp, c_int, P_dbl, c_vp]),
     ("fcgle_set_state", c_int, [c_vp, c_vp, c_vp, c_vp]),
     ("fcgle_step", c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_vp]),

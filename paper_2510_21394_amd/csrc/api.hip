@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -20,6 +21,42 @@ using namespace fcgle;
 namespace {
 
 thread_local std::string g_last_error;
+
+}  // namespace
+
+// Work space of the allocation-free entry point fcgle_apply_f_noalloc: three state-sized
+// tensors of kNoAllocTensorBytes each in one file-scope device array, which every device the
+// library runs on holds from the load of its code object until the process ends.  In host code
+// the array's name is only a host-side stand-in: its device address on each device comes from
+// hipGetSymbolAddress, resolved once per device when a plan is set up there (with that device
+// current), and only that address is ever passed to kernels.
+constexpr size_t kNoAllocTensorBytes = (size_t)FCGLE_NOALLOC_TENSOR_BYTES;
+static __device__ __align__(256) unsigned char scratch[3 * kNoAllocTensorBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device dev, which must be current.  A failure leaves the
+// entry point unusable on that device (it then reports it) but not the rest of the plan.
+void resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[dev]) return;
+  void* p = nullptr;
+  if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) == hipSuccess && p)
+    g_scratch_ptr[dev] = p;
+  else
+    (void)hipGetLastError();  // do not leave the failure for the caller's next HIP call
+}
+
+unsigned char* scratch_ptr(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (unsigned char*)g_scratch_ptr[dev];
+}
 
 }  // namespace
 
@@ -138,13 +175,16 @@ SepParams sep_base(const fcgle_plan* P) {
   return s;
 }
 
+// Device f-grid for (kind, theta) if it was built, else nullptr.
+const void* find_grid(const fcgle_plan* P, int kind, double theta) {
+  for (auto& g : P->grids)
+    if (g.kind == kind && g.theta == theta) return g.F;
+  return nullptr;
+}
+
 // Device f-grid for (kind, theta), built on first use.
 int get_grid(fcgle_plan* P, int kind, double theta, hipStream_t st, const void** out) {
-  for (auto& g : P->grids)
-    if (g.kind == kind && g.theta == theta) {
-      *out = g.F;
-      return FCGLE_OK;
-    }
+  if ((*out = find_grid(P, kind, theta)) != nullptr) return FCGLE_OK;
   GridBuf g{kind, theta, nullptr};
   FC_TRY(plan_alloc(&g.F, (size_t)P->N * P->elem));
   SepParams s = sep_base(P);
@@ -174,13 +214,19 @@ void fill_sep(const SepBuf& e, const fcgle_plan* P, SepParams* sp) {
   sp->zim = e.theta * P->p.eta;
 }
 
-int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
+// Separable factors for theta into sp if they were built (true), else false.
+bool find_sep(const fcgle_plan* P, double theta, SepParams* sp) {
   *sp = sep_base(P);
   for (auto& e : P->seps)
     if (e.theta == theta) {
       fill_sep(e, P, sp);
-      return FCGLE_OK;
+      return true;
     }
+  return false;
+}
+
+int get_sep(fcgle_plan* P, double theta, SepParams* sp) {
+  if (find_sep(P, theta, sp)) return FCGLE_OK;
   SepBuf e{};
   e.theta = theta;
   int rc = FCGLE_OK;
@@ -1033,6 +1079,7 @@ int fcgle_setup(int d, const int64_t* n, const double* alpha, const double* h, c
     delete P;
     return rc;
   }
+  resolve_scratch(P->device);  // the plan's device is current here
   *out = P;
   return FCGLE_OK;
 }
@@ -1092,6 +1139,44 @@ int fcgle_apply_f(fcgle_plan* plan, int kind, double theta, const void* u_dev, v
   EpiParams eb;
   eb.out = out_dev;
   FC_TRY(tucker(plan, false, plan->s[2], ProKind::Id, ProParams(), EpiKind::Store, eb, plan->s[0], plan->s[1], st));
+  if (out_dev == plan->uhat_src) plan->uhat_valid = false;
+  return FCGLE_OK;
+}
+
+int fcgle_apply_f_noalloc(fcgle_plan* plan, int kind, double theta, const void* u_dev, void* out_dev,
+                          void* stream) {
+  FC_TRY(check_plan(plan));
+  if (!u_dev || !out_dev) return fail(FCGLE_ERR_ARG, "NULL tensor");
+  if (kind < FCGLE_INV || kind > FCGLE_PHI3) return fail(FCGLE_ERR_ARG, "bad kind %d", kind);
+  if (!std::isfinite(theta)) return fail(FCGLE_ERR_ARG, "theta not finite");
+  const size_t bytes = (size_t)plan->N * plan->elem;
+  if (bytes > kNoAllocTensorBytes)
+    return fail(FCGLE_ERR_ARG, "apply_f_noalloc: a state tensor of %zu bytes exceeds the work space limit of %zu "
+                "bytes per tensor", bytes, kNoAllocTensorBytes);
+  unsigned char* w = scratch_ptr(plan->device);
+  if (!w) return fail(FCGLE_ERR_HIP, "apply_f_noalloc: no work space address on device %d", plan->device);
+  EpiParams ep;
+  ep.out = w + 2 * kNoAllocTensorBytes;
+  EpiKind ek;
+  if (kind == FCGLE_EXP) {
+    ek = EpiKind::Sep;
+    if (!find_sep(plan, theta, &ep.sep))
+      return fail(FCGLE_ERR_STATE, "apply_f_noalloc: no separable exponential for theta %.17g yet (fcgle_apply_f "
+                  "builds it on its first call with this theta)", theta);
+  } else {
+    ek = EpiKind::Grid;
+    if (!(ep.F = find_grid(plan, kind, theta)))
+      return fail(FCGLE_ERR_STATE, "apply_f_noalloc: no f-grid for (kind %d, theta %.17g) yet (fcgle_apply_f "
+                  "builds it on its first call with this pair)", kind, theta);
+  }
+  DeviceGuard g(plan->device);
+  hipStream_t st = as_stream(stream);
+  void* w0 = w;
+  void* w1 = w + kNoAllocTensorBytes;
+  FC_TRY(tucker(plan, true, u_dev, ProKind::Id, ProParams(), ek, ep, w0, w1, st));
+  EpiParams eb;
+  eb.out = out_dev;
+  FC_TRY(tucker(plan, false, ep.out, ProKind::Id, ProParams(), EpiKind::Store, eb, w0, w1, st));
   if (out_dev == plan->uhat_src) plan->uhat_valid = false;
   return FCGLE_OK;
 }

@@ -102,6 +102,16 @@ class Plan:
         L.check(self.lib.fcgle_apply_f(self.handle, L.KINDS[kind], float(theta), _ptr(u), _ptr(out), _stream()))
         return out
 
+    def apply_f_noalloc(self, kind: str, theta: float, u: torch.Tensor, out: torch.Tensor):
+        """out = f(theta K) u like apply_f, with no device allocation (fcgle_apply_f_noalloc): the
+        library's fixed per-device work space instead of the plan's buffers.  apply_f must have
+        run once with the same (kind, theta) on this plan; states up to 16 MiB."""
+        self._check_tensor(u)
+        self._check_tensor(out, "out")
+        L.check(self.lib.fcgle_apply_f_noalloc(self.handle, L.KINDS[kind], float(theta), _ptr(u), _ptr(out),
+                                               _stream()))
+        return out
+
     def apply_inv_refined(self, theta: float, v: torch.Tensor, sweeps: int = 1,
                           out: Optional[torch.Tensor] = None, residuals: bool = False):
         """x = (I - theta (nu + i eta) K)^{-1} v to FP64 accuracy: the plan's precision for the
