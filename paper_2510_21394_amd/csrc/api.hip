@@ -321,7 +321,8 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
 
 // Whether the backward even/odd tile configuration cfg leaves LDS for the staged rows of the
 // on-the-fly update (the same budget the kernels are instantiated under: operand tiles with
-// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows 48-byte rows).
+// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows rows of 48 bytes for FP64
+// arithmetic and 32 bytes for FP32 arithmetic).
 bool otf_fits(int pr, int cfg) {
   const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
   const size_t nbuf = (size_t)cfg_bufs(pr, cfg, 1);
@@ -333,7 +334,7 @@ bool otf_fits(int pr, int cfg) {
     const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = 40;
     ops = nbuf * 2 * np * tm * ldk * 2 + nbuf * 2 * np * 2 * tnc * ldk * 2;
   }
-  return ops + (size_t)kOtfMaxRows * 48 <= 163840;
+  return ops + (size_t)kOtfMaxRows * (pr == P_F64 ? 48 : 32) <= 163840;
 }
 
 // One Tucker operator: out = epi( pro(in) x_1 M_1 ... x_d M_d ) with M = Q^T (fwd) or Q.
@@ -447,9 +448,11 @@ int default_cfg(int pr, int64_t n, bool split) {
 }
 
 // The exponential-Euler update can run in the loads of the first backward product (axis 0,
-// N loader) when that product is an even/odd one (any precision).
+// N loader) when that product is an even/odd one (any precision) and the state is below 2 GiB
+// (its element accesses use 32-bit byte offsets into bounds-checked buffers).
 bool update_prologue_ok(const fcgle_plan* P) {
-  return P->split && P->d > 1 && mp_supported(false, ProKind::Update, EpiKind::Store);
+  return P->split && P->d > 1 && (uint64_t)P->N * (uint64_t)P->elem < 0x80000000ull &&
+         mp_supported(false, ProKind::Update, EpiKind::Store);
 }
 
 // ... and with phi_1 formed on the fly (rows of axis 0 staged in LDS)

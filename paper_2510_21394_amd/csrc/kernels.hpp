@@ -515,6 +515,34 @@ struct EpiAxpyF {
 
 #undef FCGLE_EPI_APPLY
 
+// Complex elements through a buffer resource of `bytes` bytes: the hardware bounds check reads
+// an offset at or beyond the extent as zero and drops a store there, so masked element accesses
+// need neither clamped indices nor branches.  Offsets are 32-bit byte offsets (the update
+// prologue is only used for tensors below kBufMaxBytes); kOob is the offset of a masked access.
+constexpr uint32_t kBufMaxBytes = 0x80000000u;
+constexpr uint32_t kOob = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, float2*) {
+  return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off, double2*) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+template <class C>
+__device__ __forceinline__ C buf_load(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return buf_load(r, off, (C*)nullptr);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, float2 v) {
+  typedef unsigned int u2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, uint32_t off, double2 v) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), r, off, 0, 0);
+}
+
 // Exponential-Euler update applied while the first backward product loads its input
 // (instead of in the epilogue of the last forward product):
 //   uhat_out[j] = E_j uhat[j] + tau P1[j] ghat[j],
@@ -547,22 +575,37 @@ struct ProUpdateF {
       : uhat((const C*)p.uhat), P1((const C*)p.F), uhat_out((C*)p.uhat_out), fac((const zc*)p.sep.fac[p.sep.mu]),
         s(p.sep), tau(p.tau) {}
   __device__ __forceinline__ zc col(uint32_t a, uint32_t b) const { return sep_other(s, a, b); }
-  __device__ __forceinline__ Pre load(int64_t j, int i) const { return Pre{uhat[j], P1[j], fac[i]}; }
+  // operands of the element at byte offset off (kOob: reads zero) of row i (a valid row)
+  __device__ __forceinline__ Pre load(uint32_t off, int i, uint32_t bytes) const {
+    return Pre{buf_load<C>(buf_rsrc(uhat, bytes), off), buf_load<C>(buf_rsrc(P1, bytes), off), fac[i]};
+  }
   __device__ __forceinline__ C update(const zc& Eo, C g, const Pre& pre) const {
     const zc eu = zmul(zmul(Eo, pre.f), to_zc(pre.u));
     const C pg = cmul(pre.P, g);
     return from_zc<C>(zc{eu.re + tau * (double)pg.x, eu.im + tau * (double)pg.y});
   }
-  __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
+  __device__ __forceinline__ void save(uint32_t off, C v, uint32_t bytes) const {
+    buf_store(buf_rsrc(uhat_out, bytes), off, v);
+  }
 };
 
+// Reciprocal in the arithmetic precision: the hardware approximation (1 ulp) for FP32, the
+// correctly rounded quotient for FP64.
+__device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+
 // The same update with P1 = phi_1(z) = (e^z - 1) / z formed on the fly instead of read from the
-// P1 grid (one HBM stream less; the tables are FP64, the quotient is formed in the state
-// precision).  z = (zre + i zim)(lam_row + lam_col), e^z = E_col E_row
-// and e^z - 1 = a + b + a b with a = E_col - 1, b = E_row - 1 (all from separable tables, both
-// of the same sign pattern, so the sum does not cancel); below |z| = 1e-8 the series 1 + z/2.
-// The row entries (factor, factor - 1, eigenvalue of the axis) of all n rows are staged in LDS
-// once per workgroup (n <= kOtfMaxRows); the column context once per loader unit.
+// P1 grid (one HBM stream less).  All exponents of a plan share one complex direction:
+// z = zs (lam_row + lam_col) with zs = (zre + i zim) and a real eigenvalue sum l < 0, so
+// tau P1 = (tau / zs) (e^z - 1) / l needs one real reciprocal per element, with tau / zs formed
+// once on the host in FP64.  e^z = E_col E_row and e^z - 1 = a + b + a b with a = E_col - 1,
+// b = E_row - 1 from separable tables (both with Re <= 0 on every axis, so the sum does not
+// cancel and keeps full relative accuracy however small z is).  When zs = 0 every e^z - 1 is
+// exactly 0 and P1 = 1: tau / zs is then set to 0 and the constant tau added instead.
+// E uhat stays FP64 (a state-precision E would be a fixed per-element bias every step, see
+// EpiSepF); the correction is formed in the state precision R.  The row entries (E_row FP64,
+// and E_row - 1 and lam_row in R) of all n rows are staged in LDS once per workgroup
+// (n <= kOtfMaxRows); the column context once per loader unit.
 template <class R>
 struct ProUpdateOtfF {
   static constexpr bool kId = false;
@@ -573,52 +616,52 @@ struct ProUpdateOtfF {
     C u;
   };
   struct __attribute__((aligned(16))) RowEnt {
-    zc f, fm1;
-    double lam, pad_;
+    zc f;
+    R m1re, m1im, lam, pad_;
   };
   struct Col {
-    zc E, Em1;
-    double lam;
+    zc E;
+    R m1re, m1im, lam;
   };
   const C* uhat;
   C* uhat_out;
   SepParams s;
-  double tau;
+  double c1re = 0, c1im = 0;  // tau / zs (0 when zs = 0)
+  double t0 = 0;              // tau when zs = 0, else 0
   ProUpdateOtfF() = default;
-  explicit ProUpdateOtfF(const ProParams& p)
-      : uhat((const C*)p.uhat), uhat_out((C*)p.uhat_out), s(p.sep), tau(p.tau) {}
+  explicit ProUpdateOtfF(const ProParams& p) : uhat((const C*)p.uhat), uhat_out((C*)p.uhat_out), s(p.sep) {
+    const double zq = p.sep.zre * p.sep.zre + p.sep.zim * p.sep.zim;
+    if (zq > 0.0) {
+      c1re = p.tau * p.sep.zre / zq;
+      c1im = -p.tau * p.sep.zim / zq;
+    } else {
+      t0 = p.tau;
+    }
+  }
   __device__ __forceinline__ RowEnt row_entry(int i) const {
-    return RowEnt{((const zc*)s.fac[s.mu])[i], ((const zc*)s.facm1[s.mu])[i], s.lam[s.mu][i], 0.0};
+    const zc m1 = ((const zc*)s.facm1[s.mu])[i];
+    return RowEnt{((const zc*)s.fac[s.mu])[i], (R)m1.re, (R)m1.im, (R)s.lam[s.mu][i], (R)0};
   }
   __device__ __forceinline__ Col col(uint32_t, uint32_t b) const {
-    return Col{((const zc*)s.other_first)[b], ((const zc*)s.first_m1)[b], s.first_lam[b]};
+    const zc m1 = ((const zc*)s.first_m1)[b];
+    return Col{((const zc*)s.other_first)[b], (R)m1.re, (R)m1.im, (R)s.first_lam[b]};
   }
-  __device__ __forceinline__ Pre load(int64_t j, int) const { return Pre{uhat[j]}; }
-  // E u in FP64 (a state-precision E would be a fixed per-element bias every step, see
-  // EpiSepF); the correction tau phi_1(z) g in the state precision: e^z - 1 = a + b + ab from the
-  // per-axis expm1 values (no cancellation: Re z <= 0 on every axis), divided by z, with the
-  // series 1 + z/2 below |z| = 1e-8.
+  __device__ __forceinline__ Pre load(uint32_t off, int, uint32_t bytes) const {
+    return Pre{buf_load<C>(buf_rsrc(uhat, bytes), off)};
+  }
   __device__ __forceinline__ C update(const Col& c, const RowEnt& r, C g, const Pre& pre) const {
     const zc eu = zmul(zmul(c.E, r.f), to_zc(pre.u));
-    const R ar = (R)c.Em1.re, ai = (R)c.Em1.im, br = (R)r.fm1.re, bi = (R)r.fm1.im;
+    const R ar = c.m1re, ai = c.m1im, br = r.m1re, bi = r.m1im;
     const R mr = (ar + br) + (ar * br - ai * bi), mi = (ai + bi) + (ar * bi + ai * br);
-    const R l = (R)(c.lam + r.lam);
-    const R zr = (R)s.zre * l, zi = (R)s.zim * l;
-    const R zz = zr * zr + zi * zi;
-    R pr, pi;
-    if (zz > (R)1e-16) {
-      const R inv = (R)1 / zz;
-      pr = (mr * zr + mi * zi) * inv;
-      pi = (mi * zr - mr * zi) * inv;
-    } else {
-      pr = (R)1 + (R)0.5 * zr;
-      pi = (R)0.5 * zi;
-    }
-    const R t = (R)tau;
-    const R gr = t * (pr * g.x - pi * g.y), gi = t * (pr * g.y + pi * g.x);
+    const R rl = rcp_r(c.lam + r.lam);  // every eigenvalue is negative, so the sum is too
+    const R q1r = (R)c1re, q1i = (R)c1im;
+    const R pr = (mr * q1r - mi * q1i) * rl + (R)t0, pi = (mr * q1i + mi * q1r) * rl;
+    const R gr = pr * g.x - pi * g.y, gi = pr * g.y + pi * g.x;
     return from_zc<C>(zc{eu.re + (double)gr, eu.im + (double)gi});
   }
-  __device__ __forceinline__ void save(int64_t j, C v) const { uhat_out[j] = v; }
+  __device__ __forceinline__ void save(uint32_t off, C v, uint32_t bytes) const {
+    buf_store(buf_rsrc(uhat_out, bytes), off, v);
+  }
 };
 
 // ---------------------------------------------------------------------------------------
@@ -737,55 +780,54 @@ struct UpdColOf<Pro, true> {
   using type = decltype(std::declval<const Pro&>().col(0u, 0u));
 };
 
-// Loads of the update-prologue kernels (ProUpdateF): the tensor element, and the update's
-// operands, of each element of one B unit (same element mapping as load_b_unit).  Every
-// load is issued unconditionally from a clamped index (element 0 / row 0 when outside the
-// tensor) so that the loads of a k-tile stay in flight together; upd_b_unit zeroes the
-// elements outside the tensor when the tile is written to LDS.
-template <class C, int G, bool TL>
-__device__ __forceinline__ void load_b_unit_clamped(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
-                                                    int kb, int klim, int koff, C (&v)[G]) {
+// Element accesses of the update-prologue kernels (N loader only: column b of batch a, element
+// stride B along k).  Element e of a B unit is tensor row koff + kb + e; upd_offsets gives its
+// byte offset, or kOob where the column lies outside the tensor or kb + e >= klim, so that the
+// tensor element (ghat), the update's operands and the store of the new state all go through
+// bounds-checked buffer accesses at one offset per element: every load of a k-tile is issued
+// unconditionally (elements outside read as zero and the update of zeros is zero), and no store
+// needs a branch.
+template <int G>
+__device__ __forceinline__ void upd_offsets(const Geo& g, uint32_t a, uint32_t b, int kb, int klim, int koff,
+                                            uint32_t esize, uint32_t (&off)[G]) {
+  const bool colok = b < g.B;
+  const uint32_t o0 = (((uint32_t)a * (uint32_t)g.n + (uint32_t)(koff + kb)) * g.B + b) * esize;
+  const uint32_t st = g.B * esize;
 #pragma unroll
-  for (int e = 0; e < G; ++e) {
-    const int k = kb + e;
-    const int row = koff + k;
-    const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
-    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
-    v[e] = U[ok ? j : 0];
-  }
+  for (int e = 0; e < G; ++e) off[e] = (colok && kb + e < klim) ? o0 + (uint32_t)e * st : kOob;
 }
 
-template <class C, int G, bool TL, class Pro>
-__device__ __forceinline__ void pre_b_unit(const Geo& g, const Pro& pro, uint32_t a, uint32_t b, int kb, int klim,
-                                           int koff, typename Pro::Pre (&p)[G]) {
-#pragma unroll
-  for (int e = 0; e < G; ++e) {
-    const int k = kb + e;
-    const int row = koff + k;
-    const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
-    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
-    p[e] = pro.load(ok ? j : 0, ok ? row : 0);
-  }
+// Bytes of the update prologue's tensors (below kBufMaxBytes, checked by the host).
+template <class C>
+__device__ __forceinline__ uint32_t upd_bytes(const Geo& g) {
+  return g.A * (uint32_t)g.n * g.B * (uint32_t)sizeof(C);
 }
 
-template <class C, int G, bool TL, class Pro, class Ctx, class RowT>
-__device__ __forceinline__ void upd_b_unit(const Geo& g, const Pro& pro, uint32_t a, uint32_t b, int kb, int klim,
-                                           int koff, const Ctx& Eo, const typename Pro::Pre (&p)[G], bool write,
+template <class C, int G>
+__device__ __forceinline__ void load_b_unit_buf(__amdgpu_buffer_rsrc_t rU, const uint32_t (&off)[G], C (&v)[G]) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) v[e] = buf_load<C>(rU, off[e]);
+}
+
+template <class C, int G, class Pro>
+__device__ __forceinline__ void pre_b_unit(const Pro& pro, int kb, int klim, int koff, const uint32_t (&off)[G],
+                                           uint32_t bytes, typename Pro::Pre (&p)[G]) {
+#pragma unroll
+  for (int e = 0; e < G; ++e) p[e] = pro.load(off[e], kb + e < klim ? koff + kb + e : 0, bytes);
+}
+
+template <class C, int G, class Pro, class Ctx, class RowT>
+__device__ __forceinline__ void upd_b_unit(const Pro& pro, int kb, int klim, int koff, const uint32_t (&off)[G],
+                                           uint32_t bytes, const Ctx& Eo, const typename Pro::Pre (&p)[G], bool write,
                                            const RowT* rows, C (&v)[G]) {
-  const bool colok = TL ? a < g.A : b < g.B;
 #pragma unroll
   for (int e = 0; e < G; ++e) {
+    // outside the tensor the operands read as zero, so the update gives zero there
     if constexpr (Pro::kRowLds)
-      v[e] = (colok && kb + e < klim) ? pro.update(Eo, rows[koff + kb + e], v[e], p[e]) : C{0, 0};
+      v[e] = pro.update(Eo, rows[(kb + e < klim) ? koff + kb + e : 0], v[e], p[e]);
     else
-      v[e] = (colok && kb + e < klim) ? pro.update(Eo, v[e], p[e]) : C{0, 0};
-  }
-  if (!write) return;
-#pragma unroll
-  for (int e = 0; e < G; ++e) {
-    const int row = koff + kb + e;
-    const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
-    if (colok && kb + e < klim) pro.save(j, v[e]);
+      v[e] = pro.update(Eo, v[e], p[e]);
+    pro.save(write ? off[e] : kOob, v[e], bytes);
   }
 }
 
@@ -1087,10 +1129,15 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else if constexpr (UPD) {
-          load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.me, 0, rb[0][it]);
-          load_b_unit_clamped<C, G, TL>(g, U, a, b, kb, g.mo, g.me, rb[NR - 1][it]);
-          pre_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, rp[0][it]);
-          pre_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, rp[NR - 1][it]);
+          static_assert(!TL, "the update prologue runs on N-loader products");
+          const uint32_t bytes = upd_bytes<C>(g);
+          uint32_t o[G];
+          upd_offsets<G>(g, a, b, kb, g.me, 0, sizeof(C), o);
+          load_b_unit_buf<C, G>(buf_rsrc(U, bytes), o, rb[0][it]);
+          pre_b_unit<C, G>(pro, kb, g.me, 0, o, bytes, rp[0][it]);
+          upd_offsets<G>(g, a, b, kb, g.mo, g.me, sizeof(C), o);
+          load_b_unit_buf<C, G>(buf_rsrc(U, bytes), o, rb[NR - 1][it]);
+          pre_b_unit<C, G>(pro, kb, g.mo, g.me, o, bytes, rp[NR - 1][it]);
         } else {
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, G, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
@@ -1158,9 +1205,13 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         } else {
           if constexpr (UPD) {
             // the first row tile writes the updated state; every row tile contracts it
-            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
-            upd_b_unit<C, G, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rowtab,
-                                 rb[NR - 1][it]);
+            const uint32_t bytes = upd_bytes<C>(g);
+            uint32_t o[G];
+            upd_offsets<G>(g, a, b, kb, g.me, 0, sizeof(C), o);
+            upd_b_unit<C, G>(pro, kb, g.me, 0, o, bytes, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
+            upd_offsets<G>(g, a, b, kb, g.mo, g.me, sizeof(C), o);
+            upd_b_unit<C, G>(pro, kb, g.mo, g.me, o, bytes, eo[it], rp[NR - 1][it], mt == 0, rowtab,
+                                rb[NR - 1][it]);
           }
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB, row, kq, rb[0][it]);
           put_b(reinterpret_cast<R (*)[2 * TNC * LDK]>(&Bs[0][0]), buf * NB + 1, row, kq, rb[NR - 1][it]);
@@ -1444,10 +1495,15 @@ __global__ void __launch_bounds__(T::THREADS)
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else if constexpr (UPD) {
-          load_b_unit_clamped<C, LG, TL>(g, U, a, b, kb, g.me, 0, rb[0][it]);
-          load_b_unit_clamped<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, rb[NR - 1][it]);
-          pre_b_unit<C, LG, TL>(g, pro, a, b, kb, g.me, 0, rp[0][it]);
-          pre_b_unit<C, LG, TL>(g, pro, a, b, kb, g.mo, g.me, rp[NR - 1][it]);
+          static_assert(!TL, "the update prologue runs on N-loader products");
+          const uint32_t bytes = upd_bytes<C>(g);
+          uint32_t o[LG];
+          upd_offsets<LG>(g, a, b, kb, g.me, 0, sizeof(C), o);
+          load_b_unit_buf<C, LG>(buf_rsrc(U, bytes), o, rb[0][it]);
+          pre_b_unit<C, LG>(pro, kb, g.me, 0, o, bytes, rp[0][it]);
+          upd_offsets<LG>(g, a, b, kb, g.mo, g.me, sizeof(C), o);
+          load_b_unit_buf<C, LG>(buf_rsrc(U, bytes), o, rb[NR - 1][it]);
+          pre_b_unit<C, LG>(pro, kb, g.mo, g.me, o, bytes, rp[NR - 1][it]);
         } else {
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
           load_b_unit<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
@@ -1525,9 +1581,13 @@ __global__ void __launch_bounds__(T::THREADS)
         } else {
           if constexpr (UPD) {
             // the first row tile writes the updated state; every row tile contracts it
-            upd_b_unit<C, LG, TL>(g, pro, a, b, kb, g.me, 0, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
-            upd_b_unit<C, LG, TL>(g, pro, a, b, kb, g.mo, g.me, eo[it], rp[NR - 1][it], mt == 0, rowtab,
-                                  rb[NR - 1][it]);
+            const uint32_t bytes = upd_bytes<C>(g);
+            uint32_t o[LG];
+            upd_offsets<LG>(g, a, b, kb, g.me, 0, sizeof(C), o);
+            upd_b_unit<C, LG>(pro, kb, g.me, 0, o, bytes, eo[it], rp[0][it], mt == 0, rowtab, rb[0][it]);
+            upd_offsets<LG>(g, a, b, kb, g.mo, g.me, sizeof(C), o);
+            upd_b_unit<C, LG>(pro, kb, g.mo, g.me, o, bytes, eo[it], rp[NR - 1][it], mt == 0, rowtab,
+                                rb[NR - 1][it]);
           }
           put_b(buf, 0, row, kq, rb[0][it]);
           put_b(buf, NB - 1, row, kq, rb[NR - 1][it]);
