@@ -12,7 +12,8 @@ import os
 import torch  # noqa: F401  (loads the HIP runtime the library must share)
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfcgle.so")
+# FCGLE_LIB selects another build of the same library (the host-sanitizer build of build.py)
+LIB_PATH = os.environ.get("FCGLE_LIB") or os.path.join(HERE, "libfcgle.so")
 
 c_int = ctypes.c_int
 c_i64 = ctypes.c_int64
