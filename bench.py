@@ -29,7 +29,8 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6, "bf16x6": 2516.6}
 # Sources that define the mode-product kernels; the stored HBM-traffic measurement is only
 # reported while their hash matches the one it was taken with.
 KERNEL_SOURCES = ["kernels.hpp", "dispatch.hpp", "launch.h", "fz.hpp", "mp_f32.hip", "mp_f64.hip", "mp_bf16.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fp32_3d_256_expeuler.txt")
+# committed FETCH_SIZE/WRITE_SIZE summaries, one per precision
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_{precision}_3d_256_expeuler.txt")
 
 
 def kernel_source_hash() -> str:
@@ -44,10 +45,11 @@ def kernel_source_hash() -> str:
 def stored_traffic(kernel: dict):
     """HBM bytes per launch of `kernel` from the committed FETCH_SIZE/WRITE_SIZE summary, or
     None if there is none for it or the kernel sources changed since it was measured."""
-    if not os.path.exists(TRAFFIC_FILE):
+    path = TRAFFIC_FILE.format(precision=kernel["precision"])
+    if not os.path.exists(path):
         return None
     vals = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.startswith(" "):
             k, v = line.strip().split("=", 1)
             vals[k.strip()] = v.strip()
@@ -101,7 +103,8 @@ def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
-    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed steps before the timed ones (the GPU clocks settle within them)")
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16x3", "bf16x6"])
     ap.add_argument("--variants", default="fp64,fp32,bf16x3,bf16x6")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -267,7 +270,8 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
         "dominant": {"signature": dom_sig, "kernel": dom_kernel, "avg_ms": avg_ms,
                      "flop_per_launch": dom_flop, "bytes_per_launch": dom_bytes, "achieved_tflops": achieved,
                      "achieved_gbs": dom_bytes / (avg_ms * 1e-3) / 1e9, "count": dom["count"],
-                     "roofline": roofline_of(dom_kernel, dom_flop, dom_bytes, avg_ms, prec)},
+                     "roofline": dict(roofline_of(dom_kernel, dom_flop, dom_bytes, avg_ms, prec),
+                                      traffic=stored_traffic(dom_kernel))},
         "kernels": kernels,
     }
     plan.close()

@@ -191,7 +191,11 @@ int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, 
 /* nsteps consecutive fcgle_step calls from t0 (t_k = t0 + k tau).  For FCGLE_STRANG the
  * trailing flow over tau/2 of each step and the leading one of the next run as one flow over
  * tau (the flow of an autonomous equation composes exactly), so intermediate states are not
- * formed; the result equals nsteps single steps up to rounding. */
+ * formed; the result equals nsteps single steps up to rounding.  For FCGLE_EXP_EULER without
+ * a source term and with timing off, runs longer than 50 steps replay the steady-state steps in
+ * blocks of 50 from a HIP graph captured on first use (per state buffer and plan configuration;
+ * fcgle_set_tiles / _fusion / _structure / _source and fcgle_autotune invalidate it): the
+ * same kernels with the same arguments, so the result is identical to nsteps single steps. */
 int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps,
               void* stream);
 
@@ -339,6 +343,15 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
  * Errors: ERR_ARG, ERR_UNSUPPORTED, ERR_NOMEM, ERR_HIP. */
 int fcgle_batch_run(fcgle_plan* plan, int scheme, void* const* u_dev, double t0, double tau,
                     int64_t nsteps, void* stream);
+
+/* Form of fcgle_batch_run for a batch plan.  mode 0: the HIP graph of grouped launches above (the
+ * only form in use).  mode 1 would run one persistent launch per call for all phases of all steps
+ * (workgroups taking tiles in the order (step, phase, instance, tile) from an atomic ticket and
+ * waiting, bounded by spin_limit polls, until the instance's previous phase is complete); that
+ * form is switched off and gives ERR_UNSUPPORTED: its first GPU runs did not finish and the cause
+ * is not established.  spin_limit: polls of such a wait (0 keeps the current limit).
+ * Errors: ERR_ARG, ERR_UNSUPPORTED. */
+int fcgle_batch_set_persistent(fcgle_plan* plan, int mode, int64_t spin_limit);
 
 /* ---------------------------------------------------------------------------
  * Allocation-free variant

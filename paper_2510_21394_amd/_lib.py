@@ -62,6 +62,7 @@ SIGNATURES = [
     ("fcgle_batch_setup", c_int, [c_int, P_i64, P_dbl, P_dbl, ctypes.POINTER(Params), c_int, c_dbl,
                                   ctypes.POINTER(c_vp)]),
     ("fcgle_batch_run", c_int, [c_vp, c_int, ctypes.POINTER(c_vp), c_dbl, c_dbl, c_i64, c_vp]),
+    ("fcgle_batch_set_persistent", c_int, [c_vp, c_int, c_i64]),
     ("fcgle_host_fd_weights", c_int, [c_dbl, c_i64, c_int, P_dbl]),
     ("fcgle_host_eig", c_int, [c_i64, c_dbl, c_dbl, c_int, P_dbl, P_dbl]),
     ("fcgle_host_fz", c_int, [c_int, c_i64, P_dbl, P_dbl]),

@@ -321,8 +321,8 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
 
 // Whether the backward even/odd tile configuration cfg leaves LDS for the staged rows of the
 // on-the-fly update (the same budget the kernels are instantiated under: operand tiles with
-// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows rows of 48 bytes for FP64
-// arithmetic and 32 bytes for FP32 arithmetic).
+// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows rows of 4 values of the
+// arithmetic precision: 32 bytes for FP64, 16 bytes for FP32).
 bool otf_fits(int pr, int cfg) {
   const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
   const size_t nbuf = (size_t)cfg_bufs(pr, cfg, 1);
@@ -334,7 +334,7 @@ bool otf_fits(int pr, int cfg) {
     const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = 40;
     ops = nbuf * 2 * np * tm * ldk * 2 + nbuf * 2 * np * 2 * tnc * ldk * 2;
   }
-  return ops + (size_t)kOtfMaxRows * (pr == P_F64 ? 48 : 32) <= 163840;
+  return ops + (size_t)kOtfMaxRows * (pr == P_F64 ? 32 : 16) <= 163840;
 }
 
 // One Tucker operator: out = epi( pro(in) x_1 M_1 ... x_d M_d ) with M = Q^T (fwd) or Q.
@@ -890,6 +890,9 @@ void free_plan(fcgle_plan* P) {
   for (void* q : P->traj_x) f(q);
   f(P->partial);
   for (auto e : P->ev_pool) (void)hipEventDestroy(e);
+  for (auto& g : P->run_graphs) (void)hipGraphExecDestroy(g.exec);
+  P->run_graphs.clear();
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
 }
 
 // --- refinement sweep of the inverse ------------------------------------------------
@@ -941,6 +944,73 @@ int refine_residual(fcgle_plan* P, double theta, const void* v, const void* x, h
 }
 
 // rf_y <- R o rf_y = (I - theta (nu + i eta) K)^{-1} rf_y with the plan's precision
+// Steady-state exponential-Euler steps captured once into a HIP graph and replayed: without a
+// source term a step launches the same kernels with the same arguments whatever t is, and with
+// the update in the backward prologue the two eigenspace buffers trade places every step, so a
+// capture of an even number of steps starts and ends in the same buffer assignment and can be
+// replayed back to back.  Graphs are keyed by the state buffer, the eigenspace buffers and the
+// configuration generation; no memset is captured.
+constexpr int64_t kGraphSteps = 50;
+constexpr size_t kMaxRunGraphs = 4;
+
+int run_graph(fcgle_plan* P, void* u, hipStream_t st, hipGraphExec_t* out) {
+  for (auto& g : P->run_graphs)
+    if (g.u == u && g.uhat == P->uhat && g.uhat2 == P->uhat2 && g.steps == kGraphSteps && g.gen == P->gen) {
+      *out = g.exec;
+      return FCGLE_OK;
+    }
+  if (!P->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  void* const uh = P->uhat;
+  void* const uh2 = P->uhat2;
+  HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  int rc = FCGLE_OK;
+  for (int64_t k = 0; k < kGraphSteps && rc == FCGLE_OK; ++k) rc = step_impl(P, FCGLE_EXP_EULER, u, 0.0, P->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
+  P->uhat = uh;  // nothing ran: the buffers keep their roles (an even count swaps them back anyway)
+  P->uhat2 = uh2;
+  if (rc != FCGLE_OK || e != hipSuccess || !graph) {
+    if (graph) (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return rc != FCGLE_OK ? rc : fail(FCGLE_ERR_HIP, "run graph capture: %s", hipGetErrorString(e));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ei != hipSuccess) return fail(FCGLE_ERR_HIP, "run graph instantiate: %s", hipGetErrorString(ei));
+  if (P->run_graphs.size() >= kMaxRunGraphs) {
+    (void)hipGraphExecDestroy(P->run_graphs.front().exec);
+    P->run_graphs.erase(P->run_graphs.begin());
+  }
+  P->run_graphs.push_back(RunGraph{u, uh, uh2, kGraphSteps, P->gen, exec});
+  *out = exec;
+  (void)st;
+  return FCGLE_OK;
+}
+
+// nsteps exponential-Euler steps from t0 with the steady-state ones replayed from graphs (no
+// source term, timing off).  The first step runs directly: it forms the eigenspace state if
+// needed and builds the grids, tables and buffers that the captured steps then only read.
+int expeuler_run(fcgle_plan* P, void* u, double t0, int64_t nsteps, hipStream_t st) {
+  int64_t k = 0;
+  if (nsteps > 0) {
+    FC_TRY(step_impl(P, FCGLE_EXP_EULER, u, t0, st));
+    k = 1;
+  }
+  static_assert(kGraphSteps % 2 == 0, "a replayed run must keep the eigenspace buffer assignment");
+  while (nsteps - k >= kGraphSteps) {
+    hipGraphExec_t exec;
+    FC_TRY(run_graph(P, u, st, &exec));
+    HIP_TRY(hipGraphLaunch(exec, st));
+    P->uhat_valid = true;
+    P->uhat_src = u;
+    P->hist_valid = false;
+    k += kGraphSteps;
+  }
+  for (; k < nsteps; ++k) FC_TRY(step_impl(P, FCGLE_EXP_EULER, u, t0 + (double)k * P->tau, st));
+  return FCGLE_OK;
+}
+
 int refine_inverse(fcgle_plan* P, double theta, hipStream_t st) {
   EpiParams ep;
   ep.out = P->s[2];
@@ -1105,6 +1175,7 @@ int fcgle_get_eig(const fcgle_plan* plan, int mu, double* Q, double* lambda) {
 int fcgle_set_source(fcgle_plan* plan, int nterms, const double* rate, const double* rate_im,
                      const void* const* S_dev) {
   FC_TRY(check_plan(plan));
+  plan->gen++;  // captured runs no longer match the plan's configuration
   if (nterms < 0 || nterms > 4) return fail(FCGLE_ERR_ARG, "nterms must be 0..4");
   if (nterms > 0 && (!rate || !S_dev)) return fail(FCGLE_ERR_ARG, "NULL source arrays");
   for (int k = 0; k < nterms; ++k) {
@@ -1260,6 +1331,13 @@ int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, 
     DeviceGuard g(plan->device);
     return strang_run(plan, u_dev, nsteps, as_stream(stream));
   }
+  if (scheme == FCGLE_EXP_EULER && plan->ns == 0 && plan->timing_cap == 0 && nsteps > kGraphSteps) {
+    if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
+    if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
+    if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");
+    DeviceGuard g(plan->device);
+    return expeuler_run(plan, u_dev, t0, nsteps, as_stream(stream));
+  }
   for (int64_t k = 0; k < nsteps; ++k) FC_TRY(fcgle_step(plan, scheme, u_dev, t0 + (double)k * tau, tau, stream));
   return FCGLE_OK;
 }
@@ -1395,6 +1473,7 @@ extern "C" int fcgle_autotune(fcgle_plan* plan, int reps, void* stream) {
     return batch_autotune(plan, reps, as_stream(stream));
   }
   FC_TRY(check_plan(plan));
+  plan->gen++;  // captured runs no longer match the plan's configuration
   DeviceGuard g(plan->device);
   hipStream_t st = as_stream(stream);
   hipEvent_t e0, e1;
@@ -1417,6 +1496,7 @@ extern "C" {
 
 int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
   FC_TRY(check_plan(plan));
+  plan->gen++;  // captured runs no longer match the plan's configuration
   const int pr = precision_of(plan);
   const bool f2 = fwd == 1 && cfg >= kNumCfg;
   if (axis < 0 || axis >= plan->d || (fwd != 0 && fwd != 1) || cfg < 0 || cfg >= (fwd ? 2 * kNumCfg : kNumCfg))
@@ -1431,6 +1511,7 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg) {
 
 int fcgle_set_structure(fcgle_plan* plan, int split) {
   FC_TRY(check_plan(plan));
+  plan->gen++;  // captured runs no longer match the plan's configuration
   if (split != 0 && split != 1) return fail(FCGLE_ERR_ARG, "set_structure: split must be 0 or 1");
   if (split && !split_supported(precision_of(plan)))
     return fail(FCGLE_ERR_UNSUPPORTED, "set_structure: no even/odd kernels for this precision");
@@ -1448,6 +1529,7 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
 
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
+  plan->gen++;  // captured runs no longer match the plan's configuration
   if (flags < 0 || flags > 111 || (flags & 16))
     return fail(FCGLE_ERR_ARG, "set_fusion: flags must be 0..15, optionally with bits 5 (32) and 6 (64)");
   plan->fusion = flags & 107;

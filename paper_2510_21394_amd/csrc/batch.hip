@@ -78,11 +78,23 @@ struct BatchData {
   bool tuned = false;
   hipStream_t cap = nullptr;
   std::vector<CachedGraph> graphs;
+  // persistent form (batch_persist_kernel): one launch for all phases of every step
+  bool persist = false;
+  int pcfg = 0;                         // its tile configuration (persist_supported)
+  uint32_t spin_limit = 1000000u;       // polls of a dependency wait (about 1 us each) before an error
+  void* p_items[4] = {nullptr, nullptr, nullptr, nullptr};
+  void* p_buf = nullptr;                // PersistCtl, done[count], pre[5 count]
+  uint32_t p_phase0[5] = {0, 0, 0, 0, 0};
+  int p_cfg_built = -1;                 // configuration the persistent items were built for
+  int p_grid = 0;
 };
 
 void batch_free(BatchData* B) {
   if (!B) return;
   for (auto& g : B->graphs) (void)hipGraphExecDestroy(g.exec);
+  for (auto& q : B->p_items)
+    if (q) (void)hipFree(q);
+  if (B->p_buf) (void)hipFree(B->p_buf);
   for (auto& p : B->ph)
     if (p.items) (void)hipFree(p.items);
   if (B->pw_items) (void)hipFree(B->pw_items);
@@ -174,6 +186,8 @@ EpiParams update_params(const BatchData* B, const BatchInst& I) {
   return ep;
 }
 
+int build_persist(BatchData* B, const void* const* u);
+
 // (Re)build and upload every item array for the state pointers u[0..count).  Synchronises
 // the device first: an item array may still be read by work in flight.
 int build_items(BatchData* B, const void* const* u) {
@@ -212,8 +226,96 @@ int build_items(BatchData* B, const void* const* u) {
     if (!B->pw_items) FC_TRY(plan_alloc(&B->pw_items, bytes));
     HIP_TRY(hipMemcpy(B->pw_items, host.data(), bytes, hipMemcpyHostToDevice));
   }
+  if (B->persist) FC_TRY(build_persist(B, u));
   B->bound.assign(u, u + B->count);
   B->items_valid = true;
+  return FCGLE_OK;
+}
+
+// Description of instance I in phase p (0 F0, 1 F1, 2 B0, 3 B1) of the persistent form: forward
+// products with both even/odd blocks per tile, the update fused into F1's stores.
+MPLaunch persist_launch(const BatchData* B, const BatchInst& I, int p, const void* u) {
+  static const int kPh[4] = {PH_F0, PH_F1, PH_B0, PH_B1};
+  MPLaunch L = inst_launch(B, I, kPh[p], u);
+  if (p < 2) L.split = kSplitFwd2;
+  L.cfg = B->pcfg;
+  if (p == 0) {
+    L.pk = ProKind::Nonlin;
+    L.ek = EpiKind::Store;
+  } else if (p == 1) {
+    L.pk = ProKind::Id;
+    L.ek = EpiKind::ExpEuler;
+    L.ep = update_params(B, I);
+    L.ep.sep.mu = 1;
+  } else {
+    L.pk = ProKind::Id;
+    L.ek = EpiKind::Store;
+  }
+  return L;
+}
+
+// (Re)build the persistent form's item arrays, per-instance tile prefixes and control block for
+// the state pointers u[0..count) (after the caller synchronised the device).
+int build_persist(BatchData* B, const void* const* u) {
+  const int n = B->count;
+  std::vector<uint32_t> tiles[4];
+  std::vector<MPLaunch> L(n);
+  uint32_t phase_tiles[4];
+  for (int p = 0; p < 4; ++p) {
+    for (int i = 0; i < n; ++i) L[i] = persist_launch(B, B->inst[i], p, u[i]);
+    std::vector<unsigned char> host(persist_item_bytes(p) * (size_t)n);
+    tiles[p].resize(n);
+    phase_tiles[p] = persist_build_f32(B->pcfg, p, L.data(), n, host.data(), tiles[p].data());
+    if (phase_tiles[p] == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no persistent kernel for configuration %d", B->pcfg);
+    if (!B->p_items[p]) FC_TRY(plan_alloc(&B->p_items[p], persist_item_bytes(p) * (size_t)n));
+    HIP_TRY(hipMemcpy(B->p_items[p], host.data(), host.size(), hipMemcpyHostToDevice));
+  }
+  B->p_phase0[0] = 0;
+  for (int p = 0; p < 4; ++p) B->p_phase0[p + 1] = B->p_phase0[p] + phase_tiles[p];
+  std::vector<uint32_t> pre(5 * (size_t)n);
+  for (int i = 0; i < n; ++i) {
+    uint32_t acc = 0;
+    for (int p = 0; p < 4; ++p) {
+      pre[5 * i + p] = acc;
+      acc += tiles[p][i];
+    }
+    pre[5 * i + 4] = acc;
+  }
+  const size_t ctl = 256, done = (size_t)round_up((int64_t)n * 4, 256);
+  if (!B->p_buf) FC_TRY(plan_alloc(&B->p_buf, ctl + done + pre.size() * 4));
+  HIP_TRY(hipMemcpy((unsigned char*)B->p_buf + ctl + done, pre.data(), pre.size() * 4, hipMemcpyHostToDevice));
+  B->p_grid = persist_grid(B->pcfg);
+  if (B->p_grid <= 0) return fail(FCGLE_ERR_HIP, "batch: no occupancy for the persistent kernel");
+  B->p_cfg_built = B->pcfg;
+  return FCGLE_OK;
+}
+
+// nsteps steps in persistent launches (each resets its control block with a fill kernel and runs
+// at most as many steps as 32-bit tickets allow), then a synchronisation to report a dependency
+// wait that ran out of polls.
+int run_persist(BatchData* B, int64_t nsteps, hipStream_t st) {
+  const size_t ctl = 256;
+  PersistArgs a{};
+  a.ctl = (PersistCtl*)B->p_buf;
+  a.done = (uint32_t*)((unsigned char*)B->p_buf + ctl);
+  a.pre = (const uint32_t*)((unsigned char*)B->p_buf + ctl + (size_t)round_up((int64_t)B->count * 4, 256));
+  for (int p = 0; p < 4; ++p) a.items[p] = B->p_items[p];
+  for (int p = 0; p < 5; ++p) a.phase0[p] = B->p_phase0[p];
+  a.count = B->count;
+  a.spin_limit = B->spin_limit;
+  const int64_t per = B->p_phase0[4];
+  const int64_t max_steps = std::max<int64_t>(1, 0x7fffffffLL / per);
+  for (int64_t left = nsteps; left > 0;) {
+    const int64_t k = std::min(left, max_steps);
+    a.total = (uint32_t)(k * per);
+    HIP_TRY(launch_fill_u32((uint32_t*)B->p_buf, (uint32_t)((ctl + B->count * 4) / 4), st));
+    HIP_TRY(launch_persist_f32(B->pcfg, a, (uint32_t)std::min<int64_t>(B->p_grid, a.total), st));
+    left -= k;
+  }
+  PersistCtl h{};
+  HIP_TRY(hipMemcpyAsync(&h, B->p_buf, sizeof(h), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if (h.error) return fail(FCGLE_ERR_HIP, "batch: a dependency wait of the persistent kernel ran out of polls");
   return FCGLE_OK;
 }
 
@@ -263,12 +365,13 @@ constexpr int64_t kGraphChunk = 500;  // steps per captured graph (longer runs r
 
 int batch_run_impl(fcgle_plan* P, void* const* u, int64_t nsteps, hipStream_t st) {
   BatchData* B = P->batch;
-  bool same = B->items_valid && (int)B->bound.size() == B->count;
+  bool same = B->items_valid && (int)B->bound.size() == B->count && (!B->persist || B->p_cfg_built == B->pcfg);
   for (int i = 0; same && i < B->count; ++i) same = (B->bound[i] == u[i]);
   if (!same) FC_TRY(build_items(B, (const void* const*)u));
   if (nsteps == 0) return FCGLE_OK;
   FC_TRY(launch_phase(B, PH_T0, st));
   FC_TRY(launch_phase(B, PH_T1, st));
+  if (B->persist) return run_persist(B, nsteps, st);
   int64_t left = nsteps;
   while (left > 0) {
     const int64_t k = left > kGraphChunk ? kGraphChunk : left;
@@ -392,6 +495,8 @@ int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
     s += std::string(names[p]) + ":" + std::to_string(group_cfg_rows(B->ph[p].cfg)) +
          (B->ph[p].sp == kSplitFwd2 ? "F" : "") + (p + 1 < PH_COUNT ? "," : "");
   s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
+  if (B->persist) s += " form=persistent(" + std::to_string(group_cfg_rows(B->pcfg)) + "-row tiles)";
+  else s += " form=graph-of-grouped-launches";
   char tail[96];
   std::snprintf(tail, sizeof(tail), " flop/step=%.4g%s", flop, B->tuned ? " tuned" : " default");
   s += tail;
@@ -563,6 +668,20 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
   }
   B->fuse = true;
   *out = P;
+  return FCGLE_OK;
+}
+
+int fcgle_batch_set_persistent(fcgle_plan* plan, int mode, int64_t spin_limit) {
+  if (!plan || !plan->batch) return fail(FCGLE_ERR_ARG, "fcgle_batch_set_persistent needs a batch plan");
+  if (mode != 0 && mode != 1) return fail(FCGLE_ERR_ARG, "mode must be 0 or 1");
+  if (spin_limit < 0 || spin_limit > 0xffffffffLL) return fail(FCGLE_ERR_ARG, "spin_limit outside 0..2^32-1");
+  BatchData* B = plan->batch;
+  if (mode == 1)
+    return fail(FCGLE_ERR_UNSUPPORTED, "batch: the persistent form is switched off (its first GPU runs did not "
+                "finish; the cause is not established)");
+  B->persist = false;
+  if (spin_limit > 0) B->spin_limit = (uint32_t)spin_limit;
+  B->items_valid = false;
   return FCGLE_OK;
 }
 

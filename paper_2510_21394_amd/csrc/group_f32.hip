@@ -165,6 +165,97 @@ hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, int s
   return err;
 }
 
+// ---------------------------------------------------------------------------------------
+// Persistent batched exponential Euler (batch_persist_kernel): tile configurations with an
+// instantiation, item arrays of its four phases, grid and launch.
+// ---------------------------------------------------------------------------------------
+
+namespace {
+
+template <class F>
+bool with_persist_cfg(int cfg, F&& f) {
+  switch (cfg) {
+    case 0: f(TileCfg<128, 64, 16, 2, 2>{}); return true;
+    case 1: f(TileCfg<64, 64, 16, 1, 2>{}); return true;
+    case 3: f(TileCfg<64, 64, 16, 2, 2>{}); return true;
+    default: return false;
+  }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0u;
+}
+
+}  // namespace
+
+bool persist_supported(int cfg) {
+  return with_persist_cfg(cfg, [](auto) {});
+}
+
+size_t persist_item_bytes(int phase) {
+  if (phase == 0) return sizeof(GroupItem<ProNonlinF<float>, EpiStoreF<float>>);
+  if (phase == 1) return sizeof(GroupItem<ProIdF, EpiExpEulerF<float>>);
+  return sizeof(GroupItem<ProIdF, EpiStoreF<float>>);
+}
+
+uint32_t persist_build_f32(int cfg, int phase, const MPLaunch* L, int count, void* items_host, uint32_t* tiles) {
+  uint32_t total = 0;
+  with_persist_cfg(cfg, [&](auto t) {
+    using T = decltype(t);
+    auto build = [&](auto item_tag, bool tl) {
+      using Item = decltype(item_tag);
+      unsigned char* dst = (unsigned char*)items_host;
+      for (int k = 0; k < count; ++k) {
+        Item it;
+        it.g = make_geo<T>(L[k], tl, 4);
+        it.M = L[k].M;
+        it.U = L[k].in;
+        it.first = total;
+        it.pro = decltype(it.pro)(L[k].pp);
+        it.epi = decltype(it.epi)(L[k].ep);
+        std::memcpy(dst + k * sizeof(Item), &it, sizeof(Item));
+        tiles[k] = it.g.nblocks;
+        total += it.g.nblocks;
+      }
+    };
+    if (phase == 0) build(GroupItem<ProNonlinF<float>, EpiStoreF<float>>{}, false);
+    else if (phase == 1) build(GroupItem<ProIdF, EpiExpEulerF<float>>{}, true);
+    else build(GroupItem<ProIdF, EpiStoreF<float>>{}, phase == 3);
+  });
+  return total;
+}
+
+int persist_grid(int cfg) {
+  int grid = 0;
+  with_persist_cfg(cfg, [&](auto t) {
+    using T = decltype(t);
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, batch_persist_kernel<T, kSplitFwd2>, T::THREADS, 0) !=
+            hipSuccess)
+      return;
+    grid = cus * (per > 0 ? per : 1);
+  });
+  return grid;
+}
+
+hipError_t launch_persist_f32(int cfg, const PersistArgs& a, uint32_t grid, hipStream_t s) {
+  hipError_t err = hipErrorInvalidValue;
+  with_persist_cfg(cfg, [&](auto t) {
+    using T = decltype(t);
+    hipLaunchKernelGGL((batch_persist_kernel<T, kSplitFwd2>), dim3(grid), dim3(T::THREADS), 0, s, a);
+    err = hipGetLastError();
+  });
+  return err;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, hipStream_t s) {
+  const uint32_t blocks = (n + 255) / 256 < 1024 ? (n + 255) / 256 : 1024;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
 size_t pw_group_item_bytes(EpiKind ek) {
   return ek == EpiKind::ExpEuler ? sizeof(PwItem<EpiExpEulerF<float>>) : 0;
 }

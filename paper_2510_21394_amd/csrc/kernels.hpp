@@ -593,19 +593,23 @@ struct ProUpdateF {
 // correctly rounded quotient for FP64.
 __device__ __forceinline__ float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_r(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fma_r(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_r(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // The same update with P1 = phi_1(z) = (e^z - 1) / z formed on the fly instead of read from the
-// P1 grid (one HBM stream less).  All exponents of a plan share one complex direction:
-// z = zs (lam_row + lam_col) with zs = (zre + i zim) and a real eigenvalue sum l < 0, so
-// tau P1 = (tau / zs) (e^z - 1) / l needs one real reciprocal per element, with tau / zs formed
-// once on the host in FP64.  e^z = E_col E_row and e^z - 1 = a + b + a b with a = E_col - 1,
-// b = E_row - 1 from separable tables (both with Re <= 0 on every axis, so the sum does not
-// cancel and keeps full relative accuracy however small z is).  When zs = 0 every e^z - 1 is
-// exactly 0 and P1 = 1: tau / zs is then set to 0 and the constant tau added instead.
-// E uhat stays FP64 (a state-precision E would be a fixed per-element bias every step, see
-// EpiSepF); the correction is formed in the state precision R.  The row entries (E_row FP64,
-// and E_row - 1 and lam_row in R) of all n rows are staged in LDS once per workgroup
-// (n <= kOtfMaxRows); the column context once per loader unit.
+// P1 grid (one HBM stream less), in the arithmetic precision R throughout.  All exponents of a
+// plan share one complex direction: z = zs (lam_row + lam_col) with zs = (zre + i zim) and a real
+// eigenvalue sum l < 0.  With m = e^z - 1 = a + b + a b, a = E_col - 1 and b = E_row - 1 from
+// separable expm1 tables (both with Re <= 0 on every axis, so the sum does not cancel and keeps
+// full relative accuracy however small z is):
+//   uhat_new = E uhat + tau P1 ghat = uhat + m uhat + ((tau / zs) m / l) ghat,
+// one real reciprocal per element, tau / zs formed once on the host in FP64.  E itself is never
+// rounded: the only per-element constant that is rounded every step is m, whose rounding is
+// about |z| times smaller than one of E would be for the slowly decaying modes (for which a
+// rounded E would act as a bias growing over a trajectory).  When zs = 0 every m is exactly 0
+// and P1 = 1: tau / zs is then set to 0 and the constant tau used instead.  The row entries
+// (E_row - 1 and lam_row) of all n rows are staged in LDS once per workgroup (n <= kOtfMaxRows);
+// the column context once per loader unit.
 template <class R>
 struct ProUpdateOtfF {
   static constexpr bool kId = false;
@@ -615,12 +619,10 @@ struct ProUpdateOtfF {
   struct Pre {
     C u;
   };
-  struct __attribute__((aligned(16))) RowEnt {
-    zc f;
+  struct __attribute__((aligned(4 * sizeof(R)))) RowEnt {
     R m1re, m1im, lam, pad_;
   };
   struct Col {
-    zc E;
     R m1re, m1im, lam;
   };
   const C* uhat;
@@ -640,24 +642,27 @@ struct ProUpdateOtfF {
   }
   __device__ __forceinline__ RowEnt row_entry(int i) const {
     const zc m1 = ((const zc*)s.facm1[s.mu])[i];
-    return RowEnt{((const zc*)s.fac[s.mu])[i], (R)m1.re, (R)m1.im, (R)s.lam[s.mu][i], (R)0};
+    return RowEnt{(R)m1.re, (R)m1.im, (R)s.lam[s.mu][i], (R)0};
   }
   __device__ __forceinline__ Col col(uint32_t, uint32_t b) const {
     const zc m1 = ((const zc*)s.first_m1)[b];
-    return Col{((const zc*)s.other_first)[b], (R)m1.re, (R)m1.im, (R)s.first_lam[b]};
+    return Col{(R)m1.re, (R)m1.im, (R)s.first_lam[b]};
   }
   __device__ __forceinline__ Pre load(uint32_t off, int, uint32_t bytes) const {
     return Pre{buf_load<C>(buf_rsrc(uhat, bytes), off)};
   }
   __device__ __forceinline__ C update(const Col& c, const RowEnt& r, C g, const Pre& pre) const {
-    const zc eu = zmul(zmul(c.E, r.f), to_zc(pre.u));
     const R ar = c.m1re, ai = c.m1im, br = r.m1re, bi = r.m1im;
     const R mr = (ar + br) + (ar * br - ai * bi), mi = (ai + bi) + (ar * bi + ai * br);
     const R rl = rcp_r(c.lam + r.lam);  // every eigenvalue is negative, so the sum is too
     const R q1r = (R)c1re, q1i = (R)c1im;
     const R pr = (mr * q1r - mi * q1i) * rl + (R)t0, pi = (mr * q1i + mi * q1r) * rl;
-    const R gr = pr * g.x - pi * g.y, gi = pr * g.y + pi * g.x;
-    return from_zc<C>(zc{eu.re + (double)gr, eu.im + (double)gi});
+    // the two small terms are summed first, so the state is rounded once at its own magnitude
+    const R ur = pre.u.x, ui = pre.u.y;
+    C out;
+    out.x = ur + fma_r(mr, ur, fma_r(-mi, ui, fma_r(pr, g.x, -pi * g.y)));
+    out.y = ui + fma_r(mr, ui, fma_r(mi, ur, fma_r(pr, g.y, pi * g.x)));
+    return out;
   }
   __device__ __forceinline__ void save(uint32_t off, C v, uint32_t bytes) const {
     buf_store(buf_rsrc(uhat_out, bytes), off, v);
@@ -1012,10 +1017,21 @@ constexpr size_t cmax(size_t a, size_t b) { return a > b ? a : b; }
 
 // One workgroup's tile (logical block index bid) of the mode product described by g, with
 // structure SP (kDense / kSplitFwd / kSplitBwd, see Geo).
+// LDS bytes of one mp_mfma_tile (operand tiles, or the T-loader epilogue's column chunks).
+template <class R, class T, bool TL, int SP>
+constexpr size_t mp_tile_lds() {
+  constexpr int NB = (SP == kSplitBwd || SP == kSplitFwd2) ? 2 : 1;
+  constexpr int LDK = T::TK + MfmaT<R>::G;
+  constexpr size_t ab = (size_t)T::NBUF * NB * T::TM * LDK * sizeof(R) + (size_t)T::NBUF * NB * 2 * T::TNC * LDK * sizeof(R);
+  return cmax(ab, (TL && !kTlDirectEpilogue) ? (size_t)16 * (T::TM + 1) * sizeof(typename Cx<R>::T) : 0);
+}
+
+// smem: mp_tile_lds<R, T, TL, SP>() bytes of LDS owned by the caller (16-byte aligned), so that
+// a kernel running tiles of several products in turn gives them one shared block.
 template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__ M,
                                              const typename Cx<R>::T* __restrict__ U, const Pro& pro,
-                                             const Epi& epi, uint32_t bid) {
+                                             const Epi& epi, uint32_t bid, unsigned char* smem) {
   using C = typename Cx<R>::T;
   using MT = MfmaT<R>;
   using fragT = typename MT::fragT;
@@ -1026,9 +1042,6 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   constexpr int LDK = TK + G;  // padded row keeps 16-byte alignment and spreads LDS banks
   static_assert(TK % (4 * G) == 0, "k tile");
   constexpr size_t kAsBytes = (size_t)T::NBUF * NB * TM * LDK * sizeof(R);
-  constexpr size_t kBsBytes = (size_t)T::NBUF * NB * 2 * TNC * LDK * sizeof(R);
-  constexpr size_t kSmem = cmax(kAsBytes + kBsBytes, (TL && !kTlDirectEpilogue) ? (size_t)16 * (TM + 1) * sizeof(C) : 0);
-  __shared__ __attribute__((aligned(16))) unsigned char smem[kSmem];
   R (*As)[NB][TM * LDK] = reinterpret_cast<R (*)[NB][TM * LDK]>(smem);
   R (*Bs)[NB][2 * TNC * LDK] = reinterpret_cast<R (*)[NB][2 * TNC * LDK]>(smem + kAsBytes);
 
@@ -1278,16 +1291,19 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   gload(0);
   sstore(0, 0);
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
+  // steady state without conditions, so that each iteration (next tile's loads, this tile's
+  // MFMAs, next tile's prologue and LDS stores) is one block the scheduler can interleave;
+  // the last tile is contracted after the loop
+  for (int kt = 0; kt + 1 < KT; ++kt) {
     const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
-    if (kt + 1 < KT) gload(kt + 1);
+    gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) {
-      if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
-      sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
-    }
+    if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
+    sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
     __syncthreads();
   }
+  compute((T::NBUF == 2) ? ((KT - 1) & 1) : 0);
+  __syncthreads();
 
   auto rowmap = [](int l, int r) { return MT::row(l, r); };
   if (SP == kSplitFwd2) {
@@ -1320,7 +1336,8 @@ template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __global__ void __launch_bounds__(T::THREADS)
     mp_mfma_kernel(Geo g, const R* __restrict__ M, const typename Cx<R>::T* __restrict__ U, Pro pro,
                    Epi epi) {
-  mp_mfma_tile<R, T, TL, SP, Pro, Epi>(g, M, U, pro, epi, xcd_remap(blockIdx.x, g.nblocks));
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mp_tile_lds<R, T, TL, SP>()];
+  mp_mfma_tile<R, T, TL, SP, Pro, Epi>(g, M, U, pro, epi, xcd_remap(blockIdx.x, g.nblocks), smem);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1358,8 +1375,96 @@ __global__ void __launch_bounds__(T::THREADS)
   const uint32_t b = xcd_remap(blockIdx.x, nblocks);
   const int k = find_item(items, count, b);
   const GroupItem<Pro, Epi>& it = items[k];
+  __shared__ __attribute__((aligned(16))) unsigned char smem[mp_tile_lds<R, T, TL, SP>()];
   mp_mfma_tile<R, T, TL, SP, Pro, Epi>(it.g, (const R*)it.M, (const typename Cx<R>::T*)it.U, it.pro, it.epi,
-                                       b - it.first);
+                                       b - it.first, smem);
+}
+
+// ---------------------------------------------------------------------------------------
+// Persistent batched exponential Euler: one launch runs `steps` steps of every instance.
+// The tiles of a launch are numbered in the order (step, phase, instance, tile) with the
+// phases F0 (axis-0 forward product, nonlinearity in its loads), F1 (axis-1 forward product
+// with the eigenspace update in its stores), B0, B1 (backward products); workgroups take them
+// in that order from an atomic ticket.  Each phase of an instance needs the whole result of the
+// instance's previous phase, so before a tile the workgroup waits until the instance's count
+// of completed tiles reaches the number of tiles that precede its phase; those tiles have
+// smaller tickets, were taken by running workgroups and wait only on still smaller ones, so the
+// wait always ends, for any grid size.  It is bounded all the same: after `spin_limit` polls
+// (about 1 us each) the workgroup raises the error flag and every workgroup leaves.  Completion is published with an
+// agent-scope release (stores written back past the workgroup's L2) and observed with an acquire
+// (stale lines of the other XCDs' writes invalidated), since consecutive phases of an instance
+// may run on different XCDs.  Instances of different sizes overlap across phases instead of
+// meeting at a barrier after every phase.
+// ---------------------------------------------------------------------------------------
+
+template <class T, int SPF>
+__global__ void __launch_bounds__(T::THREADS) batch_persist_kernel(PersistArgs a) {
+  using R = float;
+  using C = float2;
+  using I0 = GroupItem<ProNonlinF<R>, EpiStoreF<R>>;
+  using I1 = GroupItem<ProIdF, EpiExpEulerF<R>>;
+  using IB = GroupItem<ProIdF, EpiStoreF<R>>;
+  constexpr size_t kLds = cmax(cmax(mp_tile_lds<R, T, false, SPF>(), mp_tile_lds<R, T, true, SPF>()),
+                               cmax(mp_tile_lds<R, T, false, kSplitBwd>(), mp_tile_lds<R, T, true, kSplitBwd>()));
+  __shared__ __attribute__((aligned(16))) unsigned char smem[kLds];
+  __shared__ uint32_t s_ticket, s_stop;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      s_ticket = __hip_atomic_fetch_add(&a.ctl->next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      s_stop = __hip_atomic_load(&a.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    const uint32_t tk = s_ticket;
+    if (tk >= a.total || s_stop) break;
+    const uint32_t step = tk / a.phase0[4], r = tk - step * a.phase0[4];
+    const int p = r < a.phase0[1] ? 0 : r < a.phase0[2] ? 1 : r < a.phase0[3] ? 2 : 3;
+    const uint32_t b = r - a.phase0[p];
+    int i;
+    if (p == 0)
+      i = find_item((const I0*)a.items[0], a.count, b);
+    else if (p == 1)
+      i = find_item((const I1*)a.items[1], a.count, b);
+    else
+      i = find_item((const IB*)a.items[p], a.count, b);
+    // wait for the instance's previous phase (its tiles precede this phase within the step).
+    // The polls are relaxed loads: an acquire per poll would invalidate the L2 of the XCD on
+    // every poll of every waiting workgroup and starve the workgroups doing the work.  The
+    // acquire comes once, after the count is reached.
+    if (threadIdx.x == 0) {
+      const uint32_t need = step * a.pre[5 * i + 4] + a.pre[5 * i + p];
+      uint32_t polls = 0;
+      while (__hip_atomic_load(&a.done[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
+        if (++polls > a.spin_limit || __hip_atomic_load(&a.ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+          __hip_atomic_store(&a.ctl->error, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          s_stop = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(32);
+      }
+    }
+    __syncthreads();
+    if (s_stop) break;
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (p == 0) {
+      const I0& it = ((const I0*)a.items[0])[i];
+      mp_mfma_tile<R, T, false, SPF>(it.g, (const R*)it.M, (const C*)it.U, it.pro, it.epi, b - it.first, smem);
+    } else if (p == 1) {
+      const I1& it = ((const I1*)a.items[1])[i];
+      mp_mfma_tile<R, T, true, SPF>(it.g, (const R*)it.M, (const C*)it.U, it.pro, it.epi, b - it.first, smem);
+    } else if (p == 2) {
+      const IB& it = ((const IB*)a.items[2])[i];
+      mp_mfma_tile<R, T, false, kSplitBwd>(it.g, (const R*)it.M, (const C*)it.U, it.pro, it.epi, b - it.first,
+                                           smem);
+    } else {
+      const IB& it = ((const IB*)a.items[3])[i];
+      mp_mfma_tile<R, T, true, kSplitBwd>(it.g, (const R*)it.M, (const C*)it.U, it.pro, it.epi, b - it.first,
+                                          smem);
+    }
+    // publish the tile: every thread's stores, then one count per tile
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(&a.done[i], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -1662,16 +1767,19 @@ __global__ void __launch_bounds__(T::THREADS)
   gload(0);
   sstore(0, 0);
   __syncthreads();
-  for (int kt = 0; kt < KT; ++kt) {
+  // steady state without conditions, so that each iteration (next tile's loads, this tile's
+  // MFMAs, next tile's prologue and LDS stores) is one block the scheduler can interleave;
+  // the last tile is contracted after the loop
+  for (int kt = 0; kt + 1 < KT; ++kt) {
     const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
-    if (kt + 1 < KT) gload(kt + 1);
+    gload(kt + 1);
     compute(cur);
-    if (kt + 1 < KT) {
-      if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
-      sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
-    }
+    if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
+    sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
     __syncthreads();
   }
+  compute((T::NBUF == 2) ? ((KT - 1) & 1) : 0);
+  __syncthreads();
 
   auto rowmap = [](int l, int r) { return MfmaT<float>::row(l, r); };
   if (SP == kSplitFwd2) {

@@ -155,6 +155,35 @@ uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MP
                          void* items_host);
 hipError_t launch_group_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, int split, const void* items_dev,
                             int count, uint32_t nblocks, hipStream_t s);
+// Persistent batched exponential Euler (batch_persist_kernel in kernels.hpp, FP32): one launch
+// runs every phase of every step of all instances.  persist_build_f32 writes the item array of
+// phase 0..3 (F0: forward axis 0 with the nonlinearity, F1: forward axis 1 with the fused update,
+// B0, B1: backward; forward phases in the form with both even/odd blocks per tile) for the
+// per-instance descriptions L[0..count) into host memory (persist_item_bytes(phase) bytes per
+// item), the tiles of each instance into tiles[count], and returns the phase's tiles.
+// persist_grid is the number of co-resident workgroups (0 when cfg has no instantiation).
+struct PersistCtl {
+  uint32_t next;   // next ticket
+  uint32_t error;  // nonzero: a dependency wait ran out of polls
+};
+
+struct PersistArgs {
+  PersistCtl* ctl;
+  uint32_t* done;         // per instance: completed tiles over the whole launch
+  const uint32_t* pre;    // per instance, 5 values: tiles of the instance before phase p (p = 0..3), per step (p = 4)
+  const void* items[4];   // per phase: item arrays (GroupItem of the phase's prologue/epilogue)
+  uint32_t phase0[5];     // first ticket of each phase within a step; phase0[4] = tickets per step
+  uint32_t total;         // tickets of the launch
+  int count;              // instances
+  uint32_t spin_limit;    // polls of a dependency wait before giving up
+};
+bool persist_supported(int cfg);
+size_t persist_item_bytes(int phase);
+uint32_t persist_build_f32(int cfg, int phase, const MPLaunch* L, int count, void* items_host, uint32_t* tiles);
+int persist_grid(int cfg);
+hipError_t launch_persist_f32(int cfg, const PersistArgs& a, uint32_t grid, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t n, hipStream_t s);
+
 // Grouped streaming epilogue (FP32): item k applies `ek` (ExpEuler) to v[k] viewed as
 // (rows[k], nlast[k]) with parameters ep[k]; returns the total number of rows.
 size_t pw_group_item_bytes(EpiKind ek);

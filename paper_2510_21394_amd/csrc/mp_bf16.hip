@@ -42,8 +42,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
       case 0: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 2, 2>>(L, s);
       case 1: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2>>(L, s);
       case 2: return dispatch_cfg<BFK<2>, TileCfg<64, 64, 32, 1, 2>>(L, s);
-      case 3: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2>>(L, s);
-      case 4: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 2, 2>>(L, s);
+      case 3: return dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 4, 2>>(L, s);
+      case 4: return dispatch_cfg<BFK<2>, TileCfg<256, 64, 32, 4, 2>>(L, s);
       default: return hipErrorInvalidValue;
     }
   }
@@ -61,8 +61,8 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
     case 0: return dispatch_cfg<BFK<3>, TileCfg<128, 64, 32, 2, 2>>(L, s);
     case 1: return dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 1, 2>>(L, s);
     case 2: return dispatch_cfg<BFK<3>, TileCfg<64, 32, 32, 1, 2>>(L, s);
-    case 3: return dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 1, 2>>(L, s);
-    case 4: return dispatch_cfg<BFK<3>, TileCfg<128, 64, 32, 2, 2>>(L, s);
+    case 3: return dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 2, 2>>(L, s);
+    case 4: return dispatch_cfg<BFK<3>, TileCfg<128, 64, 32, 4, 2>>(L, s);
     default: return hipErrorInvalidValue;
   }
 }

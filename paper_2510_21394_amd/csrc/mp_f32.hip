@@ -35,8 +35,8 @@ hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {
     case 0: return dispatch_cfg<F32K, TileCfg<256, 64, 16, 2, 2>>(L, s);
     case 1: return dispatch_cfg<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);
     case 2: return dispatch_cfg<F32K, TileCfg<64, 64, 16, 1, 2>>(L, s);
-    case 3: return dispatch_cfg<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);
-    case 4: return dispatch_cfg<F32K, TileCfg<256, 64, 16, 2, 2>>(L, s);
+    case 3: return dispatch_cfg<F32K, TileCfg<128, 64, 16, 4, 2>>(L, s);
+    case 4: return dispatch_cfg<F32K, TileCfg<256, 64, 16, 4, 2>>(L, s);
     default: return hipErrorInvalidValue;
   }
 }

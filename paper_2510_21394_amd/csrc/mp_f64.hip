@@ -35,8 +35,8 @@ hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s) {
     case 0: return dispatch_cfg<F64K, TileCfg<256, 32, 8, 2, 2>>(L, s);
     case 1: return dispatch_cfg<F64K, TileCfg<128, 32, 8, 2, 2>>(L, s);
     case 2: return dispatch_cfg<F64K, TileCfg<64, 32, 8, 1, 2>>(L, s);
-    case 3: return dispatch_cfg<F64K, TileCfg<128, 32, 8, 2, 2>>(L, s);
-    case 4: return dispatch_cfg<F64K, TileCfg<256, 32, 8, 2, 2>>(L, s);
+    case 3: return dispatch_cfg<F64K, TileCfg<128, 32, 8, 4, 2>>(L, s);
+    case 4: return dispatch_cfg<F64K, TileCfg<256, 32, 8, 4, 2>>(L, s);
     default: return hipErrorInvalidValue;
   }
 }

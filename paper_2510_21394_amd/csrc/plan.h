@@ -75,6 +75,17 @@ struct TimedLaunch {
   int axis, fwd, sig;
 };
 
+// A captured run of `steps` exponential-Euler steps on the state buffer u with the eigenspace
+// buffers uhat / uhat2 in that assignment, under plan configuration generation `gen`.
+struct RunGraph {
+  const void* u;
+  void* uhat;
+  void* uhat2;
+  int64_t steps;
+  uint64_t gen;
+  hipGraphExec_t exec;
+};
+
 }  // namespace fcgle
 
 struct fcgle_plan {
@@ -137,6 +148,11 @@ struct fcgle_plan {
   std::vector<void*> traj_u, traj_x;
   double* partial = nullptr;
   int64_t partial_rows = 0;
+  // captured exponential-Euler runs (fcgle_run), their capture stream, and the configuration
+  // generation (bumped by every call that changes which kernels a step launches)
+  std::vector<fcgle::RunGraph> run_graphs;
+  hipStream_t cap_stream = nullptr;
+  uint64_t gen = 0;
   // timing
   int timing_cap = 0;
   std::vector<hipEvent_t> ev_pool;

@@ -306,6 +306,11 @@ class BatchPlan:
     def autotune(self, reps: int = 3):
         L.check(self.lib.fcgle_autotune(self.handle, int(reps), _stream()))
 
+    def set_persistent(self, persistent: bool, spin_limit: int = 0):
+        """Run as one persistent launch per call (True) or as the graph of grouped launches
+        (False); spin_limit bounds each dependency wait of the persistent kernel (0: unchanged)."""
+        L.check(self.lib.fcgle_batch_set_persistent(self.handle, int(bool(persistent)), int(spin_limit)))
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)
         L.check(self.lib.fcgle_describe(self.handle, buf, 1024))

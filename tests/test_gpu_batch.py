@@ -83,6 +83,16 @@ def test_batch_calls_are_independent_and_rebind_buffers(F):
     plan.close()
 
 
+def test_persistent_form_is_refused(F):
+    insts = _instances()[:2]
+    plan = F.BatchPlan([i[:4] for i in insts], tau=1e-3)
+    with pytest.raises(F.FcgleError) as e:
+        plan.set_persistent(True)
+    assert e.value.code == -2
+    plan.set_persistent(False)
+    plan.close()
+
+
 def test_batch_argument_errors(F):
     insts = _instances()[:2]
     with pytest.raises(F.FcgleError) as e:
@@ -100,16 +110,73 @@ def test_batch_argument_errors(F):
     plan.close()
 
 
-def test_batch_workload_64_matches_stored_oracle(F):
+PERSISTENT_OFF = ("the persistent batch form is switched off: its first GPU runs stalled (killed for silence "
+                  "during autotuning) and the cause is not established")
+
+
+@pytest.mark.parametrize("persistent", [False, pytest.param(True, marks=pytest.mark.skip(reason=PERSISTENT_OFF))],
+                         ids=["graph", "persistent"])
+def test_small_batch_each_form_matches_oracle(F, persistent):
+    """The graph of grouped launches and the persistent kernel (its default tile configuration),
+    each against the oracle, over several calls (state carried between them)."""
+    insts = _instances(7)
+    tau = 1e-3
+    plan = F.BatchPlan([i[:4] for i in insts], tau=tau)
+    plan.set_persistent(persistent)
+    us = [_dev(i[4]) for i in insts]
+    plan.run(us, 0.0, 9)
+    plan.run(us, 9 * tau, 14)
+    print(plan.describe())
+    for (n, alpha, h, params, u0), u in zip(insts, us):
+        ref = O.run(O.Problem(n, alpha, h, params), "exp_euler", u0, tau, 23)
+        err = O.rel_l2(_host(u), ref)
+        print(f"[batch {'persistent' if persistent else 'graph'} {n}] rel_l2 = {err:.3e}")
+        assert err <= 1e-5
+    plan.close()
+
+
+@pytest.mark.skip(reason=PERSISTENT_OFF)
+def test_persistent_wait_limit_ends_the_run(F):
+    """A dependency wait of the persistent kernel that runs out of polls (forced from the host
+    with a limit of one poll) abandons the run: every workgroup leaves and the call reports
+    ERR_HIP (or, if no wait had to poll twice, the run completed and is correct).  A run with the
+    default limit afterwards is correct again."""
+    insts = _instances(9)
+    tau = 1e-3
+    plan = F.BatchPlan([i[:4] for i in insts], tau=tau)
+    plan.set_persistent(True, spin_limit=1)
+    us = [_dev(i[4]) for i in insts]
+    try:
+        plan.run(us, 0.0, 30)
+        failed = False
+    except F.FcgleError as e:
+        assert e.code == -4 and "ran out of polls" in str(e)
+        failed = True
+    print(f"tiny wait limit: run abandoned = {failed}")
+    if not failed:
+        for (n, alpha, h, params, u0), u in zip(insts, us):
+            assert O.rel_l2(_host(u), O.run(O.Problem(n, alpha, h, params), "exp_euler", u0, tau, 30)) <= 1e-5
+    plan.set_persistent(True, spin_limit=1000000)
+    us = [_dev(i[4]) for i in insts]
+    plan.run(us, 0.0, 30)
+    for (n, alpha, h, params, u0), u in zip(insts, us):
+        assert O.rel_l2(_host(u), O.run(O.Problem(n, alpha, h, params), "exp_euler", u0, tau, 30)) <= 1e-5
+    plan.close()
+
+
+@pytest.mark.parametrize("form", ["tuned", pytest.param("persistent", marks=pytest.mark.skip(reason=PERSISTENT_OFF))])
+def test_batch_workload_64_matches_stored_oracle(F, form):
     """64 instances (sizes 96..512 per axis, seed 2510), 500 steps, tau = 1e-3: 256 stored
     oracle samples per instance; the relative error is taken over each instance's samples
-    against the norm of the samples."""
+    against the norm of the samples.  In the autotuned form and forced to the persistent kernel."""
     if not os.path.exists(GOLDEN):
         pytest.skip("stored oracle outputs not generated")
     g = dict(np.load(GOLDEN))
     insts = batch_2d()
     plan = F.BatchPlan([(i.n, i.alpha, i.h, i.params) for i in insts], tau=BATCH_TAU)
     plan.autotune(2)
+    if form == "persistent":
+        plan.set_persistent(True)
     print(plan.describe())
     us = [_dev(u0_batch(i)) for i in insts]
     plan.run(us, 0.0, BATCH_STEPS)
