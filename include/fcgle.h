@@ -268,6 +268,17 @@ int fcgle_set_tiles(fcgle_plan* plan, int axis, int fwd, int cfg);
  * Resets the tile choice to its default (autotune again after).  Errors: ERR_ARG. */
 int fcgle_set_structure(fcgle_plan* plan, int split);
 
+/* Loads of the mode products' tensor operand.  Every product reads its k-tiles through
+ * 32-bit offsets from per-k-tile buffer views, except N-loader products (an axis other than
+ * the last) whose 32 rows at element stride B = n_{mu+1} ... n_d span more than 2 GiB
+ * (B > 2^23 for complex64, 2^22 for complex128): those use a tile configuration with 64-bit
+ * element indices, chosen by the library and reported by fcgle_describe as
+ * "loads=64-bit-index(axes ...)".  force = 1 takes that configuration for every N-loader
+ * product (to test it on small tensors; results agree with the other configurations to
+ * rounding order); force = 0 restores the automatic choice.
+ * Errors: ERR_ARG. */
+int fcgle_set_wide_loads(fcgle_plan* plan, int force);
+
 /* Fusion switches: bit 0 fuses the pointwise prologue (nonlinearity) into the first
  * mode product of a Tucker operator, bit 1 fuses the pointwise epilogue (f-scale,
  * exponential-Euler update, LBDF2 history) into the last one; a cleared bit runs that

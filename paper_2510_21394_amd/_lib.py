@@ -55,6 +55,7 @@ SIGNATURES = [
     ("fcgle_set_tiles", c_int, [c_vp, c_int, c_int, c_int]),
     ("fcgle_set_fusion", c_int, [c_vp, c_int]),
     ("fcgle_set_structure", c_int, [c_vp, c_int]),
+    ("fcgle_set_wide_loads", c_int, [c_vp, c_int]),
     ("fcgle_describe", c_int, [c_vp, ctypes.c_char_p, ctypes.c_size_t]),
     ("fcgle_timing_enable", c_int, [c_vp, c_int]),
     ("fcgle_timing_read", c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int),

@@ -306,6 +306,7 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
   L.A = A;
   L.B = B;
   L.n = (int)P->n[mu];
+  L.wide = P->wide_force;
   if (P->split) {
     L.split = fwd ? (P->fwd2[mu] ? 3 : 1) : 2;
     L.me = P->me[mu];
@@ -1527,6 +1528,14 @@ int fcgle_set_structure(fcgle_plan* plan, int split) {
   return FCGLE_OK;
 }
 
+int fcgle_set_wide_loads(fcgle_plan* plan, int force) {
+  FC_TRY(check_plan(plan));
+  if (force != 0 && force != 1) return fail(FCGLE_ERR_ARG, "set_wide_loads: force must be 0 or 1");
+  plan->gen++;  // captured runs no longer match the plan's configuration
+  plan->wide_force = (force != 0);
+  return FCGLE_OK;
+}
+
 int fcgle_set_fusion(fcgle_plan* plan, int flags) {
   FC_TRY(check_plan(plan));
   plan->gen++;  // captured runs no longer match the plan's configuration
@@ -1568,6 +1577,14 @@ int fcgle_describe(const fcgle_plan* plan, char* buf, size_t len) {
     }
   }
   s += plan->fwd_rev ? " forward-order=reversed" : " forward-order=natural";
+  {
+    std::string w;
+    for (int m = 0; m < plan->d; ++m) {
+      const MPLaunch L = base_launch(plan, m, false);
+      if (mp_wide(L)) w += (w.empty() ? "" : ",") + std::to_string(m);
+    }
+    if (!w.empty()) s += " loads=64-bit-index(axes " + w + ")";
+  }
   s += plan->tuned ? " tuned" : " default";
   std::snprintf(buf, len, "%s", s.c_str());
   return FCGLE_OK;

@@ -70,6 +70,9 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
         return hipErrorInvalidValue;
     }
   }
+  if constexpr (T::WIDE) {
+    return hipErrorInvalidValue;  // T-loader offsets always fit the buffer views
+  } else {
   if (L.pk != ProKind::Id) {
     if constexpr (SP != kSplitBwd)
       if (L.ek == EpiKind::Store) {
@@ -103,6 +106,7 @@ hipError_t dispatch_combo(const MPLaunch& L, hipStream_t s) {
       return hipErrorInvalidValue;
     default:
       return hipErrorInvalidValue;
+  }
   }
 }
 

@@ -675,9 +675,12 @@ struct ProUpdateOtfF {
 
 // NBUF_: operand tiles in LDS double-buffered (2: one barrier per k-tile) or single-buffered (1:
 // half the LDS, so more workgroups can share a CU, for a second barrier per k-tile).
-template <int TM_, int TNC_, int TK_, int WM_, int WN_, int NBUF_ = 2>
+// WIDE_: the B operand is read with 64-bit element indices (load_b_unit_wide) instead of
+// per-k-tile buffer views, for products whose k-tile rows span more than the views' 2 GiB.
+template <int TM_, int TNC_, int TK_, int WM_, int WN_, int NBUF_ = 2, bool WIDE_ = false>
 struct TileCfg {
   static constexpr int TM = TM_, TNC = TNC_, TK = TK_, WM = WM_, WN = WN_, NBUF = NBUF_;
+  static constexpr bool WIDE = WIDE_;
   static_assert(NBUF == 1 || NBUF == 2, "operand buffers");
   static constexpr int THREADS = 64 * WM * WN;
   static constexpr int NW = WM * WN;
@@ -747,9 +750,43 @@ struct MfmaT<double> {
 // global loads of the next k-tile stay in flight during the MFMA work of the current one.
 // Element k (kb <= k < kb + G) of a B unit is tensor row koff + k, or n - 1 - k when rev;
 // rows with k >= klim read as zero.
+//
+// Each load set of a k-tile (rows koff + k, or n - 1 - k, for k0 <= k < k0 + TK) is read
+// through a buffer resource of its own (BView): for the N loader it is based at the set's
+// lowest row of batch a0, so that an element's byte offset ((row - rb) B + b) sizeof(C) stays
+// below TK B sizeof(C); for the T loader it is based at the tile's first column a0, and the
+// offset ((a - a0) n + row) sizeof(C) stays below TNC n sizeof(C).  Both must stay below 2^31
+// (kOob): the host launches the WIDE configurations (load_b_unit_wide) for N-loader products
+// with 32 B sizeof(C) above that.  Masked elements take offset kOob and read as zero, so that
+// every load of a k-tile is issued unconditionally: no branch, no wait inside the loader, and
+// 32-bit offsets.
+template <class C>
+struct BView {
+  __amdgpu_buffer_rsrc_t r;
+  int rb;  // N loader: tensor row at the base
+};
+
+template <class C, int TK, bool TL>
+__device__ __forceinline__ BView<C> b_view(const Geo& g, const C* U, uint64_t tbytes, uint32_t a0, int k0, int koff,
+                                           bool rev) {
+  int rb = 0;
+  uint64_t e0;
+  if (TL) {
+    e0 = (uint64_t)a0 * (uint32_t)g.n;
+  } else {
+    rb = rev ? max(g.n - k0 - TK, 0) : koff + k0;
+    e0 = ((uint64_t)a0 * (uint32_t)g.n + (uint32_t)rb) * g.B;
+  }
+  const uint64_t left = tbytes - e0 * sizeof(C);
+  const uint32_t nrec = left < kBufMaxBytes ? (uint32_t)left : kBufMaxBytes;
+  return {buf_rsrc(U + e0, nrec), rb};
+}
+
+// The same unit through 64-bit element indices, each element loaded under its own condition:
+// for products whose k-tile rows span more than 2 GiB (T::WIDE configurations only).
 template <class C, int G, bool TL>
-__device__ __forceinline__ void load_b_unit(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
-                                            int kb, int klim, int koff, bool rev, C (&v)[G]) {
+__device__ __forceinline__ void load_b_unit_wide(const Geo& g, const C* __restrict__ U, uint32_t a, uint32_t b,
+                                                 int kb, int klim, int koff, bool rev, C (&v)[G]) {
 #pragma unroll
   for (int e = 0; e < G; ++e) {
     const int k = kb + e;
@@ -757,6 +794,21 @@ __device__ __forceinline__ void load_b_unit(const Geo& g, const C* __restrict__ 
     const bool ok = (TL ? a < g.A : b < g.B) && k < klim;
     const int64_t j = TL ? (int64_t)a * g.n + row : ((int64_t)a * g.n + row) * g.B + b;
     v[e] = ok ? U[j] : C{0, 0};
+  }
+}
+
+template <class C, int G, bool TL>
+__device__ __forceinline__ void load_b_unit(const Geo& g, const BView<C>& vw, uint32_t a0, uint32_t a, uint32_t b,
+                                            int kb, int klim, int koff, bool rev, C (&v)[G]) {
+  const bool colok = TL ? a < g.A : b < g.B;
+  const int row0 = rev ? g.n - 1 - kb : koff + kb;
+  const uint32_t st = TL ? (uint32_t)sizeof(C) : g.B * (uint32_t)sizeof(C);
+  const uint32_t o0 = TL ? ((a - a0) * (uint32_t)g.n + (uint32_t)row0) * (uint32_t)sizeof(C)
+                         : ((uint32_t)(row0 - vw.rb) * g.B + b) * (uint32_t)sizeof(C);
+#pragma unroll
+  for (int e = 0; e < G; ++e) {
+    const uint32_t o = rev ? o0 - (uint32_t)e * st : o0 + (uint32_t)e * st;
+    v[e] = buf_load<C>(vw.r, (colok && kb + e < klim) ? o : kOob);
   }
 }
 
@@ -1111,6 +1163,8 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
       kq = u / TNC;
     }
   };
+  const uint64_t tbytes = (uint64_t)g.A * (uint32_t)g.n * g.B * sizeof(C);
+  const uint32_t a0 = TL ? c0 : a_fix;
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
@@ -1125,6 +1179,17 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         }
       }
     }
+    // the k-tile's B views: set 0 is rows k (koff 0); set 1 is rows n - 1 - k (forward
+    // even/odd products) or rows me + k (backward even/odd products)
+    const BView<C> v0 = b_view<C, TK, TL>(g, U, tbytes, a0, k0, 0, false);
+    const BView<C> v1 = b_view<C, TK, TL>(g, U, tbytes, a0, k0, SP == kSplitBwd ? g.me : 0,
+                                          SP == kSplitFwd || SP == kSplitFwd2);
+    auto ldb = [&](int set, uint32_t a, uint32_t b, int kb, int klim, int koff, bool rev, C (&dst)[G]) {
+      if constexpr (T::WIDE)
+        load_b_unit_wide<C, G, TL>(g, U, a, b, kb, klim, koff, rev, dst);
+      else
+        load_b_unit<C, G, TL>(g, set ? v1 : v0, a0, a, b, kb, klim, koff, rev, dst);
+    };
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
@@ -1134,13 +1199,13 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
         const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
         const int kb = k0 + kq * G;
         if (SP == kDense) {
-          load_b_unit<C, G, TL>(g, U, a, b, kb, g.n, 0, false, rb[0][it]);
+          ldb(0, a, b, kb, g.n, 0, false, rb[0][it]);
         } else if (SP == kSplitFwd) {
-          load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
-          load_b_unit<C, G, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+          ldb(0, a, b, kb, K, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, K, 0, true, rb[NR - 1][it]);
         } else if (SP == kSplitFwd2) {
-          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
-          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
+          ldb(0, a, b, kb, g.me, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else if constexpr (UPD) {
           static_assert(!TL, "the update prologue runs on N-loader products");
           const uint32_t bytes = upd_bytes<C>(g);
@@ -1152,8 +1217,8 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
           load_b_unit_buf<C, G>(buf_rsrc(U, bytes), o, rb[NR - 1][it]);
           pre_b_unit<C, G>(pro, kb, g.mo, g.me, o, bytes, rp[NR - 1][it]);
         } else {
-          load_b_unit<C, G, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
-          load_b_unit<C, G, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
+          ldb(0, a, b, kb, g.me, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
         }
       }
     }
@@ -1246,11 +1311,16 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
           for (int r = 0; r < 4; ++r) acc[h][fm][fn][p][r] = 0;
 
   const int lr = lane & 15, lk = (lane >> 4) * G;
-  auto compute = [&](int buf) {
+  // part `part` of `parts` of the tile's MFMA work, split over its (block, row fragment) pairs
+  auto compute = [&](int buf, int part, int parts) {
 #pragma unroll
     for (int h = 0; h < NB; ++h) {
       const R* as = As[buf][h];
       const R* bs = Bs[buf][h];
+      bool any = false;
+#pragma unroll
+      for (int fm = 0; fm < T::FM; ++fm) any |= (h * T::FM + fm) * parts / (NB * T::FM) == part;
+      if (!any) continue;
 #pragma unroll
       for (int kg = 0; kg < TK; kg += 4 * G) {
         fragT bf[T::FNC][2];
@@ -1261,6 +1331,7 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
             bf[fn][p] = *(const fragT*)&bs[(p * TNC + wn * T::WTNC + fn * 16 + lr) * LDK + kg + lk];
 #pragma unroll
         for (int fm = 0; fm < T::FM; ++fm) {
+          if ((h * T::FM + fm) * parts / (NB * T::FM) != part) continue;
           const fragT af = *(const fragT*)&as[(wm * T::WTM + fm * 16 + lr) * LDK + kg + lk];
 #pragma unroll
           for (int s = 0; s < G; ++s)
@@ -1291,18 +1362,31 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   gload(0);
   sstore(0, 0);
   __syncthreads();
-  // steady state without conditions, so that each iteration (next tile's loads, this tile's
-  // MFMAs, next tile's prologue and LDS stores) is one block the scheduler can interleave;
-  // the last tile is contracted after the loop
+  // steady state without conditions; the last tile is contracted after the loop.  The
+  // scheduling barriers fix the order of each iteration: the next tile's global loads are all
+  // issued first (left to itself the scheduler sinks them towards their use, into the last few
+  // MFMAs, where their latency is exposed), then the first part of this tile's MFMA work, the
+  // waits for the loads with the prologue and the LDS stores into the other buffer, and the
+  // rest of the MFMA work, so that the stores overlap MFMAs and the barrier ends the iteration
+  // right after the last of them.  With one buffer the stores wait for every wave's reads.
   for (int kt = 0; kt + 1 < KT; ++kt) {
     const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
     gload(kt + 1);
-    compute(cur);
-    if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
-    sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (T::NBUF == 2) {
+      compute(cur, 0, 2);
+      __builtin_amdgcn_sched_barrier(0);
+      sstore(cur ^ 1, kt + 1);
+      __builtin_amdgcn_sched_barrier(0);
+      compute(cur, 1, 2);
+    } else {
+      compute(cur, 0, 1);
+      __syncthreads();  // every wave is done reading the one buffer
+      sstore(0, kt + 1);
+    }
     __syncthreads();
   }
-  compute((T::NBUF == 2) ? ((KT - 1) & 1) : 0);
+  compute((T::NBUF == 2) ? ((KT - 1) & 1) : 0, 0, 1);
   __syncthreads();
 
   auto rowmap = [](int l, int r) { return MT::row(l, r); };
@@ -1332,8 +1416,23 @@ __device__ __forceinline__ void mp_mfma_tile(const Geo& g, const R* __restrict__
   }
 }
 
+// Waves per SIMD asked of the register allocator for a workgroup of T::THREADS threads using
+// `lds` bytes of LDS: an 8-wave workgroup whose LDS leaves room for a second one is held to
+// 128 VGPRs (4 waves per SIMD), so that two workgroups share a CU and one's prologue and
+// epilogue overlap the other's MFMA loop; no request otherwise (1).
+template <class T>
+constexpr int mp_waves_per_eu(size_t lds) {
+  return (T::THREADS == 512 && 2 * lds <= kLdsBytes) ? 4 : 1;
+}
+template <class R, class Pro>
+constexpr size_t pro_row_lds() {
+  using RowT = typename std::conditional_t<Pro::kUpdate, Pro, ProUpdateF<R>>::RowEnt;
+  return Pro::kRowLds ? (size_t)kOtfMaxRows * sizeof(RowT) : 0;
+}
+
 template <class R, class T, bool TL, int SP, class Pro, class Epi>
 __global__ void __launch_bounds__(T::THREADS)
+    __attribute__((amdgpu_waves_per_eu(mp_waves_per_eu<T>(mp_tile_lds<R, T, TL, SP>() + pro_row_lds<R, Pro>()))))
     mp_mfma_kernel(Geo g, const R* __restrict__ M, const typename Cx<R>::T* __restrict__ U, Pro pro,
                    Epi epi) {
   __shared__ __attribute__((aligned(16))) unsigned char smem[mp_tile_lds<R, T, TL, SP>()];
@@ -1570,6 +1669,8 @@ __global__ void __launch_bounds__(T::THREADS)
       kq = u / TNC;
     }
   };
+  const uint64_t tbytes = (uint64_t)g.A * (uint32_t)g.n * g.B * sizeof(C);
+  const uint32_t a0 = TL ? c0 : a_fix;
   auto gload = [&](int kt) {
     const int k0 = kt * TK;
 #pragma unroll
@@ -1583,6 +1684,17 @@ __global__ void __launch_bounds__(T::THREADS)
           ra[h][it] = *(const v8bf*)&Ma[(h * NP + q) * piece + (int64_t)(m0 + row) * g.npad + k0 + kq * 8];
         }
       }
+    // the k-tile's B views: set 0 is rows k (koff 0); set 1 is rows n - 1 - k (forward
+    // even/odd products) or rows me + k (backward even/odd products)
+    const BView<C> v0 = b_view<C, TK, TL>(g, U, tbytes, a0, k0, 0, false);
+    const BView<C> v1 = b_view<C, TK, TL>(g, U, tbytes, a0, k0, SP == kSplitBwd ? g.me : 0,
+                                          SP == kSplitFwd || SP == kSplitFwd2);
+    auto ldb = [&](int set, uint32_t a, uint32_t b, int kb, int klim, int koff, bool rev, C (&dst)[LG]) {
+      if constexpr (T::WIDE)
+        load_b_unit_wide<C, LG, TL>(g, U, a, b, kb, klim, koff, rev, dst);
+      else
+        load_b_unit<C, LG, TL>(g, set ? v1 : v0, a0, a, b, kb, klim, koff, rev, dst);
+    };
 #pragma unroll
     for (int it = 0; it < BIT; ++it) {
       const int u = tid + it * T::THREADS;
@@ -1592,13 +1704,13 @@ __global__ void __launch_bounds__(T::THREADS)
         const uint32_t a = TL ? c0 + row : a_fix, b = TL ? 0 : c0 + row;
         const int kb = k0 + kq * LG;
         if (SP == kDense) {
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.n, 0, false, rb[0][it]);
+          ldb(0, a, b, kb, g.n, 0, false, rb[0][it]);
         } else if (SP == kSplitFwd) {
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, false, rb[0][it]);
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, K, 0, true, rb[NR - 1][it]);
+          ldb(0, a, b, kb, K, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, K, 0, true, rb[NR - 1][it]);
         } else if (SP == kSplitFwd2) {
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
+          ldb(0, a, b, kb, g.me, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, g.me, 0, true, rb[NR - 1][it]);
         } else if constexpr (UPD) {
           static_assert(!TL, "the update prologue runs on N-loader products");
           const uint32_t bytes = upd_bytes<C>(g);
@@ -1610,8 +1722,8 @@ __global__ void __launch_bounds__(T::THREADS)
           load_b_unit_buf<C, LG>(buf_rsrc(U, bytes), o, rb[NR - 1][it]);
           pre_b_unit<C, LG>(pro, kb, g.mo, g.me, o, bytes, rp[NR - 1][it]);
         } else {
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.me, 0, false, rb[0][it]);
-          load_b_unit<C, LG, TL>(g, U, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
+          ldb(0, a, b, kb, g.me, 0, false, rb[0][it]);
+          ldb(1, a, b, kb, g.mo, g.me, false, rb[NR - 1][it]);
         }
       }
     }
@@ -1767,13 +1879,17 @@ __global__ void __launch_bounds__(T::THREADS)
   gload(0);
   sstore(0, 0);
   __syncthreads();
-  // steady state without conditions, so that each iteration (next tile's loads, this tile's
-  // MFMAs, next tile's prologue and LDS stores) is one block the scheduler can interleave;
-  // the last tile is contracted after the loop
+  // steady state without conditions; the last tile is contracted after the loop.  The
+  // scheduling barriers keep each iteration in three phases: the next tile's global loads are
+  // all issued first, so that their latency is covered by this tile's whole MFMA block (left to
+  // itself the scheduler sinks them towards their use, into the last few MFMAs), and the waits
+  // for them, the prologue and the LDS stores follow the block instead of splitting it.
   for (int kt = 0; kt + 1 < KT; ++kt) {
     const int cur = (T::NBUF == 2) ? (kt & 1) : 0;
     gload(kt + 1);
+    __builtin_amdgcn_sched_barrier(0);
     compute(cur);
+    __builtin_amdgcn_sched_barrier(0);
     if constexpr (T::NBUF == 1) __syncthreads();  // every wave is done reading the one buffer
     sstore(T::NBUF == 2 ? cur ^ 1 : 0, kt + 1);
     __syncthreads();

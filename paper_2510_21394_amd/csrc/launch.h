@@ -116,7 +116,17 @@ struct MPLaunch {
   ProParams pp;
   EpiKind ek = EpiKind::Store;
   EpiParams ep;
+  bool wide = false;  // force the 64-bit-index loader (see mp_wide)
 };
+
+// Whether a mode product takes the WIDE tile configuration of its precision (64-bit element
+// indices): an N-loader product (B > 1; T-loader offsets always fit) that is forced to, or
+// whose k-tile rows, up to 32 of them at element stride B, span more than the 2 GiB the other
+// configurations' buffer views address.
+inline bool mp_wide(const MPLaunch& L) {
+  const uint64_t esize = (L.prec == P_F64) ? 16 : 8;
+  return L.B > 1 && (L.wide || (uint64_t)L.B * 32u * esize > 0x80000000ull);
+}
 
 constexpr int kNumCfg = 5;  // tile configurations per precision and structure
 int cfg_rows(int prec, int cfg, int split = 0);

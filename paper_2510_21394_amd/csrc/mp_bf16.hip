@@ -27,6 +27,13 @@ struct BFK {
 hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
   // Split tiles stay within the 160 KB of LDS with two operand blocks of NP pieces each; the
   // single-buffered configurations (last template argument 1) let two workgroups share a CU.
+  if (mp_wide(L)) {
+    if (L.prec == P_BF16X3)
+      return L.split ? dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2, 1, true>>(L, s)
+                     : dispatch_cfg<BFK<2>, TileCfg<128, 64, 32, 2, 2, 2, true>>(L, s);
+    return L.split ? dispatch_split<BFK<3>, TileCfg<64, 32, 32, 1, 2, 1, true>>(L, s)
+                   : dispatch_cfg<BFK<3>, TileCfg<64, 64, 32, 1, 2, 2, true>>(L, s);
+  }
   if (L.prec == P_BF16X3) {
     if (L.split) {
       switch (L.cfg) {

@@ -21,6 +21,9 @@ struct F32K {
 };
 
 hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {
+  if (mp_wide(L))
+    return L.split ? dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2, 2, true>>(L, s)
+                   : dispatch_cfg<F32K, TileCfg<128, 64, 16, 2, 2, 2, true>>(L, s);
   if (L.split) {
     switch (L.cfg) {
       case 0: return dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);

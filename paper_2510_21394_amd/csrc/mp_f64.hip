@@ -21,6 +21,9 @@ struct F64K {
 };
 
 hipError_t launch_mp_f64(const MPLaunch& L, hipStream_t s) {
+  if (mp_wide(L))
+    return L.split ? dispatch_split<F64K, TileCfg<128, 32, 16, 2, 2, 2, true>>(L, s)
+                   : dispatch_cfg<F64K, TileCfg<128, 32, 8, 2, 2, 2, true>>(L, s);
   if (L.split) {
     switch (L.cfg) {
       case 0: return dispatch_split<F64K, TileCfg<128, 32, 16, 2, 2>>(L, s);

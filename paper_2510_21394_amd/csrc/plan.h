@@ -135,6 +135,7 @@ struct fcgle_plan {
   // exponential-Euler update in the prologue of the first backward product (when supported)
   int fusion = 3;
   bool fwd_rev = false;  // forward operators run their mode products from axis d to axis 1
+  bool wide_force = false;  // every N-loader mode product through 64-bit element indices (mp_wide)
   int* dflag = nullptr;
   // refinement sweep of the inverse (allocated on first use): FP64 Toeplitz D_mu (npad x npad),
   // the FP64 residual, a state-type work tensor, and norm partials + results

@@ -233,6 +233,12 @@ class Plan:
         """True: even/odd half-size mode products (default for fp64/fp32); False: dense."""
         L.check(self.lib.fcgle_set_structure(self.handle, int(bool(split))))
 
+    def set_wide_loads(self, force: bool):
+        """True: every N-loader mode product reads through 64-bit element indices (the
+        configuration the library picks by itself where 32 rows of the tensor span more
+        than 2 GiB); False: that automatic choice."""
+        L.check(self.lib.fcgle_set_wide_loads(self.handle, int(bool(force))))
+
     def describe(self) -> str:
         buf = ctypes.create_string_buffer(1024)
         L.check(self.lib.fcgle_describe(self.handle, buf, 1024))
