@@ -47,6 +47,14 @@ struct BatchInst {
   float2* tmp2 = nullptr;
 };
 
+// Instances can be split per phase into size classes by the half-block length of the axis the
+// phase contracts (m_e <= kClassRows: one 128-row tile covers the block; larger: several), each
+// class with its own tile configuration and grouped launch; the autotuner keeps that split or
+// one class per phase, whichever runs a step faster.  Within a class the instances are ordered
+// by work, largest first, so that their workgroups are dispatched first.
+constexpr int kClasses = 2;
+constexpr int kClassRows = 128;
+
 struct Phase {
   int cfg = 1;
   int sp = 1;  // even/odd form: kSplitFwd or kSplitFwd2 (forward phases), kSplitBwd
@@ -55,6 +63,7 @@ struct Phase {
   EpiKind ek = EpiKind::Store;
   void* items = nullptr;  // device item array
   uint32_t nblocks = 0;
+  std::vector<int> members;  // instances of this size class, largest work first
 };
 
 struct CachedGraph {
@@ -69,8 +78,9 @@ struct BatchData {
   double tau = 0;
   std::vector<BatchInst> inst;
   void* pool = nullptr;
-  Phase ph[PH_COUNT];
+  Phase ph[PH_COUNT][kClasses];
   bool fuse = true;       // F1 with the fused update (else Store + streaming pass)
+  bool classes = false;   // size classes per phase (else one class holding every instance)
   void* pw_items = nullptr;
   uint32_t pw_rows = 0;
   std::vector<const void*> bound;  // state pointers the item arrays were built for
@@ -95,8 +105,9 @@ void batch_free(BatchData* B) {
   for (auto& q : B->p_items)
     if (q) (void)hipFree(q);
   if (B->p_buf) (void)hipFree(B->p_buf);
-  for (auto& p : B->ph)
-    if (p.items) (void)hipFree(p.items);
+  for (auto& pc : B->ph)
+    for (auto& p : pc)
+      if (p.items) (void)hipFree(p.items);
   if (B->pw_items) (void)hipFree(B->pw_items);
   if (B->pool) (void)hipFree(B->pool);
   if (B->cap) (void)hipStreamDestroy(B->cap);
@@ -110,10 +121,9 @@ void clear_graphs(BatchData* B) {
   B->graphs.clear();
 }
 
-MPLaunch inst_launch(const BatchData* B, const BatchInst& I, int phase, const void* u) {
+MPLaunch inst_launch(const BatchData* B, const BatchInst& I, int phase, const Phase& ph, const void* u) {
   MPLaunch L;
   L.prec = P_F32;
-  const Phase& ph = B->ph[phase];
   L.cfg = ph.cfg;
   const bool axis1 = (phase == PH_T1 || phase == PH_F1 || phase == PH_B1);
   const bool fwd = (phase == PH_T0 || phase == PH_T1 || phase == PH_F0 || phase == PH_F1);
@@ -188,26 +198,51 @@ EpiParams update_params(const BatchData* B, const BatchInst& I) {
 
 int build_persist(BatchData* B, const void* const* u);
 
+// Members of every phase's classes: by size class (split) or all in class 0, largest work first
+// (the phase's multiply-adds are proportional to N m_e of its axis).  Invalidates the items.
+void assign_classes(BatchData* B, bool split) {
+  for (int p = 0; p < PH_COUNT; ++p) {
+    const int mu = (p == PH_T1 || p == PH_F1 || p == PH_B1) ? 1 : 0;
+    std::vector<int> order(B->count);
+    for (int i = 0; i < B->count; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+      return B->inst[a].N * B->inst[a].me[mu] > B->inst[b].N * B->inst[b].me[mu];
+    });
+    for (int c = 0; c < kClasses; ++c) {
+      Phase& ph = B->ph[p][c];
+      ph.members.clear();
+      for (int i : order)
+        if ((split && B->inst[i].me[mu] > kClassRows) == (c == 1)) ph.members.push_back(i);
+    }
+  }
+  B->classes = split;
+  B->items_valid = false;
+}
+
 // (Re)build and upload every item array for the state pointers u[0..count).  Synchronises
 // the device first: an item array may still be read by work in flight.
 int build_items(BatchData* B, const void* const* u) {
   HIP_TRY(hipDeviceSynchronize());
-  B->ph[PH_F1].ek = B->fuse ? EpiKind::ExpEuler : EpiKind::Store;
-  std::vector<MPLaunch> L(B->count);
-  for (int p = 0; p < PH_COUNT; ++p) {
-    Phase& ph = B->ph[p];
-    for (int i = 0; i < B->count; ++i) L[i] = inst_launch(B, B->inst[i], p, u[i]);
-    const size_t bytes = group_item_bytes(ph.pk, ph.ek) * (size_t)B->count;
-    if (bytes == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no grouped kernel for phase %d", p);
-    std::vector<unsigned char> host(bytes);
-    ph.nblocks = group_build_f32(ph.cfg, ph.tl, ph.pk, ph.ek, L.data(), B->count, host.data());
-    if (!ph.items) {
-      // largest item type over the epilogue choices of this phase
-      const size_t cap = std::max(group_item_bytes(ph.pk, EpiKind::Store), group_item_bytes(ph.pk, EpiKind::ExpEuler));
-      FC_TRY(plan_alloc(&ph.items, cap * (size_t)B->count));
+  for (auto& ph : B->ph[PH_F1]) ph.ek = B->fuse ? EpiKind::ExpEuler : EpiKind::Store;
+  std::vector<MPLaunch> L;
+  for (int p = 0; p < PH_COUNT; ++p)
+    for (Phase& ph : B->ph[p]) {
+      const int nc = (int)ph.members.size();
+      if (nc == 0) continue;
+      L.resize(nc);
+      for (int k = 0; k < nc; ++k) L[k] = inst_launch(B, B->inst[ph.members[k]], p, ph, u[ph.members[k]]);
+      const size_t bytes = group_item_bytes(ph.pk, ph.ek) * (size_t)nc;
+      if (bytes == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no grouped kernel for phase %d", p);
+      std::vector<unsigned char> host(bytes);
+      ph.nblocks = group_build_f32(ph.cfg, ph.tl, ph.pk, ph.ek, L.data(), nc, host.data());
+      if (!ph.items) {
+        // largest item type over the epilogue choices of this phase
+        const size_t cap =
+            std::max(group_item_bytes(ph.pk, EpiKind::Store), group_item_bytes(ph.pk, EpiKind::ExpEuler));
+        FC_TRY(plan_alloc(&ph.items, cap * (size_t)B->count));  // any class may hold every instance
+      }
+      HIP_TRY(hipMemcpy(ph.items, host.data(), bytes, hipMemcpyHostToDevice));
     }
-    HIP_TRY(hipMemcpy(ph.items, host.data(), bytes, hipMemcpyHostToDevice));
-  }
   {
     std::vector<int64_t> rows(B->count);
     std::vector<int> nl(B->count);
@@ -236,7 +271,7 @@ int build_items(BatchData* B, const void* const* u) {
 // products with both even/odd blocks per tile, the update fused into F1's stores.
 MPLaunch persist_launch(const BatchData* B, const BatchInst& I, int p, const void* u) {
   static const int kPh[4] = {PH_F0, PH_F1, PH_B0, PH_B1};
-  MPLaunch L = inst_launch(B, I, kPh[p], u);
+  MPLaunch L = inst_launch(B, I, kPh[p], B->ph[kPh[p]][0], u);
   if (p < 2) L.split = kSplitFwd2;
   L.cfg = B->pcfg;
   if (p == 0) {
@@ -319,10 +354,17 @@ int run_persist(BatchData* B, int64_t nsteps, hipStream_t st) {
   return FCGLE_OK;
 }
 
-int launch_phase(const BatchData* B, int p, hipStream_t st) {
-  const Phase& ph = B->ph[p];
+int launch_class(const BatchData* B, int p, int c, hipStream_t st) {
+  const Phase& ph = B->ph[p][c];
+  if (ph.members.empty()) return FCGLE_OK;
   const bool fwd = (p == PH_T0 || p == PH_T1 || p == PH_F0 || p == PH_F1);
-  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, fwd ? ph.sp : kSplitBwd, ph.items, B->count, ph.nblocks, st));
+  HIP_TRY(launch_group_f32(ph.cfg, ph.tl, ph.pk, ph.ek, fwd ? ph.sp : kSplitBwd, ph.items, (int)ph.members.size(),
+                           ph.nblocks, st));
+  return FCGLE_OK;
+}
+
+int launch_phase(const BatchData* B, int p, hipStream_t st) {
+  for (int c = 0; c < kClasses; ++c) FC_TRY(launch_class(B, p, c, st));
   return FCGLE_OK;
 }
 
@@ -406,59 +448,103 @@ int autotune_impl(fcgle_plan* P, int reps, hipStream_t st, hipEvent_t e0, hipEve
     HIP_TRY(hipMemsetAsync(B->inst[i].tmp, 0, (size_t)B->inst[i].N * 8, st));
     HIP_TRY(hipMemsetAsync(B->inst[i].uhat, 0, (size_t)B->inst[i].N * 8, st));
   }
-  // per phase: tile configuration, and for forward phases the even/odd form (two row
-  // tiles, or both blocks in one tile)
-  const int order[] = {PH_F0, PH_B0, PH_B1};
-  for (int p : order) {
+  // per phase and size class: tile configuration, and for forward phases the even/odd form
+  // (two row tiles, or both blocks in one tile)
+  auto tune_class = [&](int p, int c, bool forms, float* best_ms) -> int {
+    Phase& ph = B->ph[p][c];
     float best = 1e30f;
-    int best_c = B->ph[p].cfg, best_sp = B->ph[p].sp;
-    const int nsp = (p == PH_F0) ? 2 : 1;
-    for (int f2 = 0; f2 < nsp; ++f2)
-      for (int c = 0; c < kGroupCfg; ++c) {
-        B->ph[p].cfg = c;
-        if (p == PH_F0) B->ph[p].sp = f2 ? kSplitFwd2 : kSplitFwd;
+    int best_c = ph.cfg, best_sp = ph.sp;
+    for (int f2 = 0; f2 < (forms ? 2 : 1); ++f2)
+      for (int k = 0; k < kGroupCfg; ++k) {
+        ph.cfg = k;
+        if (forms) ph.sp = f2 ? kSplitFwd2 : kSplitFwd;
         FC_TRY(build_items(B, scratch.data()));
         float ms;
-        FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_phase(B, p, st); }, &ms));
+        FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_class(B, p, c, st); }, &ms));
         if (ms < best) {
           best = ms;
-          best_c = c;
-          best_sp = B->ph[p].sp;
+          best_c = k;
+          best_sp = ph.sp;
         }
       }
-    B->ph[p].cfg = best_c;
-    B->ph[p].sp = best_sp;
-  }
-  // F1: fused update (each tile configuration and form) against Store + streaming pass
-  float best = 1e30f;
-  int best_c = 1, best_sp = kSplitFwd;
-  bool best_fuse = true;
-  for (int f = 0; f < 2; ++f)
-    for (int f2 = 0; f2 < 2; ++f2)
-    for (int c = 0; c < kGroupCfg; ++c) {
+    ph.cfg = best_c;
+    ph.sp = best_sp;
+    *best_ms = best;
+    return FCGLE_OK;
+  };
+  struct Choice {
+    int cfg[PH_COUNT][kClasses], sp[PH_COUNT][kClasses];
+    bool fuse;
+    float step_ms;
+  } choice[2];
+  for (int mode = 0; mode < 2; ++mode) {
+    assign_classes(B, mode == 1);
+    for (auto& pc : B->ph)
+      for (auto& ph : pc) {
+        ph.cfg = 1;
+        ph.sp = kSplitFwd;
+      }
+    const int order[] = {PH_F0, PH_B0, PH_B1};
+    for (int p : order)
+      for (int c = 0; c < kClasses; ++c) {
+        if (B->ph[p][c].members.empty()) continue;
+        float ms;
+        FC_TRY(tune_class(p, c, p == PH_F0, &ms));
+      }
+    // F1: fused update (each class at its best tile and form) against Store + streaming pass
+    int keep_cfg[2][kClasses], keep_sp[2][kClasses];
+    float total[2] = {0.f, 0.f};
+    for (int f = 0; f < 2; ++f) {
       B->fuse = (f == 0);
-      B->ph[PH_F1].cfg = c;
-      B->ph[PH_F1].sp = f2 ? kSplitFwd2 : kSplitFwd;
-      FC_TRY(build_items(B, scratch.data()));
-      float ms;
-      FC_TRY(time_phase(st, e0, e1, reps, [&]() -> int {
-        FC_TRY(launch_phase(B, PH_F1, st));
-        if (!B->fuse) HIP_TRY(launch_pw_group_f32(EpiKind::ExpEuler, B->pw_items, B->count, B->pw_rows, st));
-        return (int)FCGLE_OK;
-      }, &ms));
-      if (ms < best) {
-        best = ms;
-        best_c = c;
-        best_sp = B->ph[PH_F1].sp;
-        best_fuse = B->fuse;
+      for (int c = 0; c < kClasses; ++c) {
+        keep_cfg[f][c] = B->ph[PH_F1][c].cfg;
+        keep_sp[f][c] = B->ph[PH_F1][c].sp;
+        if (B->ph[PH_F1][c].members.empty()) continue;
+        float ms;
+        FC_TRY(tune_class(PH_F1, c, true, &ms));
+        keep_cfg[f][c] = B->ph[PH_F1][c].cfg;
+        keep_sp[f][c] = B->ph[PH_F1][c].sp;
+        total[f] += ms;
+      }
+      if (!B->fuse) {
+        FC_TRY(build_items(B, scratch.data()));
+        float ms;
+        FC_TRY(time_phase(st, e0, e1, reps, [&]() -> int {
+          HIP_TRY(launch_pw_group_f32(EpiKind::ExpEuler, B->pw_items, B->count, B->pw_rows, st));
+          return (int)FCGLE_OK;
+        }, &ms));
+        total[f] += ms;
       }
     }
-  B->fuse = best_fuse;
-  B->ph[PH_F1].cfg = best_c;
-  B->ph[PH_F1].sp = best_sp;
-  B->ph[PH_T0].cfg = B->ph[PH_F0].cfg;
-  B->ph[PH_T0].sp = B->ph[PH_F0].sp;
-  B->ph[PH_T1].cfg = B->ph[PH_B1].cfg;
+    const int bf = total[0] <= total[1] ? 0 : 1;
+    B->fuse = (bf == 0);
+    for (int c = 0; c < kClasses; ++c) {
+      B->ph[PH_F1][c].cfg = keep_cfg[bf][c];
+      B->ph[PH_F1][c].sp = keep_sp[bf][c];
+      B->ph[PH_T0][c].cfg = B->ph[PH_F0][c].cfg;
+      B->ph[PH_T0][c].sp = B->ph[PH_F0][c].sp;
+      B->ph[PH_T1][c].cfg = B->ph[PH_B1][c].cfg;
+    }
+    FC_TRY(build_items(B, scratch.data()));
+    float ms;
+    FC_TRY(time_phase(st, e0, e1, reps, [&] { return launch_step(B, st); }, &ms));
+    Choice& ch = choice[mode];
+    for (int p = 0; p < PH_COUNT; ++p)
+      for (int c = 0; c < kClasses; ++c) {
+        ch.cfg[p][c] = B->ph[p][c].cfg;
+        ch.sp[p][c] = B->ph[p][c].sp;
+      }
+    ch.fuse = B->fuse;
+    ch.step_ms = ms;
+  }
+  const int best_mode = choice[1].step_ms < choice[0].step_ms ? 1 : 0;
+  assign_classes(B, best_mode == 1);
+  for (int p = 0; p < PH_COUNT; ++p)
+    for (int c = 0; c < kClasses; ++c) {
+      B->ph[p][c].cfg = choice[best_mode].cfg[p][c];
+      B->ph[p][c].sp = choice[best_mode].sp[p][c];
+    }
+  B->fuse = choice[best_mode].fuse;
   B->items_valid = false;
   clear_graphs(B);
   return FCGLE_OK;
@@ -491,9 +577,25 @@ int batch_describe(const fcgle_plan* P, char* buf, size_t len) {
   static const char* names[] = {"t0", "t1", "f0", "f1", "b0", "b1"};
   std::string s = "batch count=" + std::to_string(B->count) + " n in [" + std::to_string(nmin) + "," +
                   std::to_string(nmax) + "] precision=fp32 structure=even-odd tiles(rows)=";
-  for (int p = 0; p < PH_COUNT; ++p)
-    s += std::string(names[p]) + ":" + std::to_string(group_cfg_rows(B->ph[p].cfg)) +
-         (B->ph[p].sp == kSplitFwd2 ? "F" : "") + (p + 1 < PH_COUNT ? "," : "");
+  for (int p = 0; p < PH_COUNT; ++p) {
+    s += std::string(names[p]) + ":";
+    bool first = true;
+    for (int c = 0; c < kClasses; ++c) {
+      const Phase& ph = B->ph[p][c];
+      if (ph.members.empty()) continue;
+      s += std::string(first ? "" : "|") + std::to_string(group_cfg_rows(ph.cfg)) + (ph.sp == kSplitFwd2 ? "F" : "");
+      first = false;
+    }
+    s += (p + 1 < PH_COUNT ? "," : "");
+  }
+  if (B->classes) {
+    int nl = 0;
+    for (const auto& I : B->inst) nl += I.me[0] > kClassRows;
+    s += " classes(m_e<=" + std::to_string(kClassRows) + "|larger, axis 0)=" + std::to_string(B->count - nl) + "|" +
+         std::to_string(nl);
+  } else {
+    s += " classes=one";
+  }
   s += std::string(" update=") + (B->fuse ? "fused" : "streaming");
   if (B->persist) s += " form=persistent(" + std::to_string(group_cfg_rows(B->pcfg)) + "-row tiles)";
   else s += " form=graph-of-grouped-launches";
@@ -658,14 +760,16 @@ int fcgle_batch_setup(int count, const int64_t* n, const double* alpha, const do
   if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "batch setup: %s", hipGetErrorString(e)));
   e = hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking);
   if (e != hipSuccess) return cleanup(fail(FCGLE_ERR_HIP, "hipStreamCreate: %s", hipGetErrorString(e)));
-  // phase kinds and default tiles (128-row tiles suit the 96..512 sizes)
-  for (int p = 0; p < PH_COUNT; ++p) {
-    Phase& ph = B->ph[p];
-    ph.cfg = 1;
-    ph.tl = (p == PH_T1 || p == PH_F1 || p == PH_B1);
-    ph.pk = (p == PH_F0) ? ProKind::Nonlin : ProKind::Id;
-    ph.ek = (p == PH_F1) ? EpiKind::ExpEuler : EpiKind::Store;
-  }
+  // phase kinds, default tiles (128-row tiles suit the 96..512 sizes), one class per phase
+  for (int p = 0; p < PH_COUNT; ++p)
+    for (int c = 0; c < kClasses; ++c) {
+      Phase& ph = B->ph[p][c];
+      ph.cfg = 1;
+      ph.tl = (p == PH_T1 || p == PH_F1 || p == PH_B1);
+      ph.pk = (p == PH_F0) ? ProKind::Nonlin : ProKind::Id;
+      ph.ek = (p == PH_F1) ? EpiKind::ExpEuler : EpiKind::Store;
+    }
+  assign_classes(B, false);
   B->fuse = true;
   *out = P;
   return FCGLE_OK;

@@ -11,14 +11,14 @@ namespace fcgle {
 // their tiles are smaller.
 constexpr int kCfgRows[2][4][kNumCfg] = {
     {{256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}, {256, 128, 64, 128, 256}, {128, 64, 64, 64, 128}},
-    {{128, 64, 128, 128, 128}, {128, 128, 128, 128, 128}, {64, 128, 64, 128, 64}, {64, 64, 128, 64, 128}}};
+    {{128, 64, 128, 128, 128}, {128, 128, 128, 128, 128}, {64, 128, 128, 128, 64}, {64, 64, 128, 64, 128}}};
 constexpr int kCfgCols[2][4][kNumCfg] = {
     {{32, 32, 32, 32, 32}, {64, 64, 64, 64, 64}, {64, 64, 64, 64, 64}, {64, 64, 32, 64, 64}},
-    {{32, 32, 64, 32, 64}, {64, 64, 128, 64, 128}, {32, 32, 32, 32, 64}, {32, 16, 16, 32, 16}}};
+    {{32, 32, 64, 32, 64}, {64, 64, 128, 64, 128}, {32, 32, 64, 32, 64}, {32, 16, 16, 32, 16}}};
 // LDS buffers of the operand tiles (1: single-buffered configurations).
 constexpr int kCfgBufs[2][4][kNumCfg] = {
     {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}},
-    {{2, 1, 2, 2, 2}, {2, 2, 2, 2, 2}, {1, 2, 2, 1, 1}, {2, 1, 2, 1, 1}}};
+    {{2, 1, 2, 2, 2}, {2, 1, 2, 2, 2}, {1, 2, 1, 1, 1}, {2, 1, 2, 1, 1}}};
 
 // Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
 // combinations a structure never needs are not instantiated.

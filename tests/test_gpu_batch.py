@@ -54,7 +54,13 @@ def test_small_batch_matches_oracle(F, tune):
     plan = F.BatchPlan([i[:4] for i in insts], tau=tau)
     if tune:
         plan.autotune(2)
-    print(plan.describe())
+    desc = plan.describe()
+    print(desc)
+    # one class per phase (the default), or size classes of the axis-0 half-block length
+    # m_e = ceil(n_0 / 2) <= 128 and larger when the autotuner times them faster
+    nsmall = sum(1 for i in insts if (i[0][0] + 1) // 2 <= 128)
+    split = f"classes(m_e<=128|larger, axis 0)={nsmall}|{len(insts) - nsmall}"
+    assert ("classes=one" in desc) or (tune and split in desc)
     us = [_dev(i[4]) for i in insts]
     plan.run(us, 0.0, steps)
     for (n, alpha, h, params, u0), u in zip(insts, us):
