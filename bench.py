@@ -184,6 +184,15 @@ def time_precision(prec, w, U0, steps, warmup, autotune, golden, tile_sweep=Fals
         plan.autotune(3)
     u0 = torch.from_numpy(U0).to(dt).cuda()
     u = u0.clone()
+    # one-time set-up outside the timed region: the library replays runs from HIP graphs captured
+    # on first use of each block length and eigenspace-buffer assignment; the warmup and the timed
+    # run are made twice here (the single direct step swaps the two eigenspace buffers, so both
+    # assignments occur) and the state reset, so that no capture falls in the timed region
+    for _ in range(2):
+        plan.run("exp_euler", u, 0.0, warmup)
+        plan.run("exp_euler", u, warmup * w.tau, steps)
+        u.copy_(u0)
+    torch.cuda.synchronize()
     plan.run("exp_euler", u, 0.0, warmup)          # includes the one-time forward transform
     torch.cuda.synchronize()
     t0 = time.perf_counter()

@@ -192,10 +192,13 @@ int fcgle_step(fcgle_plan* plan, int scheme, void* u_dev, double t, double tau, 
  * trailing flow over tau/2 of each step and the leading one of the next run as one flow over
  * tau (the flow of an autonomous equation composes exactly), so intermediate states are not
  * formed; the result equals nsteps single steps up to rounding.  For FCGLE_EXP_EULER without
- * a source term and with timing off, runs longer than 50 steps replay the steady-state steps in
- * blocks of 50 from a HIP graph captured on first use (per state buffer and plan configuration;
- * fcgle_set_tiles / _fusion / _structure / _source and fcgle_autotune invalidate it): the
- * same kernels with the same arguments, so the result is identical to nsteps single steps. */
+ * a source term and with timing off, runs of two or more steps replay them in blocks of 64,
+ * 16, 4 and 2 steps from HIP graphs captured on first use of each block length (per state
+ * buffer, eigenspace buffer assignment and plan configuration; fcgle_set_tiles / _fusion /
+ * _structure / _source / _wide_loads and fcgle_autotune invalidate them; up to 8 are kept).
+ * The first step runs directly unless the state of u_dev is cached and a step already ran
+ * under the current configuration, and an odd remainder runs directly: the same kernels with
+ * the same arguments, so the result is identical to nsteps single steps. */
 int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, int64_t nsteps,
               void* stream);
 

@@ -951,12 +951,14 @@ int refine_residual(fcgle_plan* P, double theta, const void* v, const void* x, h
 // capture of an even number of steps starts and ends in the same buffer assignment and can be
 // replayed back to back.  Graphs are keyed by the state buffer, the eigenspace buffers and the
 // configuration generation; no memset is captured.
-constexpr int64_t kGraphSteps = 50;
-constexpr size_t kMaxRunGraphs = 4;
+// Steps per captured graph: a run is cut greedily into these (even) chunk lengths, so that runs
+// of any length replay graphs, with at most one step left to run directly.
+constexpr int64_t kGraphChunks[] = {64, 16, 4, 2};
+constexpr size_t kMaxRunGraphs = 8;
 
-int run_graph(fcgle_plan* P, void* u, hipStream_t st, hipGraphExec_t* out) {
+int run_graph(fcgle_plan* P, void* u, int64_t steps, hipGraphExec_t* out) {
   for (auto& g : P->run_graphs)
-    if (g.u == u && g.uhat == P->uhat && g.uhat2 == P->uhat2 && g.steps == kGraphSteps && g.gen == P->gen) {
+    if (g.u == u && g.uhat == P->uhat && g.uhat2 == P->uhat2 && g.steps == steps && g.gen == P->gen) {
       *out = g.exec;
       return FCGLE_OK;
     }
@@ -965,7 +967,7 @@ int run_graph(fcgle_plan* P, void* u, hipStream_t st, hipGraphExec_t* out) {
   void* const uh2 = P->uhat2;
   HIP_TRY(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
   int rc = FCGLE_OK;
-  for (int64_t k = 0; k < kGraphSteps && rc == FCGLE_OK; ++k) rc = step_impl(P, FCGLE_EXP_EULER, u, 0.0, P->cap_stream);
+  for (int64_t k = 0; k < steps && rc == FCGLE_OK; ++k) rc = step_impl(P, FCGLE_EXP_EULER, u, 0.0, P->cap_stream);
   hipGraph_t graph = nullptr;
   const hipError_t e = hipStreamEndCapture(P->cap_stream, &graph);
   P->uhat = uh;  // nothing ran: the buffers keep their roles (an even count swaps them back anyway)
@@ -983,30 +985,36 @@ int run_graph(fcgle_plan* P, void* u, hipStream_t st, hipGraphExec_t* out) {
     (void)hipGraphExecDestroy(P->run_graphs.front().exec);
     P->run_graphs.erase(P->run_graphs.begin());
   }
-  P->run_graphs.push_back(RunGraph{u, uh, uh2, kGraphSteps, P->gen, exec});
+  P->run_graphs.push_back(RunGraph{u, uh, uh2, steps, P->gen, exec});
   *out = exec;
-  (void)st;
   return FCGLE_OK;
 }
 
 // nsteps exponential-Euler steps from t0 with the steady-state ones replayed from graphs (no
-// source term, timing off).  The first step runs directly: it forms the eigenspace state if
-// needed and builds the grids, tables and buffers that the captured steps then only read.
+// source term, timing off).  The first step runs directly unless the state of u is cached and a
+// step already ran directly under the plan's current configuration: that step forms the
+// eigenspace state if needed and builds the grids, tables and buffers that the captured steps
+// then only read.  An odd remainder is run directly at the end.
 int expeuler_run(fcgle_plan* P, void* u, double t0, int64_t nsteps, hipStream_t st) {
   int64_t k = 0;
-  if (nsteps > 0) {
+  const bool ready = P->uhat_valid && P->uhat_src == u && P->ready_gen == P->gen;
+  if (nsteps > 0 && !ready) {
     FC_TRY(step_impl(P, FCGLE_EXP_EULER, u, t0, st));
+    P->ready_gen = P->gen;
     k = 1;
   }
-  static_assert(kGraphSteps % 2 == 0, "a replayed run must keep the eigenspace buffer assignment");
-  while (nsteps - k >= kGraphSteps) {
-    hipGraphExec_t exec;
-    FC_TRY(run_graph(P, u, st, &exec));
-    HIP_TRY(hipGraphLaunch(exec, st));
-    P->uhat_valid = true;
-    P->uhat_src = u;
-    P->hist_valid = false;
-    k += kGraphSteps;
+  for (const int64_t chunk : kGraphChunks) {
+    static_assert(kGraphChunks[0] % 2 == 0 && kGraphChunks[3] % 2 == 0,
+                  "a replayed run must keep the eigenspace buffer assignment");
+    while (nsteps - k >= chunk) {
+      hipGraphExec_t exec;
+      FC_TRY(run_graph(P, u, chunk, &exec));
+      HIP_TRY(hipGraphLaunch(exec, st));
+      P->uhat_valid = true;
+      P->uhat_src = u;
+      P->hist_valid = false;
+      k += chunk;
+    }
   }
   for (; k < nsteps; ++k) FC_TRY(step_impl(P, FCGLE_EXP_EULER, u, t0 + (double)k * P->tau, st));
   return FCGLE_OK;
@@ -1332,7 +1340,7 @@ int fcgle_run(fcgle_plan* plan, int scheme, void* u_dev, double t0, double tau, 
     DeviceGuard g(plan->device);
     return strang_run(plan, u_dev, nsteps, as_stream(stream));
   }
-  if (scheme == FCGLE_EXP_EULER && plan->ns == 0 && plan->timing_cap == 0 && nsteps > kGraphSteps) {
+  if (scheme == FCGLE_EXP_EULER && plan->ns == 0 && plan->timing_cap == 0 && nsteps >= 2) {
     if (!u_dev) return fail(FCGLE_ERR_ARG, "u_dev is NULL");
     if (tau != plan->tau) return fail(FCGLE_ERR_ARG, "tau %.17g differs from the plan's %.17g", tau, plan->tau);
     if (!std::isfinite(t0)) return fail(FCGLE_ERR_ARG, "t0 not finite");

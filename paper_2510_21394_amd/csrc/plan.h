@@ -154,6 +154,7 @@ struct fcgle_plan {
   std::vector<fcgle::RunGraph> run_graphs;
   hipStream_t cap_stream = nullptr;
   uint64_t gen = 0;
+  uint64_t ready_gen = ~0ull;  // gen of the last directly run exponential-Euler step (its lazy set-up done)
   // timing
   int timing_cap = 0;
   std::vector<hipEvent_t> ev_pool;

@@ -159,6 +159,20 @@ def test_graph_replayed_run_equals_single_steps(F, prec, update_in_backward):
         plan.step("exp_euler", v, k * 1e-3)
     torch.cuda.synchronize()
     assert torch.equal(u, v)
+    # runs of other lengths in a row: the later ones start from the cached state with graphs of
+    # 16, 4 and 2 steps and end with a direct step when the count is odd
+    for lengths in ((5, 20, 3), (2, 1, 17)):
+        a = torch.from_numpy(U0).to(dt).cuda()
+        b = torch.from_numpy(U0).to(dt).cuda()
+        t = 0
+        for m in lengths:
+            plan.run("exp_euler", a, t * 1e-3, m)
+            t += m
+        plan.set_state(b)
+        for k in range(t):
+            plan.step("exp_euler", b, k * 1e-3)
+        torch.cuda.synchronize()
+        assert torch.equal(a, b), lengths
     # the graph of the first buffer is replayed again, then the configuration changes
     w = torch.from_numpy(U0).to(dt).cuda()
     plan.set_state(u)
