@@ -322,17 +322,18 @@ MPLaunch base_launch(const fcgle_plan* P, int mu, bool fwd) {
 
 // Whether the backward even/odd tile configuration cfg leaves LDS for the staged rows of the
 // on-the-fly update (the same budget the kernels are instantiated under: operand tiles with
-// k-tiles of 16, padded by one MFMA operand group, plus kOtfMaxRows rows of 4 values of the
-// arithmetic precision: 32 bytes for FP64, 16 bytes for FP32).
+// the configuration's k-tile, padded by one MFMA operand group, plus kOtfMaxRows rows of 4
+// values of the arithmetic precision: 32 bytes for FP64, 16 bytes for FP32).
 bool otf_fits(int pr, int cfg) {
   const size_t tm = (size_t)cfg_rows(pr, cfg, 1), tnc = (size_t)cfg_cols(pr, cfg, 1);
   const size_t nbuf = (size_t)cfg_bufs(pr, cfg, 1);
   size_t ops;
+  const size_t tk = (size_t)cfg_tk_split(pr, cfg);
   if (pr == P_F64 || pr == P_F32) {
-    const size_t r = (pr == P_F64) ? 8 : 4, ldk = 16 + (pr == P_F64 ? 2 : 4);
+    const size_t r = (pr == P_F64) ? 8 : 4, ldk = tk + (pr == P_F64 ? 2 : 4);
     ops = nbuf * 2 * tm * ldk * r + nbuf * 2 * 2 * tnc * ldk * r;
-  } else {  // split BF16: NP pieces of 2 bytes, k-tiles of 32 padded by 8
-    const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = 40;
+  } else {  // split BF16: NP pieces of 2 bytes, k-tiles padded by 8
+    const size_t np = (pr == P_BF16X3) ? 2 : 3, ldk = tk + 8;
     ops = nbuf * 2 * np * tm * ldk * 2 + nbuf * 2 * np * 2 * tnc * ldk * 2;
   }
   return ops + (size_t)kOtfMaxRows * (pr == P_F64 ? 32 : 16) <= 163840;

@@ -39,7 +39,7 @@ hipError_t launch_mp_bf16(const MPLaunch& L, hipStream_t s) {
       switch (L.cfg) {
         case 0: return dispatch_split<BFK<2>, TileCfg<64, 32, 32, 1, 2, 1>>(L, s);
         case 1: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2>>(L, s);
-        case 2: return dispatch_split<BFK<2>, TileCfg<128, 64, 32, 2, 2, 1>>(L, s);
+        case 2: return dispatch_split<BFK<2>, TileCfg<128, 32, 64, 2, 2, 1>>(L, s);
         case 3: return dispatch_split<BFK<2>, TileCfg<128, 32, 32, 2, 2, 1>>(L, s);
         case 4: return dispatch_split<BFK<2>, TileCfg<64, 64, 32, 1, 2, 1>>(L, s);
         default: return hipErrorInvalidValue;

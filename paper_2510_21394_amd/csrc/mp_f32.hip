@@ -27,7 +27,7 @@ hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {
   if (L.split) {
     switch (L.cfg) {
       case 0: return dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);
-      case 1: return dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2, 1>>(L, s);
+      case 1: return dispatch_split<F32K, TileCfg<128, 128, 32, 2, 4, 1>>(L, s);
       case 2: return dispatch_split<F32K, TileCfg<128, 128, 16, 4, 4>>(L, s);
       case 3: return dispatch_split<F32K, TileCfg<128, 64, 16, 4, 2>>(L, s);
       case 4: return dispatch_split<F32K, TileCfg<128, 128, 16, 2, 4>>(L, s);
