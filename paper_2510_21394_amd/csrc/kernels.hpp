@@ -1930,6 +1930,129 @@ __global__ void __launch_bounds__(T::THREADS)
 }
 
 // ---------------------------------------------------------------------------------------
+// Q-stationary even/odd FP32 mode product (N loader, no prologue, plain store).  The two
+// half-size blocks of the operator stay in LDS for the workgroup's lifetime (rows and k below
+// KP = 16 MT, k contiguous, rows padded to LDQ floats), and each of the 8 waves streams column
+// tiles of 16 tensor columns on its own: its B fragments go from global memory straight into
+// registers one 16-deep k-chunk ahead of the MFMAs that use them, so after the set-up there is
+// no barrier and no LDS store.  SP = kSplitFwd2: the forward fold (x[k] + x[n-1-k] for the even
+// block, x[k] - x[n-1-k] for the odd one, k < m_e), outputs to rows i and m_e + i;
+// SP = kSplitBwd: inputs rows k and m_e + k, outputs p + q to rows i and p - q to rows n-1-i.
+// The MFMA sequence per output element is that of mp_mfma_tile (k in steps of 4 per lane group,
+// 16 per chunk, chunks in order), so results are the same.  Wave w of workgroup b takes column
+// tiles t = 8 b + w, 8 (b + grid) + w, ...; the host keeps n B sizeof(float2) below 2^31.
+constexpr int kQresWaves = 8;
+
+template <int MT>
+constexpr size_t qres_lds_bytes() {
+  return (size_t)2 * (16 * MT) * (16 * MT + 4) * sizeof(float);
+}
+
+template <int SP, int MT>
+__global__ void __launch_bounds__(64 * kQresWaves)
+    mp_qres_kernel(Geo g, const float* __restrict__ M, const float2* __restrict__ U, float2* __restrict__ out) {
+  static_assert(SP == kSplitFwd2 || SP == kSplitBwd, "even/odd forms with both blocks");
+  constexpr int KP = 16 * MT, LDQ = KP + 4;
+  static_assert(qres_lds_bytes<MT>() <= kLdsBytes, "both blocks in LDS");
+  __shared__ __attribute__((aligned(16))) float qs[2 * KP * LDQ];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < 2 * KP * (KP / 4); q += 64 * kQresWaves) {
+    const int h = q / (KP * (KP / 4)), rem = q % (KP * (KP / 4));
+    const int row = rem / (KP / 4), k4 = rem % (KP / 4);
+    *(float4*)&qs[(h * KP + row) * LDQ + 4 * k4] =
+        *(const float4*)&M[(int64_t)h * g.npad * g.npad + (int64_t)row * g.npad + 4 * k4];
+  }
+  __syncthreads();
+  const int lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t tilesB = (g.B + 15) / 16, ntiles = g.A * tilesB;
+  const uint32_t nB = (uint32_t)g.n * g.B;
+  for (uint32_t t = blockIdx.x * kQresWaves + wave; t < ntiles; t += gridDim.x * kQresWaves) {
+    const uint32_t a = t / tilesB, b = (t % tilesB) * 16 + lr;
+    const bool colok = b < g.B;
+    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(U + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
+    const __amdgpu_buffer_rsrc_t rout = buf_rsrc(out + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
+    // a masked element gets the top bit set (an offset of at least 2^31 = kOob, which the
+    // bounds check reads as zero and drops on store): no select the compiler could turn into
+    // a branch around the load
+    auto off = [&](int row, bool ok) -> uint32_t {
+      return (((uint32_t)row * g.B + b) * (uint32_t)sizeof(float2)) | ((uint32_t)(!ok) << 31);
+    };
+    // the two input values of rows k = 16 kc + 4 lg + s, s < 4
+    auto load = [&](int kc, float2 (&l0)[4], float2 (&l1)[4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int k = 16 * kc + 4 * lg + s;
+        if constexpr (SP == kSplitFwd2) {
+          l0[s] = buf_load<float2>(rin, off(k, colok && k < g.me));
+          l1[s] = buf_load<float2>(rin, off(g.n - 1 - k, colok && k < g.me));
+        } else {
+          l0[s] = buf_load<float2>(rin, off(k, colok && k < g.me));
+          l1[s] = buf_load<float2>(rin, off(g.me + k, colok && k < g.mo));
+        }
+      }
+    };
+    v4f acc[2][MT][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[h][mt][0] = acc[h][mt][1] = v4f{0.f, 0.f, 0.f, 0.f};
+    float2 x0[4], x1[4];
+    load(0, x0, x1);
+    // one chunk per iteration, not unrolled: the chunk's B values are formed from the loads in
+    // flight, then the next chunk's loads are issued into the same registers (the scheduling
+    // barrier keeps them ahead of the MFMAs), and the MFMAs run row tile by row tile with both
+    // blocks' A fragments of that tile from LDS (four independent accumulators per k step)
+#pragma unroll 1
+    for (int kc = 0; kc < MT; ++kc) {
+      float2 bv[2][4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        if constexpr (SP == kSplitFwd2) {
+          bv[0][s] = float2{x0[s].x + x1[s].x, x0[s].y + x1[s].y};
+          bv[1][s] = float2{x0[s].x - x1[s].x, x0[s].y - x1[s].y};
+        } else {
+          bv[0][s] = x0[s];
+          bv[1][s] = x1[s];
+        }
+      }
+      load(kc + 1 < MT ? kc + 1 : kc, x0, x1);
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        float4 af[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) af[h] = *(const float4*)&qs[(h * KP + mt * 16 + lr) * LDQ + 16 * kc + 4 * lg];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const float av = s == 0 ? af[h].x : s == 1 ? af[h].y : s == 2 ? af[h].z : af[h].w;
+            acc[h][mt][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[h][s].x, acc[h][mt][0], 0, 0, 0);
+            acc[h][mt][1] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, bv[h][s].y, acc[h][mt][1], 0, 0, 0);
+          }
+      }
+    }
+    // accumulator slot r of lane l holds row 4 (l / 16) + r of its 16-row tile, column l % 16
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = mt * 16 + 4 * lg + r;
+        if constexpr (SP == kSplitFwd2) {
+          buf_store(rout, off(i, colok && i < g.me), float2{acc[0][mt][0][r], acc[0][mt][1][r]});
+          buf_store(rout, off(g.me + i, colok && i < g.mo), float2{acc[1][mt][0][r], acc[1][mt][1][r]});
+        } else {
+          buf_store(rout, off(i, colok && i < g.me),
+                    float2{acc[0][mt][0][r] + acc[1][mt][0][r], acc[0][mt][1][r] + acc[1][mt][1][r]});
+          buf_store(rout, off(g.n - 1 - i, colok && i < g.mo),
+                    float2{acc[0][mt][0][r] - acc[1][mt][0][r], acc[0][mt][1][r] - acc[1][mt][1][r]});
+        }
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // Host-side helpers shared by the per-precision dispatch units
 // ---------------------------------------------------------------------------------------
 

@@ -20,14 +20,63 @@ struct F32K {
   }
 };
 
+// The Q-stationary even/odd products (mp_qres_kernel): both blocks of up to 128 rows in LDS,
+// N loader, no prologue, plain store, offsets of one batch index below 2 GiB; hipErrorNotSupported
+// for every other case.
+template <int SP, int MT>
+static hipError_t go_qres(const MPLaunch& L, hipStream_t s) {
+  Geo g{};
+  g.A = (uint32_t)L.A;
+  g.B = (uint32_t)L.B;
+  g.n = L.n;
+  g.npad = L.npad;
+  g.me = L.me;
+  g.mo = L.mo;
+  const uint64_t tiles = (uint64_t)L.A * (uint64_t)((L.B + 15) / 16);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return hipErrorNotSupported;
+  const uint64_t want = (tiles + kQresWaves - 1) / kQresWaves;
+  const uint32_t grid = (uint32_t)(want < (uint64_t)cus ? want : (uint64_t)cus);
+  hipLaunchKernelGGL((mp_qres_kernel<SP, MT>), dim3(grid), dim3(64 * kQresWaves), 0, s, g, (const float*)L.M,
+                     (const float2*)L.in, (float2*)L.ep.out);
+  return hipGetLastError();
+}
+
+template <int SP>
+static hipError_t go_qres_rows(const MPLaunch& L, hipStream_t s) {
+  switch ((L.me + 15) / 16) {
+    case 4: return go_qres<SP, 4>(L, s);
+    case 5: return go_qres<SP, 5>(L, s);
+    case 6: return go_qres<SP, 6>(L, s);
+    case 7: return go_qres<SP, 7>(L, s);
+    case 8: return go_qres<SP, 8>(L, s);
+    default: return hipErrorNotSupported;
+  }
+}
+
+static hipError_t launch_qres_f32(const MPLaunch& L, hipStream_t s) {
+  if (L.B <= 1 || L.pk != ProKind::Id || L.ek != EpiKind::Store || L.wide) return hipErrorNotSupported;
+  if ((uint64_t)L.n * (uint64_t)L.B * sizeof(float2) >= 0x80000000ull) return hipErrorNotSupported;
+  if (L.split == kSplitFwd2) return go_qres_rows<kSplitFwd2>(L, s);
+  if (L.split == kSplitBwd) return go_qres_rows<kSplitBwd>(L, s);
+  return hipErrorNotSupported;
+}
+
 hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {
+  // split configuration 1: the Q-stationary kernel where it applies, else the 128 x 128 tile
+  if (L.split && L.cfg == 1 && !mp_wide(L)) {
+    const hipError_t e = launch_qres_f32(L, s);
+    if (e != hipErrorNotSupported) return e;
+    return dispatch_split<F32K, TileCfg<128, 128, 16, 2, 4>>(L, s);
+  }
   if (mp_wide(L))
     return L.split ? dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2, 2, true>>(L, s)
                    : dispatch_cfg<F32K, TileCfg<128, 64, 16, 2, 2, 2, true>>(L, s);
   if (L.split) {
     switch (L.cfg) {
       case 0: return dispatch_split<F32K, TileCfg<128, 64, 16, 2, 2>>(L, s);
-      case 1: return dispatch_split<F32K, TileCfg<128, 128, 32, 2, 4, 1>>(L, s);
+      case 1: return dispatch_split<F32K, TileCfg<128, 128, 16, 2, 4>>(L, s);  // handled above
       case 2: return dispatch_split<F32K, TileCfg<128, 128, 16, 4, 4>>(L, s);
       case 3: return dispatch_split<F32K, TileCfg<128, 64, 16, 4, 2>>(L, s);
       case 4: return dispatch_split<F32K, TileCfg<128, 128, 16, 2, 4>>(L, s);

@@ -491,3 +491,29 @@ def test_dispersive_exponential_conserves_norm(F, prec, tol):
         assert drift <= tol
         assert O.rel_l2(out, ref) <= TOL_OP[prec]
         plan.close()
+
+
+@pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33)], ids=lambda s: "x".join(map(str, s)))
+def test_q_stationary_products_equal_tiled(F, n):
+    """FP32 even/odd tile configuration 1 runs the Q-stationary kernel (both half-size blocks
+    held in LDS, each wave streaming its own column tiles) for the plain backward products and
+    the forward products with both blocks per tile along every axis but the last (half-blocks of
+    49..128 rows); it issues the same MFMA sequence per output element as the 128x128 tile, so
+    the operator's result must be identical bit for bit, and match the oracle."""
+    from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
+    alpha, h = _setup(n, 71)
+    V = random_complex(n, 72)
+    out = {}
+    for cfg in (1, 4):
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+        for ax in range(len(n)):
+            plan.set_tiles(ax, False, cfg)
+            plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
+        out[cfg] = {k: plan.apply_f(k, 1e-2, _dev(V, "fp32")) for k in ("exp", "inv")}
+        plan.close()
+    P = O.Problem(n, alpha, h, BASE_PARAMS)
+    for k in ("exp", "inv"):
+        assert torch.equal(out[1][k], out[4][k]), k
+        err = O.rel_l2(_host(out[1][k]), P.f(k, 1e-2, V))
+        print(f"[q-stationary {n} {k}] rel_l2 = {err:.3e}")
+        assert err <= TOL_OP["fp32"]
