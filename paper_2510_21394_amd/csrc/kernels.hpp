@@ -1930,17 +1930,21 @@ __global__ void __launch_bounds__(T::THREADS)
 }
 
 // ---------------------------------------------------------------------------------------
-// Q-stationary even/odd FP32 mode product (N loader, no prologue, plain store).  The two
-// half-size blocks of the operator stay in LDS for the workgroup's lifetime (rows and k below
-// KP = 16 MT, k contiguous, rows padded to LDQ floats), and each of the 8 waves streams column
-// tiles of 16 tensor columns on its own: its B fragments go from global memory straight into
-// registers one 16-deep k-chunk ahead of the MFMAs that use them, so after the set-up there is
-// no barrier and no LDS store.  SP = kSplitFwd2: the forward fold (x[k] + x[n-1-k] for the even
-// block, x[k] - x[n-1-k] for the odd one, k < m_e), outputs to rows i and m_e + i;
-// SP = kSplitBwd: inputs rows k and m_e + k, outputs p + q to rows i and p - q to rows n-1-i.
-// The MFMA sequence per output element is that of mp_mfma_tile (k in steps of 4 per lane group,
-// 16 per chunk, chunks in order), so results are the same.  Wave w of workgroup b takes column
-// tiles t = 8 b + w, 8 (b + grid) + w, ...; the host keeps n B sizeof(float2) below 2^31.
+// Q-stationary even/odd FP32 mode product (no prologue or the plain nonlinearity, plain
+// store).  The two half-size blocks of the operator stay in LDS for the workgroup's lifetime
+// (rows and k below KP = 16 MT, k contiguous, rows padded to LDQ floats), and each of the 8
+// waves streams column tiles of 16 tensor columns on its own: its B fragments go from global
+// memory straight into registers one 16-deep k-chunk ahead of the MFMAs that use them, so
+// after the set-up there is no barrier and no LDS store.  (Loading the wave's next tile during
+// the last chunk instead of nothing measured slower: its second tile context costs registers.)  SP = kSplitFwd2: the forward fold (pro(x[k]) +
+// pro(x[n-1-k]) for the even block, the difference for the odd one, k < m_e), outputs to rows i
+// and m_e + i; SP = kSplitBwd: inputs rows k and m_e + k, outputs p + q to rows i and p - q to
+// rows n-1-i.  N loader (TL false): a tile is 16 consecutive columns b of one batch index a,
+// element (a, row, b) at (a n + row) B + b; T loader (TL true, B = 1): a tile is 16 consecutive
+// fibres a, element (a, row) at a n + row.  The MFMA sequence per output element is that of
+// mp_mfma_tile (k in steps of 4 per lane group, 16 per chunk, chunks in order), so results are
+// the same.  Wave w of workgroup b takes tiles t = 8 b + w, 8 (b + grid) + w, ...; the host keeps
+// a tile's offsets below 2^31 (N loader: n B sizeof(float2) < 2^31).
 constexpr int kQresWaves = 8;
 
 template <int MT>
@@ -1948,10 +1952,51 @@ constexpr size_t qres_lds_bytes() {
   return (size_t)2 * (16 * MT) * (16 * MT + 4) * sizeof(float);
 }
 
-template <int SP, int MT>
+// Where one wave's tile lives: a buffer view of its input and of its output (based at the
+// batch index for the N loader, at the tile's first fibre for the T loader), the lane's
+// column (N: b; T: fibre offset within the tile) and whether that column exists.
+struct QresTile {
+  __amdgpu_buffer_rsrc_t rin, rout;
+  uint32_t col;
+  bool colok;
+};
+
+template <bool TL>
+__device__ __forceinline__ QresTile qres_tile(const Geo& g, const float2* U, float2* out, uint32_t t, int lr) {
+  QresTile q;
+  if constexpr (TL) {
+    const uint32_t a0 = t * 16;
+    const uint64_t left = ((uint64_t)g.A - a0) * (uint32_t)g.n * sizeof(float2);
+    const uint32_t nrec = left < kBufMaxBytes ? (uint32_t)left : kBufMaxBytes;
+    q.rin = buf_rsrc(U + (uint64_t)a0 * (uint32_t)g.n, nrec);
+    q.rout = buf_rsrc(out + (uint64_t)a0 * (uint32_t)g.n, nrec);
+    q.col = (uint32_t)lr;
+    q.colok = a0 + (uint32_t)lr < g.A;
+  } else {
+    const uint32_t tilesB = (g.B + 15) / 16, nB = (uint32_t)g.n * g.B;
+    const uint32_t a = t / tilesB;
+    q.rin = buf_rsrc(U + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
+    q.rout = buf_rsrc(out + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
+    q.col = (t % tilesB) * 16 + (uint32_t)lr;
+    q.colok = q.col < g.B;
+  }
+  return q;
+}
+
+// Byte offset of row `row` of the lane's column; a masked element gets the top bit set (an
+// offset of at least 2^31 = kOob, which the bounds check reads as zero and drops on store):
+// no select the compiler could turn into a branch around the access.
+template <bool TL>
+__device__ __forceinline__ uint32_t qres_off(const Geo& g, const QresTile& q, int row, bool ok) {
+  const uint32_t e = TL ? q.col * (uint32_t)g.n + (uint32_t)row : (uint32_t)row * g.B + q.col;
+  return (e * (uint32_t)sizeof(float2)) | ((uint32_t)(!(ok && q.colok)) << 31);
+}
+
+template <int SP, int MT, bool TL, class Pro>
 __global__ void __launch_bounds__(64 * kQresWaves)
-    mp_qres_kernel(Geo g, const float* __restrict__ M, const float2* __restrict__ U, float2* __restrict__ out) {
+    mp_qres_kernel(Geo g, const float* __restrict__ M, const float2* __restrict__ U, float2* __restrict__ out, Pro pro) {
   static_assert(SP == kSplitFwd2 || SP == kSplitBwd, "even/odd forms with both blocks");
+  static_assert(Pro::kId || SP == kSplitFwd2, "the prologue belongs to the forward product");
   constexpr int KP = 16 * MT, LDQ = KP + 4;
   static_assert(qres_lds_bytes<MT>() <= kLdsBytes, "both blocks in LDS");
   __shared__ __attribute__((aligned(16))) float qs[2 * KP * LDQ];
@@ -1965,40 +2010,32 @@ __global__ void __launch_bounds__(64 * kQresWaves)
   __syncthreads();
   const int lane = tid & 63, lr = lane & 15, lg = lane >> 4;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const uint32_t tilesB = (g.B + 15) / 16, ntiles = g.A * tilesB;
-  const uint32_t nB = (uint32_t)g.n * g.B;
-  for (uint32_t t = blockIdx.x * kQresWaves + wave; t < ntiles; t += gridDim.x * kQresWaves) {
-    const uint32_t a = t / tilesB, b = (t % tilesB) * 16 + lr;
-    const bool colok = b < g.B;
-    const __amdgpu_buffer_rsrc_t rin = buf_rsrc(U + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
-    const __amdgpu_buffer_rsrc_t rout = buf_rsrc(out + (uint64_t)a * nB, nB * (uint32_t)sizeof(float2));
-    // a masked element gets the top bit set (an offset of at least 2^31 = kOob, which the
-    // bounds check reads as zero and drops on store): no select the compiler could turn into
-    // a branch around the load
-    auto off = [&](int row, bool ok) -> uint32_t {
-      return (((uint32_t)row * g.B + b) * (uint32_t)sizeof(float2)) | ((uint32_t)(!ok) << 31);
-    };
-    // the two input values of rows k = 16 kc + 4 lg + s, s < 4
-    auto load = [&](int kc, float2 (&l0)[4], float2 (&l1)[4]) {
+  const uint32_t ntiles = TL ? (g.A + 15) / 16 : g.A * ((g.B + 15) / 16);
+  const uint32_t stride = gridDim.x * kQresWaves;
+  uint32_t t = blockIdx.x * kQresWaves + wave;
+  // the input values of rows k = 16 kc + 4 lg + s (s < 4) of the two sets of tile q
+  auto load = [&](const QresTile& q, int kc, float2 (&l0)[4], float2 (&l1)[4]) {
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int k = 16 * kc + 4 * lg + s;
-        if constexpr (SP == kSplitFwd2) {
-          l0[s] = buf_load<float2>(rin, off(k, colok && k < g.me));
-          l1[s] = buf_load<float2>(rin, off(g.n - 1 - k, colok && k < g.me));
-        } else {
-          l0[s] = buf_load<float2>(rin, off(k, colok && k < g.me));
-          l1[s] = buf_load<float2>(rin, off(g.me + k, colok && k < g.mo));
-        }
+    for (int s = 0; s < 4; ++s) {
+      const int k = 16 * kc + 4 * lg + s;
+      if constexpr (SP == kSplitFwd2) {
+        l0[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, k, k < g.me));
+        l1[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, g.n - 1 - k, k < g.me));
+      } else {
+        l0[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, k, k < g.me));
+        l1[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, g.me + k, k < g.mo));
       }
-    };
+    }
+  };
+  for (; t < ntiles; t += stride) {
+    const QresTile cur = qres_tile<TL>(g, U, out, t, lr);
+    float2 x0[4], x1[4];
+    load(cur, 0, x0, x1);
     v4f acc[2][MT][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) acc[h][mt][0] = acc[h][mt][1] = v4f{0.f, 0.f, 0.f, 0.f};
-    float2 x0[4], x1[4];
-    load(0, x0, x1);
     // one chunk per iteration, not unrolled: the chunk's B values are formed from the loads in
     // flight, then the next chunk's loads are issued into the same registers (the scheduling
     // barrier keeps them ahead of the MFMAs), and the MFMAs run row tile by row tile with both
@@ -2009,14 +2046,15 @@ __global__ void __launch_bounds__(64 * kQresWaves)
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         if constexpr (SP == kSplitFwd2) {
-          bv[0][s] = float2{x0[s].x + x1[s].x, x0[s].y + x1[s].y};
-          bv[1][s] = float2{x0[s].x - x1[s].x, x0[s].y - x1[s].y};
+          const float2 p0 = pro(0, x0[s]), p1 = pro(0, x1[s]);
+          bv[0][s] = float2{p0.x + p1.x, p0.y + p1.y};
+          bv[1][s] = float2{p0.x - p1.x, p0.y - p1.y};
         } else {
           bv[0][s] = x0[s];
           bv[1][s] = x1[s];
         }
       }
-      load(kc + 1 < MT ? kc + 1 : kc, x0, x1);
+      load(cur, kc + 1 < MT ? kc + 1 : kc, x0, x1);  // the last chunk's reload goes unused
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {
@@ -2040,12 +2078,12 @@ __global__ void __launch_bounds__(64 * kQresWaves)
       for (int r = 0; r < 4; ++r) {
         const int i = mt * 16 + 4 * lg + r;
         if constexpr (SP == kSplitFwd2) {
-          buf_store(rout, off(i, colok && i < g.me), float2{acc[0][mt][0][r], acc[0][mt][1][r]});
-          buf_store(rout, off(g.me + i, colok && i < g.mo), float2{acc[1][mt][0][r], acc[1][mt][1][r]});
+          buf_store(cur.rout, qres_off<TL>(g, cur, i, i < g.me), float2{acc[0][mt][0][r], acc[0][mt][1][r]});
+          buf_store(cur.rout, qres_off<TL>(g, cur, g.me + i, i < g.mo), float2{acc[1][mt][0][r], acc[1][mt][1][r]});
         } else {
-          buf_store(rout, off(i, colok && i < g.me),
+          buf_store(cur.rout, qres_off<TL>(g, cur, i, i < g.me),
                     float2{acc[0][mt][0][r] + acc[1][mt][0][r], acc[0][mt][1][r] + acc[1][mt][1][r]});
-          buf_store(rout, off(g.n - 1 - i, colok && i < g.mo),
+          buf_store(cur.rout, qres_off<TL>(g, cur, g.n - 1 - i, i < g.mo),
                     float2{acc[0][mt][0][r] - acc[1][mt][0][r], acc[0][mt][1][r] - acc[1][mt][1][r]});
         }
       }

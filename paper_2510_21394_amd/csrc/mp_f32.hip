@@ -20,10 +20,10 @@ struct F32K {
   }
 };
 
-// The Q-stationary even/odd products (mp_qres_kernel): both blocks of up to 128 rows in LDS,
-// N loader, no prologue, plain store, offsets of one batch index below 2 GiB; hipErrorNotSupported
-// for every other case.
-template <int SP, int MT>
+// The Q-stationary even/odd products (mp_qres_kernel): both blocks of 49..128 rows in LDS,
+// either loader, no prologue (or the plain nonlinearity on forward products), plain store,
+// offsets of one tile below 2 GiB; hipErrorNotSupported for every other case.
+template <int SP, int MT, bool TL, class Pro>
 static hipError_t go_qres(const MPLaunch& L, hipStream_t s) {
   Geo g{};
   g.A = (uint32_t)L.A;
@@ -32,35 +32,50 @@ static hipError_t go_qres(const MPLaunch& L, hipStream_t s) {
   g.npad = L.npad;
   g.me = L.me;
   g.mo = L.mo;
-  const uint64_t tiles = (uint64_t)L.A * (uint64_t)((L.B + 15) / 16);
+  const uint64_t tiles = TL ? (uint64_t)((L.A + 15) / 16) : (uint64_t)L.A * (uint64_t)((L.B + 15) / 16);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return hipErrorNotSupported;
   const uint64_t want = (tiles + kQresWaves - 1) / kQresWaves;
   const uint32_t grid = (uint32_t)(want < (uint64_t)cus ? want : (uint64_t)cus);
-  hipLaunchKernelGGL((mp_qres_kernel<SP, MT>), dim3(grid), dim3(64 * kQresWaves), 0, s, g, (const float*)L.M,
-                     (const float2*)L.in, (float2*)L.ep.out);
+  hipLaunchKernelGGL((mp_qres_kernel<SP, MT, TL, Pro>), dim3(grid), dim3(64 * kQresWaves), 0, s, g,
+                     (const float*)L.M, (const float2*)L.in, (float2*)L.ep.out, Pro(L.pp));
   return hipGetLastError();
 }
 
-template <int SP>
+template <int SP, bool TL, class Pro>
 static hipError_t go_qres_rows(const MPLaunch& L, hipStream_t s) {
   switch ((L.me + 15) / 16) {
-    case 4: return go_qres<SP, 4>(L, s);
-    case 5: return go_qres<SP, 5>(L, s);
-    case 6: return go_qres<SP, 6>(L, s);
-    case 7: return go_qres<SP, 7>(L, s);
-    case 8: return go_qres<SP, 8>(L, s);
+    case 4: return go_qres<SP, 4, TL, Pro>(L, s);
+    case 5: return go_qres<SP, 5, TL, Pro>(L, s);
+    case 6: return go_qres<SP, 6, TL, Pro>(L, s);
+    case 7: return go_qres<SP, 7, TL, Pro>(L, s);
+    case 8: return go_qres<SP, 8, TL, Pro>(L, s);
     default: return hipErrorNotSupported;
   }
 }
 
-static hipError_t launch_qres_f32(const MPLaunch& L, hipStream_t s) {
-  if (L.B <= 1 || L.pk != ProKind::Id || L.ek != EpiKind::Store || L.wide) return hipErrorNotSupported;
-  if ((uint64_t)L.n * (uint64_t)L.B * sizeof(float2) >= 0x80000000ull) return hipErrorNotSupported;
-  if (L.split == kSplitFwd2) return go_qres_rows<kSplitFwd2>(L, s);
-  if (L.split == kSplitBwd) return go_qres_rows<kSplitBwd>(L, s);
+template <bool TL>
+static hipError_t launch_qres_loader(const MPLaunch& L, hipStream_t s) {
+  if (L.split == kSplitBwd) {
+    if (L.pk != ProKind::Id) return hipErrorNotSupported;
+    return go_qres_rows<kSplitBwd, TL, ProIdF>(L, s);
+  }
+  if (L.split != kSplitFwd2) return hipErrorNotSupported;
+  if (L.pk == ProKind::Id) return go_qres_rows<kSplitFwd2, TL, ProIdF>(L, s);
+  if (L.pk == ProKind::Nonlin && L.pp.ns == 0 && !L.pp.up)
+    return go_qres_rows<kSplitFwd2, TL, ProNonlinF<float, true>>(L, s);
   return hipErrorNotSupported;
+}
+
+static hipError_t launch_qres_f32(const MPLaunch& L, hipStream_t s) {
+  if (L.ek != EpiKind::Store || L.wide) return hipErrorNotSupported;
+  if (L.B > 1) {
+    if ((uint64_t)L.n * (uint64_t)L.B * sizeof(float2) >= 0x80000000ull) return hipErrorNotSupported;
+    return launch_qres_loader<false>(L, s);
+  }
+  if ((uint64_t)16 * (uint64_t)L.n * sizeof(float2) >= 0x80000000ull) return hipErrorNotSupported;
+  return launch_qres_loader<true>(L, s);
 }
 
 hipError_t launch_mp_f32(const MPLaunch& L, hipStream_t s) {

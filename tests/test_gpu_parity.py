@@ -493,13 +493,16 @@ def test_dispersive_exponential_conserves_norm(F, prec, tol):
         plan.close()
 
 
-@pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33)], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33), (40, 130), (20, 17, 200)],
+                         ids=lambda s: "x".join(map(str, s)))
 def test_q_stationary_products_equal_tiled(F, n):
     """FP32 even/odd tile configuration 1 runs the Q-stationary kernel (both half-size blocks
     held in LDS, each wave streaming its own column tiles) for the plain backward products and
-    the forward products with both blocks per tile along every axis but the last (half-blocks of
-    49..128 rows); it issues the same MFMA sequence per output element as the 128x128 tile, so
-    the operator's result must be identical bit for bit, and match the oracle."""
+    the forward products with both blocks per tile, N and T loaders (half-blocks of 49..128
+    rows; other axes run the 128x128 tile); it issues the same MFMA sequence per output element
+    as the 128x128 tile, so the operator's result must be identical bit for bit, and match the
+    oracle; so must an exponential-Euler run, whose first forward product carries the
+    nonlinearity in its loads."""
     from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
     alpha, h = _setup(n, 71)
     V = random_complex(n, 72)
@@ -517,3 +520,19 @@ def test_q_stationary_products_equal_tiled(F, n):
         err = O.rel_l2(_host(out[1][k]), P.f(k, 1e-2, V))
         print(f"[q-stationary {n} {k}] rel_l2 = {err:.3e}")
         assert err <= TOL_OP["fp32"]
+    U0 = random_complex(n, 73) * 0.5
+    runs = {}
+    for cfg in (1, 4):
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+        plan.set_fusion(True, True, False)
+        for ax in range(len(n)):
+            plan.set_tiles(ax, False, cfg)
+            plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
+        u = _dev(U0, "fp32")
+        plan.run("exp_euler", u, 0.0, 5)
+        runs[cfg] = u
+        plan.close()
+    assert torch.equal(runs[1], runs[4])
+    err = O.rel_l2(_host(runs[1]), O.run(P, "exp_euler", U0, 1e-3, 5))
+    print(f"[q-stationary {n} exp_euler] rel_l2 = {err:.3e}")
+    assert err <= TOL_OP["fp32"]
