@@ -1996,11 +1996,18 @@ template <int SP, int MT, bool TL, class Pro>
 __global__ void __launch_bounds__(64 * kQresWaves)
     mp_qres_kernel(Geo g, const float* __restrict__ M, const float2* __restrict__ U, float2* __restrict__ out, Pro pro) {
   static_assert(SP == kSplitFwd2 || SP == kSplitBwd, "even/odd forms with both blocks");
-  static_assert(Pro::kId || SP == kSplitFwd2, "the prologue belongs to the forward product");
+  constexpr bool UPD = Pro::kUpdate;
+  static_assert(Pro::kId || (UPD ? (SP == kSplitBwd && !TL) : SP == kSplitFwd2),
+                "the nonlinearity belongs to forward products, the update to N-loader backward ones");
   constexpr int KP = 16 * MT, LDQ = KP + 4;
-  static_assert(qres_lds_bytes<MT>() <= kLdsBytes, "both blocks in LDS");
+  constexpr int kRows = UPD ? kOtfMaxRows : 1;
+  using RowT = typename std::conditional_t<UPD, Pro, ProUpdateOtfF<float>>::RowEnt;
+  static_assert(qres_lds_bytes<MT>() + (UPD ? kRows * sizeof(RowT) : 0) <= kLdsBytes, "both blocks in LDS");
   __shared__ __attribute__((aligned(16))) float qs[2 * KP * LDQ];
+  __shared__ RowT rowtab[kRows];
   const int tid = threadIdx.x;
+  if constexpr (UPD)
+    for (int k = tid; k < g.n; k += 64 * kQresWaves) rowtab[k] = pro.row_entry(k);
   for (int q = tid; q < 2 * KP * (KP / 4); q += 64 * kQresWaves) {
     const int h = q / (KP * (KP / 4)), rem = q % (KP * (KP / 4));
     const int row = rem / (KP / 4), k4 = rem % (KP / 4);
@@ -2013,8 +2020,14 @@ __global__ void __launch_bounds__(64 * kQresWaves)
   const uint32_t ntiles = TL ? (g.A + 15) / 16 : g.A * ((g.B + 15) / 16);
   const uint32_t stride = gridDim.x * kQresWaves;
   uint32_t t = blockIdx.x * kQresWaves + wave;
-  // the input values of rows k = 16 kc + 4 lg + s (s < 4) of the two sets of tile q
-  auto load = [&](const QresTile& q, int kc, float2 (&l0)[4], float2 (&l1)[4]) {
+  // update prologue: the operands and the new state are addressed over the whole tensor (the
+  // host keeps it below 2 GiB), batch index a at byte a n B sizeof(float2)
+  const uint32_t ubytes = UPD ? g.A * (uint32_t)g.n * g.B * (uint32_t)sizeof(float2) : 0;
+  // the input values of rows k = 16 kc + 4 lg + s (s < 4) of the two sets of tile q (and with
+  // the update prologue the state's values at the same elements)
+  using PreT = typename std::conditional_t<UPD, Pro, ProUpdateOtfF<float>>::Pre;
+  auto load = [&](const QresTile& q, uint32_t gbase, int kc, float2 (&l0)[4], float2 (&l1)[4], PreT (&p0)[4],
+                  PreT (&p1)[4]) {
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
       const int k = 16 * kc + 4 * lg + s;
@@ -2022,15 +2035,26 @@ __global__ void __launch_bounds__(64 * kQresWaves)
         l0[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, k, k < g.me));
         l1[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, g.n - 1 - k, k < g.me));
       } else {
-        l0[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, k, k < g.me));
-        l1[s] = buf_load<float2>(q.rin, qres_off<TL>(g, q, g.me + k, k < g.mo));
+        const uint32_t o0 = qres_off<TL>(g, q, k, k < g.me), o1 = qres_off<TL>(g, q, g.me + k, k < g.mo);
+        l0[s] = buf_load<float2>(q.rin, o0);
+        l1[s] = buf_load<float2>(q.rin, o1);
+        if constexpr (UPD) {
+          p0[s] = pro.load(gbase + o0, 0, ubytes);
+          p1[s] = pro.load(gbase + o1, 0, ubytes);
+        }
       }
     }
   };
   for (; t < ntiles; t += stride) {
     const QresTile cur = qres_tile<TL>(g, U, out, t, lr);
+    const uint32_t gbase = TL ? 0u : (t / ((g.B + 15) / 16)) * ((uint32_t)g.n * g.B * (uint32_t)sizeof(float2));
+    using ColT = typename UpdColOf<Pro, UPD>::type;
+    ColT eo{};
+    if constexpr (UPD)
+      if (cur.colok) eo = pro.col(0u, cur.col);
     float2 x0[4], x1[4];
-    load(cur, 0, x0, x1);
+    PreT p0[4], p1[4];
+    load(cur, gbase, 0, x0, x1, p0, p1);
     v4f acc[2][MT][2];
 #pragma unroll
     for (int h = 0; h < 2; ++h)
@@ -2049,12 +2073,20 @@ __global__ void __launch_bounds__(64 * kQresWaves)
           const float2 p0 = pro(0, x0[s]), p1 = pro(0, x1[s]);
           bv[0][s] = float2{p0.x + p1.x, p0.y + p1.y};
           bv[1][s] = float2{p0.x - p1.x, p0.y - p1.y};
+        } else if constexpr (UPD) {
+          // the new state of both elements, stored, then contracted
+          const int k = 16 * kc + 4 * lg + s;
+          const bool ok0 = k < g.me, ok1 = k < g.mo;
+          bv[0][s] = pro.update(eo, rowtab[ok0 ? k : 0], x0[s], p0[s]);
+          bv[1][s] = pro.update(eo, rowtab[ok1 ? g.me + k : 0], x1[s], p1[s]);
+          pro.save(gbase + qres_off<TL>(g, cur, k, ok0), bv[0][s], ubytes);
+          pro.save(gbase + qres_off<TL>(g, cur, g.me + k, ok1), bv[1][s], ubytes);
         } else {
           bv[0][s] = x0[s];
           bv[1][s] = x1[s];
         }
       }
-      load(cur, kc + 1 < MT ? kc + 1 : kc, x0, x1);  // the last chunk's reload goes unused
+      load(cur, gbase, kc + 1 < MT ? kc + 1 : kc, x0, x1, p0, p1);  // the last chunk's reload goes unused
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int mt = 0; mt < MT; ++mt) {

@@ -58,8 +58,12 @@ static hipError_t go_qres_rows(const MPLaunch& L, hipStream_t s) {
 template <bool TL>
 static hipError_t launch_qres_loader(const MPLaunch& L, hipStream_t s) {
   if (L.split == kSplitBwd) {
-    if (L.pk != ProKind::Id) return hipErrorNotSupported;
-    return go_qres_rows<kSplitBwd, TL, ProIdF>(L, s);
+    if (L.pk == ProKind::Id) return go_qres_rows<kSplitBwd, TL, ProIdF>(L, s);
+    if constexpr (!TL)
+      if (L.pk == ProKind::UpdateOtf && L.n <= kOtfMaxRows &&
+          (uint64_t)L.A * (uint64_t)L.n * (uint64_t)L.B * sizeof(float2) < 0x80000000ull)
+        return go_qres_rows<kSplitBwd, TL, ProUpdateOtfF<float>>(L, s);
+    return hipErrorNotSupported;
   }
   if (L.split != kSplitFwd2) return hipErrorNotSupported;
   if (L.pk == ProKind::Id) return go_qres_rows<kSplitFwd2, TL, ProIdF>(L, s);

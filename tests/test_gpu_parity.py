@@ -521,18 +521,20 @@ def test_q_stationary_products_equal_tiled(F, n):
         print(f"[q-stationary {n} {k}] rel_l2 = {err:.3e}")
         assert err <= TOL_OP["fp32"]
     U0 = random_complex(n, 73) * 0.5
-    runs = {}
-    for cfg in (1, 4):
-        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
-        plan.set_fusion(True, True, False)
-        for ax in range(len(n)):
-            plan.set_tiles(ax, False, cfg)
-            plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
-        u = _dev(U0, "fp32")
-        plan.run("exp_euler", u, 0.0, 5)
-        runs[cfg] = u
-        plan.close()
-    assert torch.equal(runs[1], runs[4])
-    err = O.rel_l2(_host(runs[1]), O.run(P, "exp_euler", U0, 1e-3, 5))
-    print(f"[q-stationary {n} exp_euler] rel_l2 = {err:.3e}")
-    assert err <= TOL_OP["fp32"]
+    ref = O.run(P, "exp_euler", U0, 1e-3, 5)
+    for upd in (False, True):  # the update in the first backward product's loads, or not
+        runs = {}
+        for cfg in (1, 4):
+            plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+            plan.set_fusion(True, True, False, update_in_backward=upd, phi1_on_the_fly=upd)
+            for ax in range(len(n)):
+                plan.set_tiles(ax, False, cfg)
+                plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
+            u = _dev(U0, "fp32")
+            plan.run("exp_euler", u, 0.0, 5)
+            runs[cfg] = u
+            plan.close()
+        assert torch.equal(runs[1], runs[4]), upd
+        err = O.rel_l2(_host(runs[1]), ref)
+        print(f"[q-stationary {n} exp_euler update_in_backward={upd}] rel_l2 = {err:.3e}")
+        assert err <= TOL_OP["fp32"]
