@@ -18,7 +18,7 @@ constexpr int kCfgCols[2][4][kNumCfg] = {
 // k-tile length of the split configurations (the dense ones use 16 for FP32, 8 for FP64 and
 // 32 for split BF16); index [prec][cfg].
 constexpr int kCfgTkSplit[4][kNumCfg] = {
-    {16, 16, 16, 16, 16}, {16, 16, 16, 16, 16}, {32, 32, 64, 32, 32}, {32, 32, 32, 32, 32}};
+    {16, 16, 16, 16, 16}, {16, 16, 16, 16, 16}, {32, 32, 32, 32, 32}, {32, 32, 32, 32, 32}};
 // LDS buffers of the operand tiles (1: single-buffered configurations).
 constexpr int kCfgBufs[2][4][kNumCfg] = {
     {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}},

@@ -2122,6 +2122,128 @@ __global__ void __launch_bounds__(64 * kQresWaves)
   }
 }
 
+// Q-stationary even/odd product in split BF16 with two pieces (BF16x3: hi*lo + lo*hi + hi*hi,
+// FP32 accumulation), N loader, no prologue or the plain nonlinearity, plain store: the FP32
+// kernel above with 32-deep k-chunks (v_mfma_f32_16x16x32_bf16) and both pieces of both blocks
+// in LDS (rows below 16 MT, k below 32 KC, KC = ceil(MT / 2), rows padded to LDQ halves).  A
+// lane holds k = 32 kc + 8 lg + e, e < 8, of its column, folds (forward) and splits the values
+// into pieces in registers; per accumulator the MFMA sequence is that of mp_bf16_kernel
+// (chunks in order, hi*lo, lo*hi, hi*hi within a chunk), so results are the same.
+template <int MT>
+constexpr size_t qres_bf16_lds_bytes() {
+  return (size_t)2 * 2 * (16 * MT) * (32 * ((MT + 1) / 2) + 8) * sizeof(__bf16);
+}
+
+template <int SP, int MT, class Pro>
+__global__ void __launch_bounds__(64 * kQresWaves)
+    mp_qres_bf16_kernel(Geo g, const __bf16* __restrict__ Mp, const float2* __restrict__ U, float2* __restrict__ out,
+                        Pro pro) {
+  static_assert(SP == kSplitFwd2 || SP == kSplitBwd, "even/odd forms with both blocks");
+  static_assert(Pro::kId || SP == kSplitFwd2, "the nonlinearity belongs to forward products");
+  constexpr int KC = (MT + 1) / 2, KP = 32 * KC, RP = 16 * MT, LDQ = KP + 8;
+  static_assert(qres_bf16_lds_bytes<MT>() <= kLdsBytes, "both pieces of both blocks in LDS");
+  __shared__ __attribute__((aligned(16))) __bf16 qs[2 * 2 * RP * LDQ];  // [h][piece][row][k]
+  const int tid = threadIdx.x;
+  const int64_t piece = (int64_t)g.npad * g.npad;
+  for (int q = tid; q < 4 * RP * (KP / 8); q += 64 * kQresWaves) {
+    const int hq = q / (RP * (KP / 8)), rem = q % (RP * (KP / 8));
+    const int row = rem / (KP / 8), k8 = rem % (KP / 8);
+    *(v8bf*)&qs[(hq * RP + row) * LDQ + 8 * k8] = *(const v8bf*)&Mp[hq * piece + (int64_t)row * g.npad + 8 * k8];
+  }
+  __syncthreads();
+  const int lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const uint32_t ntiles = g.A * ((g.B + 15) / 16);
+  const uint32_t stride = gridDim.x * kQresWaves;
+  auto load = [&](const QresTile& q, int kc, float2 (&l0)[8], float2 (&l1)[8]) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 32 * kc + 8 * lg + e;
+      if constexpr (SP == kSplitFwd2) {
+        l0[e] = buf_load<float2>(q.rin, qres_off<false>(g, q, k, k < g.me));
+        l1[e] = buf_load<float2>(q.rin, qres_off<false>(g, q, g.n - 1 - k, k < g.me));
+      } else {
+        l0[e] = buf_load<float2>(q.rin, qres_off<false>(g, q, k, k < g.me));
+        l1[e] = buf_load<float2>(q.rin, qres_off<false>(g, q, g.me + k, k < g.mo));
+      }
+    }
+  };
+  for (uint32_t t = blockIdx.x * kQresWaves + wave; t < ntiles; t += stride) {
+    const QresTile cur = qres_tile<false>(g, U, out, t, lr);
+    float2 x0[8], x1[8];
+    load(cur, 0, x0, x1);
+    v4f acc[2][MT][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) acc[h][mt][0] = acc[h][mt][1] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int kc = 0; kc < KC; ++kc) {
+      // B pieces [block][re/im][piece] of this chunk, then the next chunk's loads
+      v8bf bp[2][2][2];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        float2 v[2];
+        if constexpr (SP == kSplitFwd2) {
+          const float2 p0 = pro(0, x0[e]), p1 = pro(0, x1[e]);
+          v[0] = float2{p0.x + p1.x, p0.y + p1.y};
+          v[1] = float2{p0.x - p1.x, p0.y - p1.y};
+        } else {
+          v[0] = x0[e];
+          v[1] = x1[e];
+        }
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          __bf16 pr[2], pi[2];
+          split_bf16<2>(v[h].x, pr);
+          split_bf16<2>(v[h].y, pi);
+          bp[h][0][0][e] = pr[0];
+          bp[h][0][1][e] = pr[1];
+          bp[h][1][0][e] = pi[0];
+          bp[h][1][1][e] = pi[1];
+        }
+      }
+      load(cur, kc + 1 < KC ? kc + 1 : kc, x0, x1);  // the last chunk's reload goes unused
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt) {
+        v8bf af[2][2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+            af[h][q] = *(const v8bf*)&qs[((h * 2 + q) * RP + mt * 16 + lr) * LDQ + 32 * kc + 8 * lg];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int p = 0; p < 2; ++p) {
+            v4f c = acc[h][mt][p];
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][0], bp[h][p][1], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][1], bp[h][p][0], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[h][0], bp[h][p][0], c, 0, 0, 0);
+            acc[h][mt][p] = c;
+          }
+      }
+    }
+    // accumulator slot r of lane l holds row 4 (l / 16) + r of its 16-row tile, column l % 16
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = mt * 16 + 4 * lg + r;
+        if constexpr (SP == kSplitFwd2) {
+          buf_store(cur.rout, qres_off<false>(g, cur, i, i < g.me), float2{acc[0][mt][0][r], acc[0][mt][1][r]});
+          buf_store(cur.rout, qres_off<false>(g, cur, g.me + i, i < g.mo), float2{acc[1][mt][0][r], acc[1][mt][1][r]});
+        } else {
+          buf_store(cur.rout, qres_off<false>(g, cur, i, i < g.me),
+                    float2{acc[0][mt][0][r] + acc[1][mt][0][r], acc[0][mt][1][r] + acc[1][mt][1][r]});
+          buf_store(cur.rout, qres_off<false>(g, cur, g.n - 1 - i, i < g.mo),
+                    float2{acc[0][mt][0][r] - acc[1][mt][0][r], acc[0][mt][1][r] - acc[1][mt][1][r]});
+        }
+      }
+  }
+}
+
 // ---------------------------------------------------------------------------------------
 // Host-side helpers shared by the per-precision dispatch units
 // ---------------------------------------------------------------------------------------

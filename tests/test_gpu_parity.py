@@ -493,48 +493,50 @@ def test_dispersive_exponential_conserves_norm(F, prec, tol):
         plan.close()
 
 
+@pytest.mark.parametrize("prec,cq,cref", [("fp32", 1, 4), ("bf16x3", 2, 3)], ids=["fp32", "bf16x3"])
 @pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33), (40, 130), (20, 17, 200)],
                          ids=lambda s: "x".join(map(str, s)))
-def test_q_stationary_products_equal_tiled(F, n):
-    """FP32 even/odd tile configuration 1 runs the Q-stationary kernel (both half-size blocks
-    held in LDS, each wave streaming its own column tiles) for the plain backward products and
-    the forward products with both blocks per tile, N and T loaders (half-blocks of 49..128
-    rows; other axes run the 128x128 tile); it issues the same MFMA sequence per output element
-    as the 128x128 tile, so the operator's result must be identical bit for bit, and match the
-    oracle; so must an exponential-Euler run, whose first forward product carries the
-    nonlinearity in its loads."""
+def test_q_stationary_products_equal_tiled(F, n, prec, cq, cref):
+    """FP32 even/odd tile configuration 1 (BF16x3: 2) runs the Q-stationary kernel (both
+    half-size blocks held in LDS, each wave streaming its own column tiles) for the plain
+    backward products and the forward products with both blocks per tile (FP32: N and T
+    loaders, BF16x3: N loader; half-blocks of 49..128 rows; other cases run the 128x128
+    (BF16x3: 128x32 single-buffered) tile); it issues the same MFMA sequence per output element
+    as that tile, so the operator's result must be identical bit for bit, and match the oracle;
+    so must exponential-Euler runs, whose first forward product carries the nonlinearity in its
+    loads (FP32: also with the update in the first backward product's loads)."""
     from paper_2510_21394_amd.fcgle import NUM_TILE_CONFIGS
     alpha, h = _setup(n, 71)
     V = random_complex(n, 72)
     out = {}
-    for cfg in (1, 4):
-        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+    for cfg in (cq, cref):
+        plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
         for ax in range(len(n)):
             plan.set_tiles(ax, False, cfg)
             plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
-        out[cfg] = {k: plan.apply_f(k, 1e-2, _dev(V, "fp32")) for k in ("exp", "inv")}
+        out[cfg] = {k: plan.apply_f(k, 1e-2, _dev(V, prec)) for k in ("exp", "inv")}
         plan.close()
     P = O.Problem(n, alpha, h, BASE_PARAMS)
     for k in ("exp", "inv"):
-        assert torch.equal(out[1][k], out[4][k]), k
-        err = O.rel_l2(_host(out[1][k]), P.f(k, 1e-2, V))
-        print(f"[q-stationary {n} {k}] rel_l2 = {err:.3e}")
-        assert err <= TOL_OP["fp32"]
+        assert torch.equal(out[cq][k], out[cref][k]), k
+        err = O.rel_l2(_host(out[cq][k]), P.f(k, 1e-2, V))
+        print(f"[q-stationary {prec} {n} {k}] rel_l2 = {err:.3e}")
+        assert err <= TOL_OP[prec]
     U0 = random_complex(n, 73) * 0.5
     ref = O.run(P, "exp_euler", U0, 1e-3, 5)
-    for upd in (False, True):  # the update in the first backward product's loads, or not
+    for upd in ((False, True) if prec == "fp32" else (False,)):  # update in the backward loads, or not
         runs = {}
-        for cfg in (1, 4):
-            plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision="fp32")
+        for cfg in (cq, cref):
+            plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=1e-3, precision=prec)
             plan.set_fusion(True, True, False, update_in_backward=upd, phi1_on_the_fly=upd)
             for ax in range(len(n)):
                 plan.set_tiles(ax, False, cfg)
                 plan.set_tiles(ax, True, cfg + NUM_TILE_CONFIGS)
-            u = _dev(U0, "fp32")
+            u = _dev(U0, prec)
             plan.run("exp_euler", u, 0.0, 5)
             runs[cfg] = u
             plan.close()
-        assert torch.equal(runs[1], runs[4]), upd
-        err = O.rel_l2(_host(runs[1]), ref)
-        print(f"[q-stationary {n} exp_euler update_in_backward={upd}] rel_l2 = {err:.3e}")
-        assert err <= TOL_OP["fp32"]
+        assert torch.equal(runs[cq], runs[cref]), upd
+        err = O.rel_l2(_host(runs[cq]), ref)
+        print(f"[q-stationary {prec} {n} exp_euler update_in_backward={upd}] rel_l2 = {err:.3e}")
+        assert err <= TOL_OP[prec]
