@@ -1983,13 +1983,14 @@ __device__ __forceinline__ QresTile qres_tile(const Geo& g, const float2* U, flo
   return q;
 }
 
-// Byte offset of row `row` of the lane's column; a masked element gets the top bit set (an
-// offset of at least 2^31 = kOob, which the bounds check reads as zero and drops on store):
-// no select the compiler could turn into a branch around the access.
+// Byte offset (from `base`) of row `row` of the lane's column; a masked element gets the top
+// bit set (an offset of at least 2^31 = kOob, which the bounds check of a view below 2 GiB
+// reads as zero and drops on store): no select the compiler could turn into a branch around
+// the access.  The bit is set after the base is added, so no sum wraps into the view.
 template <bool TL>
-__device__ __forceinline__ uint32_t qres_off(const Geo& g, const QresTile& q, int row, bool ok) {
+__device__ __forceinline__ uint32_t qres_off(const Geo& g, const QresTile& q, int row, bool ok, uint32_t base = 0) {
   const uint32_t e = TL ? q.col * (uint32_t)g.n + (uint32_t)row : (uint32_t)row * g.B + q.col;
-  return (e * (uint32_t)sizeof(float2)) | ((uint32_t)(!(ok && q.colok)) << 31);
+  return (base + e * (uint32_t)sizeof(float2)) | ((uint32_t)(!(ok && q.colok)) << 31);
 }
 
 template <int SP, int MT, bool TL, class Pro>
@@ -2039,8 +2040,8 @@ __global__ void __launch_bounds__(64 * kQresWaves)
         l0[s] = buf_load<float2>(q.rin, o0);
         l1[s] = buf_load<float2>(q.rin, o1);
         if constexpr (UPD) {
-          p0[s] = pro.load(gbase + o0, 0, ubytes);
-          p1[s] = pro.load(gbase + o1, 0, ubytes);
+          p0[s] = pro.load(qres_off<TL>(g, q, k, k < g.me, gbase), 0, ubytes);
+          p1[s] = pro.load(qres_off<TL>(g, q, g.me + k, k < g.mo, gbase), 0, ubytes);
         }
       }
     }
@@ -2079,8 +2080,8 @@ __global__ void __launch_bounds__(64 * kQresWaves)
           const bool ok0 = k < g.me, ok1 = k < g.mo;
           bv[0][s] = pro.update(eo, rowtab[ok0 ? k : 0], x0[s], p0[s]);
           bv[1][s] = pro.update(eo, rowtab[ok1 ? g.me + k : 0], x1[s], p1[s]);
-          pro.save(gbase + qres_off<TL>(g, cur, k, ok0), bv[0][s], ubytes);
-          pro.save(gbase + qres_off<TL>(g, cur, g.me + k, ok1), bv[1][s], ubytes);
+          pro.save(qres_off<TL>(g, cur, k, ok0, gbase), bv[0][s], ubytes);
+          pro.save(qres_off<TL>(g, cur, g.me + k, ok1, gbase), bv[1][s], ubytes);
         } else {
           bv[0][s] = x0[s];
           bv[1][s] = x1[s];
