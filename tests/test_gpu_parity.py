@@ -494,7 +494,8 @@ def test_dispersive_exponential_conserves_norm(F, prec, tol):
 
 
 @pytest.mark.parametrize("prec,cq,cref", [("fp32", 1, 4), ("bf16x3", 2, 3)], ids=["fp32", "bf16x3"])
-@pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33), (40, 130), (20, 17, 200)],
+@pytest.mark.parametrize("n", [(130, 75), (120, 100, 64), (256, 40, 30), (97, 33), (40, 130), (20, 17, 200),
+                               (180, 40), (24, 181)],
                          ids=lambda s: "x".join(map(str, s)))
 def test_q_stationary_products_equal_tiled(F, n, prec, cq, cref):
     """FP32 even/odd tile configuration 1 (BF16x3: 2) runs the Q-stationary kernel (both
