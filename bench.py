@@ -412,7 +412,9 @@ def strang_timing():
     del res
     # the paper's own timed configurations of this example (Section 4, second 3-D experiment):
     # n = 250, 30 steps in FP64 (its workstation figure: V100, 0.567 s) and 25 steps in FP32 (its
-    # laptop figure: GTX 1650 Ti, 1.91 s); wall-clock of the time integration, set-up excluded
+    # laptop figure: GTX 1650 Ti, 1.91 s).  Timed here: the time integration, set-up excluded; the
+    # paper's figures are the wall-clock time of its whole integration, of which it reports the
+    # diagonalisation and the host-to-GPU transfer as a negligible part
     w250 = W.strang_3d(n=250)
     U250 = W.u0_strang(w250)
     for prec, steps, paper_s, paper_hw in (("fp64", 30, 0.567, "V100"), ("fp32", 25, 1.91, "GTX 1650 Ti")):
@@ -436,7 +438,9 @@ def lbdf2_paper_timing():
     """Context: the paper's own timed LBDF2 configurations of its Example 1 in 3-D (Section 4,
     first 3-D experiment): n = 200 on (-1,1)^3, alpha = (1.2, 1.8, 1.5), one source term with
     rate -i; 50 steps in FP64 (its workstation figure: V100, 0.879 s) and 35 steps in FP32 (its
-    laptop figure: GTX 1650 Ti, 1.37 s); wall-clock of the time integration, set-up excluded.
+    laptop figure: GTX 1650 Ti, 1.37 s).  Timed here: the time integration, set-up excluded; the
+    paper's figures are the wall-clock time of its whole integration, of which it reports the
+    diagonalisation and the host-to-GPU transfer as a negligible part.
     The source tensor here is a stand-in of the same shape (its values do not change the work);
     the manufactured one, and the errors it gives, are checked by the test suite."""
     import torch
