@@ -373,6 +373,7 @@ int tucker(fcgle_plan* P, bool fwd, const void* in, ProKind pk, const ProParams&
         L.pp.sep.mu = mu;
         if (P->cfg_upd >= 0) L.cfg = P->cfg_upd;
         if (pk == ProKind::UpdateOtf && !otf_fits(L.prec, L.cfg)) L.pk = ProKind::Update;  // reads the P1 grid
+        if (L.split) L.cfg = cfg_update_tile(L.prec, L.cfg, L.pk == ProKind::UpdateOtf);  // a tile that keeps its registers
       } else if ((pk == ProKind::Flow ? (P->fusion & 64) : (P->fusion & 1)) &&
                  mp_supported(tl, pk, last ? ek : EpiKind::Store)) {
         L.pk = pk;
@@ -1447,6 +1448,8 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
       const int fusion = kFusions[fi];
       const bool upd = (fusion & 8) != 0;
       for (int c = upd ? 0 : -1; c < (upd ? kNumCfg : 0); ++c) {
+        // a configuration that hands its update prologue to another tile would time that tile again
+        if (upd && cfg_update_tile(pr, c, (fusion & 32) && otf_fits(pr, c)) != c) continue;
         plan->fwd_rev = (rev != 0);
         plan->fusion = fusion;
         plan->cfg_upd = c;

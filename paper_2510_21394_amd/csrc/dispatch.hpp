@@ -24,6 +24,17 @@ constexpr int kCfgBufs[2][4][kNumCfg] = {
     {{2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}, {2, 2, 2, 2, 2}},
     {{2, 1, 2, 2, 2}, {2, 2, 2, 2, 2}, {1, 2, 1, 1, 1}, {2, 1, 2, 1, 1}}};
 
+// Even/odd configuration whose tile runs the update prologue of configuration c; index
+// [prec][otf][c] (otf: the on-the-fly form, else the P1-grid form).  The 16-wave tiles (FP64
+// and FP32 configuration 2) leave 128 VGPRs per lane, which the update prologue overflows into
+// scratch, and so does FP32 configuration 3 with the P1-grid form; each hands the update to the
+// tile of the same shape with fewer waves (same rows, columns and LDS, so the same results).
+constexpr int kCfgUpdTile[4][2][kNumCfg] = {
+    {{0, 1, 4, 3, 4}, {0, 1, 4, 3, 4}},
+    {{0, 1, 4, 0, 4}, {0, 1, 4, 3, 4}},
+    {{0, 1, 2, 3, 4}, {0, 1, 2, 3, 4}},
+    {{0, 1, 2, 3, 4}, {0, 1, 2, 3, 4}}};
+
 // Instantiates the (loader, prologue, epilogue) combination of L for structure SP; the
 // combinations a structure never needs are not instantiated.
 template <class K, class T, int SP>

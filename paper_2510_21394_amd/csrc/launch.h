@@ -133,6 +133,7 @@ int cfg_rows(int prec, int cfg, int split = 0);
 int cfg_cols(int prec, int cfg, int split = 0);  // complex columns per tile
 int cfg_bufs(int prec, int cfg, int split = 0);  // LDS buffers of the operand tiles (1 or 2)
 int cfg_tk_split(int prec, int cfg);              // k-tile length of an even/odd configuration
+int cfg_update_tile(int prec, int cfg, bool otf);  // configuration that runs the update prologue
 // True when the even/odd split kernels exist for the precision.
 bool split_supported(int prec);
 

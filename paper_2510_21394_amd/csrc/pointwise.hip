@@ -230,6 +230,7 @@ int cfg_rows(int prec, int cfg, int split) { return kCfgRows[split ? 1 : 0][prec
 int cfg_cols(int prec, int cfg, int split) { return kCfgCols[split ? 1 : 0][prec][cfg]; }
 int cfg_bufs(int prec, int cfg, int split) { return kCfgBufs[split ? 1 : 0][prec][cfg]; }
 int cfg_tk_split(int prec, int cfg) { return kCfgTkSplit[prec][cfg]; }
+int cfg_update_tile(int prec, int cfg, bool otf) { return kCfgUpdTile[prec][otf ? 1 : 0][cfg]; }
 bool split_supported(int prec) { return prec >= P_F64 && prec <= P_BF16X6; }
 
 }  // namespace fcgle

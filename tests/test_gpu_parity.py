@@ -336,7 +336,8 @@ def test_update_in_backward_prologue(F, prec, cfg, n, otf):
     ragged column tiles, and two row tiles per column (n0 = 150 and 131 with 64-row tiles), where
     only the first row tile stores the new state; phi_1 read from the grid or formed on the fly
     (every configuration leaves LDS for the staged rows).  Against the oracle trajectory, and the
-    timing record shows the update prologue on the axis-0 backward product."""
+    timing record shows the update prologue on the axis-0 backward product, in the tile that
+    runs it (configurations whose tile would spill hand it to the same-shape tile)."""
     alpha, h = _setup(n, 31)
     params = (0.9, -0.4, 0.8, 1.1, 0.6)
     tau, steps = 2e-3, 6
@@ -360,9 +361,37 @@ def test_update_in_backward_prologue(F, prec, cfg, n, otf):
     # every configuration leaves LDS for the staged rows (4 values of the arithmetic precision each)
     grid_only = not otf
     assert pro == {"exp_euler_update" if grid_only else "exp_euler_update_otf"}
+    # the 16-wave tiles (FP64 and FP32 configuration 2), and FP32 configuration 3 with the grid,
+    # would spill the update's registers: the update runs the same-shape tile with fewer waves
+    want = {("fp64", 2): 4, ("fp32", 2): 4}.get((prec, cfg), cfg)
+    if prec == "fp32" and cfg == 3 and grid_only:
+        want = 0
+    upd_cfg = {F.fcgle.decode_signature(r[2])["tile_cfg"] for r in rec if r[0] == 0 and r[1] == 0}
+    assert upd_cfg == {want}
     epi = {F.fcgle.decode_signature(r[2])["epilogue"] for r in rec if r[1] == 1}
     assert epi == {"store"}
     plan.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_update_tile_handover_is_exact(F, prec):
+    """A 16-wave configuration (2) hands the update prologue to the same-shape 8-wave tile
+    (configuration 4): trajectories with either configuration on the update product are equal
+    bit for bit, in both forms of phi_1."""
+    n = (150, 21, 26)
+    alpha, h = _setup(n, 31)
+    U0 = sech_product(grid_axes(n, ((-9.0, 9.0),) * 3), [0.7, 0.2, 0.2], 0.3)
+    for otf in (False, True):
+        runs = {}
+        for cfg in (2, 4):
+            plan = F.Plan(n, alpha, h, BASE_PARAMS, tau=2e-3, precision=prec)
+            plan.set_fusion(True, True, False, update_in_backward=True, phi1_on_the_fly=otf)
+            plan.set_tiles(0, 0, cfg)
+            u = _dev(U0, prec)
+            plan.run("exp_euler", u, 0.0, 4)
+            runs[cfg] = u
+            plan.close()
+        assert torch.equal(runs[2], runs[4]), otf
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
