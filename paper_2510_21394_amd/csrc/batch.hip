@@ -235,6 +235,7 @@ int build_items(BatchData* B, const void* const* u) {
       if (bytes == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no grouped kernel for phase %d", p);
       std::vector<unsigned char> host(bytes);
       ph.nblocks = group_build_f32(ph.cfg, ph.tl, ph.pk, ph.ek, L.data(), nc, host.data());
+      if (ph.nblocks == 0) return fail(FCGLE_ERR_UNSUPPORTED, "batch: no grouped kernel for the items of phase %d", p);
       if (!ph.items) {
         // largest item type over the epilogue choices of this phase
         const size_t cap =

@@ -21,7 +21,9 @@ template <int SP, class F>
 bool with_fwd_combo(bool tl, ProKind pk, EpiKind ek, F&& f) {
   using R = float;
   if (!tl && pk == ProKind::Nonlin && ek == EpiKind::Store) {
-    f(Combo<false, SP, ProNonlinF<R>, EpiStoreF<R>>{});
+    // batched instances carry no source terms and no extrapolated state (group_build_f32
+    // refuses items that do): the plain form of the nonlinearity
+    f(Combo<false, SP, ProNonlinF<R, true>, EpiStoreF<R>>{});
     return true;
   }
   if (!tl && pk == ProKind::Id && ek == EpiKind::Store) {
@@ -125,6 +127,9 @@ size_t group_item_bytes(ProKind pk, EpiKind ek) {
 uint32_t group_build_f32(int cfg, bool tloader, ProKind pk, EpiKind ek, const MPLaunch* L, int count,
                          void* items_host) {
   uint32_t total = 0;
+  if (pk == ProKind::Nonlin)
+    for (int k = 0; k < count; ++k)
+      if (L[k].pp.ns != 0 || L[k].pp.up != nullptr) return 0;  // only the plain nonlinearity is grouped
   const int sp = count > 0 ? L[0].split : 0;
   with_cfg(cfg, [&](auto t) {
     using T = decltype(t);

@@ -158,7 +158,8 @@ inline hipError_t launch_mode_product(const MPLaunch& L, hipStream_t s) {
 // bytes per item) and returns the total number of workgroups; the array must then be copied
 // to the device and passed to launch_group_f32 with the same split (1 or 3 forward, 2
 // backward).  Supported: forward (N loader, Nonlin or Id, Store), (T loader, Id, Store or
-// ExpEuler); backward (either loader, Id, Store).
+// ExpEuler); backward (either loader, Id, Store).  Nonlin is the plain form only: items with
+// source terms or an extrapolated state make group_build_f32 return 0.
 bool group_supported(bool tloader, ProKind pk, EpiKind ek, bool fwd);
 constexpr int kGroupCfg = 5;  // tile configurations of the grouped kernels
 int group_cfg_rows(int cfg);   // rows per tile of grouped configuration cfg
