@@ -1398,11 +1398,14 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
   const size_t bytes = (size_t)plan->N * plan->elem;
   HIP_TRY(hipMemsetAsync(plan->s[0], 0, bytes, st));
   HIP_TRY(hipMemsetAsync(plan->s[2], 0, bytes, st));
-  // 1. tile configuration of every plain mode product
+  // 1. tile configuration of every plain mode product (the runner-up is kept for step 3)
+  int second_c[4][2], second_f2[4][2];  // [axis][fwd], like the plan's cfg
   for (int mu = 0; mu < plan->d; ++mu)
     for (int dir = 0; dir < 2; ++dir) {
-      float best = 1e30f;
+      float best = 1e30f, second = 1e30f;
       int best_c = plan->cfg[mu][dir];
+      second_c[mu][dir] = -1;
+      second_f2[mu][dir] = 0;
       // forward even/odd products: also the form with both blocks in one tile
       const int nform = (dir == 1 && plan->split) ? 2 : 1;
       bool best_f2 = false;
@@ -1416,9 +1419,16 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
           float ms;
           FC_TRY(time_ms(st, e0, e1, reps * 3 > 10 ? reps * 3 : 10, [&] { return launch_mode_product(L, st); }, &ms));
           if (ms < best) {
+            second = best;
+            second_c[mu][dir] = best < 1e30f ? best_c : -1;
+            second_f2[mu][dir] = best_f2;
             best = ms;
             best_c = c;
             best_f2 = (form == 1);
+          } else if (ms < second) {
+            second = ms;
+            second_c[mu][dir] = c;
+            second_f2[mu][dir] = (form == 1);
           }
         }
       plan->cfg[mu][dir] = best_c;
@@ -1438,11 +1448,25 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
   // configuration again (its loads differ from the plain product's)
   static const int kFusions[] = {0, 1, 2, 3, 8, 9, 40, 41};
   const int nfus = update_otf_ok(plan) ? 8 : update_prologue_ok(plan) ? 6 : 4;
-  // whole steps differ by a few percent between the best choices: time more of them
+  // whole steps differ by a few percent between the best choices: time more of them, then
+  // time the fastest few again in interleaved rounds and keep each one's best time, so that a
+  // single slow or fast measurement does not decide
   const int reps2 = reps * 3 > 10 ? reps * 3 : 10;
-  float best = 1e30f;
-  int best_fusion = 3, best_cfg_upd = -1;
-  bool best_rev = false;
+  struct Cand {
+    bool rev;
+    int fusion, cfg_upd;
+    float ms;
+  };
+  std::vector<Cand> cands;
+  auto time_step = [&](const Cand& c, float* ms) {
+    plan->fwd_rev = c.rev;
+    plan->fusion = c.fusion;
+    plan->cfg_upd = c.cfg_upd;
+    return time_ms(st, e0, e1, reps2, [&] {
+      const int rc = expeuler_body(plan, plan->uprev, 0.0, st);
+      return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
+    }, ms);
+  };
   for (int rev = 0; rev < (plan->d > 1 ? 2 : 1); ++rev)
     for (int fi = 0; fi < nfus; ++fi) {
       const int fusion = kFusions[fi];
@@ -1450,22 +1474,25 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
       for (int c = upd ? 0 : -1; c < (upd ? kNumCfg : 0); ++c) {
         // a configuration that hands its update prologue to another tile would time that tile again
         if (upd && cfg_update_tile(pr, c, (fusion & 32) && otf_fits(pr, c)) != c) continue;
-        plan->fwd_rev = (rev != 0);
-        plan->fusion = fusion;
-        plan->cfg_upd = c;
-        float ms;
-        FC_TRY(time_ms(st, e0, e1, reps2, [&] {
-          const int rc = expeuler_body(plan, plan->uprev, 0.0, st);
-          return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
-        }, &ms));
-        if (ms < best) {
-          best = ms;
-          best_fusion = fusion;
-          best_rev = (rev != 0);
-          best_cfg_upd = c;
-        }
+        Cand cd{rev != 0, fusion, c, 0.f};
+        FC_TRY(time_step(cd, &cd.ms));
+        cands.push_back(cd);
       }
     }
+  std::stable_sort(cands.begin(), cands.end(), [](const Cand& a, const Cand& b) { return a.ms < b.ms; });
+  const size_t top = cands.size() < 4 ? cands.size() : 4;
+  for (int round = 0; round < 3; ++round)
+    for (size_t i = 0; i < top; ++i) {
+      float ms;
+      FC_TRY(time_step(cands[i], &ms));
+      if (ms < cands[i].ms) cands[i].ms = ms;
+    }
+  size_t bi = 0;
+  for (size_t i = 1; i < top; ++i)
+    if (cands[i].ms < cands[bi].ms) bi = i;
+  const bool best_rev = cands[bi].rev;
+  int best_fusion = cands[bi].fusion;
+  const int best_cfg_upd = cands[bi].cfg_upd;
   (void)pr;
   plan->fwd_rev = best_rev;
   // with the update in the backward prologue the last forward product of an exponential-Euler
@@ -1474,6 +1501,37 @@ int autotune_impl(fcgle_plan* plan, int reps, hipStream_t st, hipEvent_t e0, hip
   if (best_fusion & 8) best_fusion |= 2;
   plan->fusion = best_fusion;
   plan->cfg_upd = best_cfg_upd;
+  // 3. products timed alone can rank two tiles within noise, or otherwise than inside a step:
+  //    compare each product's runner-up with its choice in whole steps (interleaved rounds,
+  //    best time of each) and keep the faster
+  for (int mu = 0; mu < plan->d; ++mu)
+    for (int dir = 0; dir < 2; ++dir) {
+      if (second_c[mu][dir] < 0) continue;
+      const int cc[2] = {plan->cfg[mu][dir], second_c[mu][dir]};
+      const bool ff[2] = {dir == 1 && plan->fwd2[mu], dir == 1 && second_f2[mu][dir] != 0};
+      float t[2] = {1e30f, 1e30f};
+      bool ok1 = true;  // the runner-up runs inside the step (else the choice stays)
+      for (int round = 0; round < 3 && ok1; ++round)
+        for (int k = 0; k < 2 && ok1; ++k) {
+          plan->cfg[mu][dir] = cc[k];
+          if (dir == 1) plan->fwd2[mu] = ff[k];
+          float ms;
+          auto body = [&] {
+            const int rc = expeuler_body(plan, plan->uprev, 0.0, st);
+            return rc == FCGLE_OK ? hipSuccess : hipErrorUnknown;
+          };
+          if (k == 0) {
+            FC_TRY(time_ms(st, e0, e1, reps2, body, &ms));
+          } else if (time_ms(st, e0, e1, reps2, body, &ms) != FCGLE_OK) {
+            ok1 = false;
+            break;
+          }
+          if (ms < t[k]) t[k] = ms;
+        }
+      const int k = (ok1 && t[1] < t[0]) ? 1 : 0;
+      plan->cfg[mu][dir] = cc[k];
+      if (dir == 1) plan->fwd2[mu] = ff[k];
+    }
   return FCGLE_OK;
 }
 
