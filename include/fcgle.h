@@ -246,7 +246,10 @@ int fcgle_plan_shape(const fcgle_plan* plan, int64_t* N, int* elem_bytes);
 /* Time every candidate tile configuration of each mode product on `stream`
  * (scratch inputs, max(3 reps, 10) launches each) and keep the fastest per axis and
  * direction; then time whole exponential-Euler steps (as many) for every placement of
- * the nonlinearity and of the update (fcgle_set_fusion) and keep the fastest.
+ * the nonlinearity and of the update (fcgle_set_fusion), time the fastest four again in
+ * three interleaved rounds and keep the best of them; finally compare each product's
+ * runner-up tile with its choice in whole steps (three interleaved rounds) and keep the
+ * faster.
  * For a batch plan: the same per grouped phase over all instances (`reps` launches).
  * Overwrites the plan's scratch buffers, so the cached eigenspace state and the LBDF2 history
  * are forgotten (as by fcgle_set_state): the next step of any scheme starts from u_dev alone.
